@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Benchmark of the PVFinder hot path on one MI355X, through the C ABI.
+
+A step is one pvf_execute over one batch: FC stage + histogram, the UNet, and
+peak finding, with the inputs already resident in HBM.  Default workload: the
+production slice of 1000 events (Poisson(180) tracks, Poisson(5.6) vertices,
+seed 0) in FP32.  Prints ONE JSON line on stdout; per-launch detail goes to
+stderr.
+
+Roofline: the dominant kernel is the kernel instance with the largest total
+time; its algorithmic FLOPs per launch (2 x MACs of the layers it runs, per
+event, times the events of one launch) over its average launch duration,
+measured with HIP events recorded by the library on the stream the kernels
+run on, against the MI355X dense FP32 matrix peak (157.3 TFLOP/s).
+
+CPU baseline: the FP64 oracle (plain C, threads over events) on a bounded
+sample of the same batch, on the host cores this process may use (at most 16).
+"""
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "events/sec on 1 MI355X (FP32 vs BF16/FP8 at stated tol); p99 µs/event"
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2516.6, "fp16": 2516.6, "fp8_e4m3": 5033.2}
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def layer_macs(spec, n_hidden=6, hidden=20, n_feat=9):
+    """Algorithmic multiply-adds per event of each launch, in launch order
+    (the track stage's figure is per track)."""
+    n, c0, L0 = spec.n_levels, spec.base_channels, spec.n_bins
+    out = {"track": n_feat * hidden + (n_hidden - 1) * hidden * hidden + hidden * spec.bins_per_interval}
+    for l in range(n):
+        L, C = L0 >> l, c0 << l
+        cin = 1 if l == 0 else (c0 << (l - 1))
+        out[f"enc{l}.c1"] = L * C * cin * 5
+        out[f"enc{l}.c2"] = L * C * C * 5
+    for l in range(n - 2, -1, -1):
+        L, C = L0 >> l, c0 << l
+        out[f"up{l}"] = L * C * (2 * C)
+        out[f"dec{l}.c1"] = L * C * 2 * C * 5
+        key = "dec0.c2+head" if l == 0 else f"dec{l}.c2"
+        out[key] = L * C * C * 5 + (L * C if l == 0 else 0)
+    out["peaks"] = 0
+    return out
+
+
+def cpu_threads():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(batch, w, target_s):
+    import oracle
+    threads = cpu_threads()
+    t0 = time.perf_counter()
+    oracle.run_batch(batch.subset([0]), w, threads=1)
+    t_one = time.perf_counter() - t0
+    n = int(max(threads, min(batch.n_events, round(target_s * threads / max(t_one, 1e-3)))))
+    n = min(n, batch.n_events)
+    sub = batch.subset(range(n))
+    t0 = time.perf_counter()
+    oracle.run_batch(sub, w, threads=threads)
+    dt = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": n / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} events of the same batch, FP64 C oracle, {threads} threads, "
+                      f"{dt:.1f} s wall on {cpu}"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--events", type=int, default=1000)
+    ap.add_argument("--mix", default="poisson", choices=["poisson", "lognormal"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--dtype", default="fp32", choices=["fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the path shards by event with no collective, so a "
+              "multi-GPU figure is the one-GPU value times N; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2602_19959_amd as pv
+    from synth import make_events, make_weights, weights_to_blob
+
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X", file=sys.stderr)
+        sys.exit(1)
+    E = args.events
+    batch = make_events(E, seed=args.seed, mix=args.mix)
+    w = make_weights(args.seed)
+    T = np.diff(batch.offsets)
+    spec = pv.default_spec(max_events=E, max_tracks_total=int(max(T.sum(), 1)), compute_dtype=args.dtype)
+    eng = pv.Engine(weights_to_blob(w), spec)
+    feat, off = pv.upload_events(batch)
+    out = eng.alloc_outputs(E, with_prob=False)
+    names = eng.launch_names()
+    kernels = eng.launch_kernels()
+    print(f"[bench] E={E} mix={args.mix} tracks={int(T.sum())} arena={eng.arena_bytes / 1e9:.2f} GB "
+          f"launches={len(names)}", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        eng.execute(feat, off, out)
+    eng.synchronize()
+    torch.cuda.synchronize()
+
+    eng.profile(True)
+    per_launch = [[] for _ in names]
+    step_ms = []
+    s = eng.stream
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(s)
+        eng.execute(feat, off, out)
+        ev1.record(s)
+        s.synchronize()
+        step_ms.append(ev0.elapsed_time(ev1))
+        for i, ms in enumerate(eng.profile_read()):
+            per_launch[i].append(ms)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    eng.profile(False)
+
+    host = out.to_host()
+    if np.any(host["status"] & (pv.EV_TOO_MANY_TRACKS | pv.EV_BAD_INPUT)):
+        print("[bench] unexpected bypassed events", file=sys.stderr)
+        sys.exit(1)
+
+    macs = layer_macs(spec)
+    valid_tracks = float(T.sum())
+    mean_ms = [statistics.mean(v) for v in per_launch]
+    flops_launch = [2.0 * (macs[n] * valid_tracks if n == "track" else macs[n] * E) for n in names]
+    print(f"[bench] {'launch':14s} {'kernel':36s} {'ms':>8s} {'TFLOP/s':>8s}", file=sys.stderr)
+    for n, k, ms, fl in zip(names, kernels, mean_ms, flops_launch):
+        print(f"[bench] {n:14s} {k:36s} {ms:8.3f} {fl / ms / 1e9:8.2f}", file=sys.stderr)
+
+    # dominant kernel instance: largest total time per step
+    by_kernel = {}
+    for n, k, ms, fl in zip(names, kernels, mean_ms, flops_launch):
+        d = by_kernel.setdefault(k, {"ms": 0.0, "flops": 0.0, "launches": 0, "layers": []})
+        d["ms"] += ms
+        d["flops"] += fl
+        d["launches"] += 1
+        d["layers"].append(n)
+    dom_name, dom = max(by_kernel.items(), key=lambda kv: kv[1]["ms"])
+    avg_dur_s = dom["ms"] / dom["launches"] / 1e3
+    flops_per_launch = dom["flops"] / dom["launches"]
+    achieved = flops_per_launch / avg_dur_s / 1e12
+    peak = PEAK_TFLOPS[args.dtype]
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE)).get(f"{dom_name}|E={E}|{args.dtype}")
+        if tr:
+            traffic = tr.get("bytes_per_launch")
+
+    stage = {"track": mean_ms[0], "unet": sum(mean_ms[1:-1]), "peaks": mean_ms[-1]}
+    ms_per_step = wall / args.steps * 1e3
+    us_ev = sorted(m * 1e3 / E for m in step_ms)
+    p50 = statistics.median(us_ev)
+    p99 = us_ev[min(len(us_ev) - 1, int(round(0.99 * (len(us_ev) - 1))))]
+    unet_flops = sum(f for n, f in zip(names, flops_launch) if n not in ("track", "peaks"))
+
+    result = {
+        "metric": METRIC,
+        "value": E * args.steps / wall,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: seeded events (Poisson(5.6) PVs, Poisson(180) tracks) and seeded He-init weights",
+        "config": {"workload": f"{E} events per batch, {args.mix} track counts (mean {T.mean():.1f}), "
+                               f"UNet 32/64/128/256 over 4000 bins, FP32, seed {args.seed}",
+                   "events_per_batch": E, "tracks_total": int(T.sum())},
+        "p50_us_per_event": p50,
+        "p99_us_per_event": p99,
+        "stages_ms": stage,
+        "unet_tflops": unet_flops / (stage["unet"] / 1e3) / 1e12,
+        "roofline": {"bound": "mfma", "kernel": dom_name, "layers": dom["layers"],
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": traffic, "flops_per_launch": flops_per_launch,
+                     "avg_launch_ms": avg_dur_s * 1e3},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] CPU baseline (FP64 oracle)...", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(batch, w, args.cpu_seconds)
+    eng.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,205 @@
+/*
+ * pvf.h -- C ABI of the MI355X (gfx950) PVFinder inference library.
+ *
+ * The library runs the hybrid PVFinder hot path of arXiv:2602.19959 on one
+ * GPU: per-track FC network and histogram (Section 2, FC stage), the UNet CNN
+ * over the histogram (Section 2, CNN stage), and heuristic peak finding
+ * (Section 2), taking per-event structure-of-arrays track features in and
+ * giving vertex z positions and probabilities out.
+ *
+ * Execution contract (Section 3, "Allen Integration and Translation Layer"):
+ *  - a frozen tensor specification at initialisation (batch capacity,
+ *    channel count, sequence length, data type), validated once;
+ *  - one caller-owned device arena bound at initialisation and reused by
+ *    every call; nothing is allocated on the device after pvf_init;
+ *  - every kernel runs on the one stream given at initialisation; the
+ *    library never uses the null stream and never synchronises in
+ *    pvf_execute;
+ *  - non-owning views: the caller owns every device buffer it passes;
+ *  - a status code per call and a status word per event, so an event that
+ *    fails validation is bypassed (no vertices) without disturbing the rest
+ *    of the batch.
+ *
+ * No function throws; every function is callable from C.  No HIP, PyTorch or
+ * C++ type appears in a signature: streams are passed as `void *` holding a
+ * hipStream_t, device buffers as plain pointers.
+ */
+#ifndef PVF_H
+#define PVF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PVF_ABI_VERSION 1u
+#define PVF_N_FEATURES 9
+
+/* Call-level status (Section 3: the Status enum).  Whatever the host can
+ * check before enqueueing work yields one of these, and then nothing is
+ * enqueued. */
+typedef enum {
+    PVF_OK = 0,
+    PVF_ERR_INVALID_ARGUMENT = 1,  /* null pointer, negative count, bad enum   */
+    PVF_ERR_SHAPE = 2,             /* spec geometry the kernels cannot run    */
+    PVF_ERR_CAPACITY = 3,          /* batch larger than the frozen spec       */
+    PVF_ERR_ARENA_TOO_SMALL = 4,   /* arena smaller than pvf_arena_bytes      */
+    PVF_ERR_WEIGHTS = 5,           /* blob malformed or shape != spec          */
+    PVF_ERR_UNSUPPORTED_DTYPE = 6, /* compute dtype not built                 */
+    PVF_ERR_DEVICE = 7,            /* a HIP runtime call failed               */
+    PVF_ERR_ALIGNMENT = 8          /* a buffer is not aligned as documented   */
+} pvf_status;
+
+/* Per-event status bits written to pvf_vertices.d_event_status.  Bypass
+ * bits (TOO_MANY_TRACKS, BAD_INPUT) give that event 0 vertices; the other
+ * events' results are unchanged by a bypassed event. */
+enum {
+    PVF_EV_OK = 0,
+    PVF_EV_TOO_MANY_TRACKS = 1,  /* bypass: more tracks than max_tracks_per_event */
+    PVF_EV_BAD_INPUT = 2,        /* bypass: offsets decreasing or out of range    */
+    PVF_EV_PEAKS_TRUNCATED = 4,  /* more vertices than max_peaks_per_event        */
+    PVF_EV_TRACKS_DROPPED = 8    /* some tracks outside the z window or with a
+                                    non-finite feature were left out          */
+};
+
+/* Arithmetic type of the UNet convolutions.  FP32 is the deployed
+ * precision of the paper (Section 2, Fig. 1). */
+typedef enum { PVF_FP32 = 0, PVF_BF16 = 1, PVF_FP16 = 2, PVF_FP8_E4M3 = 3 } pvf_dtype;
+
+/* The frozen tensor specification ("TensorSpec", Section 3).  Fill it with
+ * pvf_spec_default and change what differs. */
+typedef struct pvf_spec {
+    uint32_t abi_version;          /* PVF_ABI_VERSION                           */
+    int32_t  max_events;           /* batch capacity (events per call)          */
+    int32_t  max_tracks_per_event; /* larger events are bypassed                */
+    int32_t  max_peaks_per_event;  /* vertex slots per event (<= n_bins / 2)    */
+    int64_t  max_tracks_total;     /* tracks per call, <= INT32_MAX             */
+    int32_t  compute_dtype;        /* pvf_dtype                                 */
+    int32_t  n_levels;             /* UNet levels (4)                           */
+    int32_t  base_channels;        /* channels of level 0 (32); level l has
+                                      base_channels << l                        */
+    int32_t  n_bins;               /* histogram bins per event (4000)           */
+    int32_t  bins_per_interval;    /* bins per spatial interval (100)           */
+    int32_t  half_window;          /* peak integration half-width in bins (5)   */
+    double   z_min_mm;             /* lower edge of the histogram (-100 mm)     */
+    double   bin_width_mm;         /* bin width (0.1 mm)                        */
+    double   peak_min;             /* a vertex needs p > peak_min (0.01)        */
+    double   integral_min;         /* and a window sum > integral_min (0.2)     */
+} pvf_spec;
+
+/* Input view: one batch of events in structure-of-arrays form (Section 3:
+ * the trigger's SoA buffers, reinterpreted without copies).
+ * d_event_offsets: device int32 [n_events + 1]; event e owns tracks
+ *   offsets[e] .. offsets[e+1]-1; offsets[0] is expected to be 0.
+ * d_feat[k]: device float32 plane k of n_tracks_total values, feature order
+ *   z, x, y, c1, c2, c3, s1, s2, s3 (mm for positions).  4-byte aligned.
+ * Counts are host values. */
+typedef struct pvf_tracks {
+    int32_t        n_events;
+    int64_t        n_tracks_total;
+    const int32_t *d_event_offsets;
+    const float   *d_feat[PVF_N_FEATURES];
+} pvf_tracks;
+
+/* Output view (Section 3, Extract phase: results left on the device for
+ * downstream consumers).  Every array is device memory owned by the caller,
+ * laid out per event with stride max_peaks_per_event for the vertex arrays:
+ *   d_n_vertices    int32  [n_events]
+ *   d_z             double [n_events][max_peaks]   vertex z (mm), ascending
+ *   d_peak_prob     float  [n_events][max_peaks]   p at the vertex bin
+ *   d_integral      double [n_events][max_peaks]   sum of p over the window
+ *   d_event_status  int32  [n_events]               PVF_EV_* bits
+ *   d_prob_hist     float  [n_events][n_bins] or NULL: per-bin probability
+ *   d_bin           int32  [n_events][max_peaks] or NULL: bin of each vertex
+ * Slots past d_n_vertices[e] are left unwritten. */
+typedef struct pvf_vertices {
+    int32_t *d_n_vertices;
+    double  *d_z;
+    float   *d_peak_prob;
+    double  *d_integral;
+    int32_t *d_event_status;
+    float   *d_prob_hist;
+    int32_t *d_bin;
+} pvf_vertices;
+
+typedef struct pvf_engine pvf_engine;
+
+/* Defaults: the 4000-bin, 4-level, 32..256-channel network in FP32, 1000
+ * events per call, 1500 tracks per event, 2000 vertex slots per event,
+ * 0.1 mm bins from -100 mm, thresholds 0.01 and 0.2 over +-5 bins. */
+void pvf_spec_default(pvf_spec *spec);
+
+/* Bytes of device arena the engine needs for `spec` (weights, activations
+ * and per-event scratch).  Host-only; touches no device. */
+pvf_status pvf_arena_bytes(const pvf_spec *spec, size_t *out_bytes);
+
+/* Create an engine (Section 3: init takes the stream and the workspace).
+ * weights_blob: host bytes in the "PVFW" layout (network shape, fixed
+ *   constants, then every tensor in forward order); copied, not kept.
+ * d_arena: device memory of at least pvf_arena_bytes, 256-byte aligned,
+ *   owned by the caller, used exclusively by this engine until
+ *   pvf_destroy.
+ * stream: a hipStream_t cast to void*; NULL is rejected (no null stream).
+ * The only call that synchronises (once, on `stream`, after uploading the
+ * packed weights and clearing the arena).  On error *out is NULL. */
+pvf_status pvf_init(const pvf_spec *spec, const void *weights_blob, size_t blob_bytes,
+                    void *d_arena, size_t arena_bytes, void *stream, pvf_engine **out);
+
+/* Enqueue the whole path for one batch on the engine's stream and return
+ * at once (Section 3, Execute phase).  No allocation, no synchronisation.
+ * n_events == 0 enqueues nothing.  Results are visible once the stream
+ * reaches the enqueued work.  Host-detectable errors return before
+ * anything is enqueued. */
+pvf_status pvf_execute(pvf_engine *eng, const pvf_tracks *tracks, const pvf_vertices *out);
+
+/* Same as pvf_execute on another stream (a hipStream_t as void*).  Calls
+ * that overlap in time must use different engines (each engine has one
+ * arena). */
+pvf_status pvf_execute_on(pvf_engine *eng, const pvf_tracks *tracks, const pvf_vertices *out,
+                          void *stream);
+
+/* Release the engine's host state.  The arena is the caller's to free. */
+pvf_status pvf_destroy(pvf_engine *eng);
+
+/* Static English text of a status code. */
+const char *pvf_status_string(pvf_status s);
+
+/* ---- instrumentation (not on the hot path) ---------------------------- */
+
+/* Number of kernel launches one pvf_execute enqueues for this engine. */
+int pvf_launch_count(const pvf_engine *eng);
+
+/* Name of launch i (e.g. "track", "enc0.c2", "up1", "peaks"); NULL if out
+ * of range.  Static storage. */
+const char *pvf_launch_name(const pvf_engine *eng, int i);
+
+/* Kernel that launch i runs, as it appears in a profiler's kernel name
+ * (e.g. "conv_mfma_f32<4, 2, 4, 4, 5, 0>", "track_stage"); NULL if out of
+ * range.  Static storage for the engine's life. */
+const char *pvf_launch_kernel(const pvf_engine *eng, int i);
+
+/* on != 0: create one HIP event per launch boundary now, and from then on
+ * record them around every launch that pvf_execute enqueues.  on == 0:
+ * stop recording and destroy them.  Recording adds no synchronisation. */
+pvf_status pvf_profile_enable(pvf_engine *eng, int on);
+
+/* After the caller has synchronised the stream: elapsed milliseconds of
+ * each launch of the most recent profiled pvf_execute, into ms[0..n). */
+pvf_status pvf_profile_read(pvf_engine *eng, float *ms, int n);
+
+/* Debug view of one internal activation of the most recent call, for
+ * per-layer parity checks: copies tensor `name` ("hist", "enc0.c1", ...,
+ * "dec0.c1", "prob"), for the first n_events events, into d_dst as float32
+ * [n_events][C][L] (channels first), on the engine's stream.  Returns
+ * PVF_ERR_INVALID_ARGUMENT for an unknown name; *out_count receives the
+ * number of floats (C * L * n_events), also when d_dst is NULL. */
+pvf_status pvf_debug_tensor(pvf_engine *eng, const char *name, int32_t n_events, float *d_dst,
+                            int64_t *out_count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PVF_H */

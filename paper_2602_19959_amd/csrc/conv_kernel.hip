@@ -1,0 +1,258 @@
+// UNet convolutions as implicit GEMM on the CDNA4 matrix cores (FP32).
+//
+// The UNet of Section 2 (arXiv:2602.19959) is a stack of 1D convolutions.
+// Each is a GEMM  D[m][n] = sum_k A[m][k] B[k][n]  with
+//   m = (event, position)  rows of the channels-last activation,
+//   n = output channel     (transposed conv: (tap, output channel)),
+//   k = (tap, input channel).
+// A is never materialised: a block stages the (BM + 4) x 16 halo tile of input
+// rows once per 16-channel chunk in LDS and all five taps read it with a row
+// shift.  The packed weights are [N][taps][Cin], so one 16-byte LDS read gives
+// a lane four consecutive k of its column.
+//
+// MFMA: v_mfma_f32_16x16x4_f32.  For one 16-wide k chunk, lane group g = lane/16
+// supplies k = 4g+s to the s-th of four MFMAs; A and B use the same order, so
+// the four MFMAs add up the whole chunk.  The k order of every output is fixed
+// by the kernel alone (chunk, tap, s), never by the tile's position, so results
+// are bitwise independent of the batch size and of where an event sits in it.
+//
+// Epilogues (fused, nothing re-read from HBM):
+//   EPI_STORE  bias + LeakyReLU
+//   EPI_POOL   bias + LeakyReLU, plus the width-2 max-pool of row pairs into
+//              the next level's input
+//   EPI_CONVT  stride-2 2-tap transposed conv: row t of the coarse level goes
+//              to rows 2t and 2t+1 of the fine level, bias, no activation
+//   EPI_HEAD   bias + LeakyReLU, then the 1x1 head over all channels and the
+//              sigmoid, writing the per-bin probability
+// Guard rows (the two zero rows before and after each event) are never written.
+#include "pvf_internal.h"
+
+namespace pvf {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int KC = 16;         // input channels per LDS stage
+constexpr int KPAD = KC + 4;   // LDS pitch in floats (80 B): 8 consecutive rows'
+                               // 16-byte reads fall on distinct bank groups
+
+__device__ __forceinline__ float lrelu(float x, float s) { return x >= 0.f ? x : s * x; }
+
+template <int WM, int WN, int TMW, int TNW, int TAPS, int EPI>
+__global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32(ConvArgs a)
+{
+    constexpr int NT = WM * WN * 64;
+    constexpr int BM = WM * TMW * 16;
+    constexpr int BN = WN * TNW * 16;
+    constexpr int RAD = (TAPS - 1) / 2;
+    constexpr int XROWS = BM + TAPS - 1;
+
+    __shared__ float xs[XROWS * KPAD];
+    __shared__ float ws[BN * TAPS * KPAD];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave % WM;
+    const int wn = wave / WM;
+    const int li = lane & 15;
+    const int lg = lane >> 4;
+
+    const int64_t m0 = (int64_t)blockIdx.x * BM;
+    const int n0 = blockIdx.y * BN;
+    const int kw = TAPS * a.cin;
+
+    f32x4 acc[TMW][TNW];
+#pragma unroll
+    for (int i = 0; i < TMW; ++i)
+#pragma unroll
+        for (int j = 0; j < TNW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int c0 = 0; c0 < a.cin; c0 += KC) {
+        for (int idx = tid; idx < XROWS * (KC / 4); idx += NT) {
+            const int row = idx / (KC / 4), q = idx % (KC / 4);
+            const int64_t g = m0 - RAD + row;
+            f32x4 v = {0.f, 0.f, 0.f, 0.f};
+            if (g >= 0 && g < a.m_rows)
+                v = *reinterpret_cast<const f32x4*>(a.in + g * a.ld_in + c0 + 4 * q);
+            *reinterpret_cast<f32x4*>(xs + row * KPAD + 4 * q) = v;
+        }
+        for (int idx = tid; idx < BN * TAPS * (KC / 4); idx += NT) {
+            const int q = idx % (KC / 4);
+            const int rest = idx / (KC / 4);
+            const int tap = rest % TAPS, nn = rest / TAPS;
+            f32x4 v = {0.f, 0.f, 0.f, 0.f};
+            if (n0 + nn < a.n)
+                v = *reinterpret_cast<const f32x4*>(a.w + (int64_t)(n0 + nn) * kw + tap * a.cin + c0 + 4 * q);
+            *reinterpret_cast<f32x4*>(ws + (nn * TAPS + tap) * KPAD + 4 * q) = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tap = 0; tap < TAPS; ++tap) {
+            f32x4 av[TMW], bv[TNW];
+#pragma unroll
+            for (int i = 0; i < TMW; ++i)
+                av[i] = *reinterpret_cast<const f32x4*>(xs + (wm * TMW * 16 + i * 16 + li + tap) * KPAD + 4 * lg);
+#pragma unroll
+            for (int j = 0; j < TNW; ++j)
+                bv[j] = *reinterpret_cast<const f32x4*>(ws + ((wn * TNW * 16 + j * 16 + li) * TAPS + tap) * KPAD + 4 * lg);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int i = 0; i < TMW; ++i)
+#pragma unroll
+                    for (int j = 0; j < TNW; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][s], bv[j][s], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+
+    // Output D layout of the 16x16 MFMA: lane holds rows 4*lg + v (v = 0..3)
+    // of column li.
+    const int64_t rbase = m0 + wm * TMW * 16;
+    const int cbase = n0 + wn * TNW * 16;
+
+    if constexpr (EPI == EPI_HEAD) {
+        // the block holds every channel of its rows (BN == n, one wave in N)
+#pragma unroll
+        for (int i = 0; i < TMW; ++i) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                float s = 0.f;
+#pragma unroll
+                for (int j = 0; j < TNW; ++j) {
+                    const int col = cbase + j * 16 + li;
+                    s += lrelu(acc[i][j][v] + a.bias[col], a.slope) * a.head_w[col];
+                }
+                s += __shfl_xor(s, 8);
+                s += __shfl_xor(s, 4);
+                s += __shfl_xor(s, 2);
+                s += __shfl_xor(s, 1);
+                const int64_t r = rbase + i * 16 + 4 * lg + v;
+                if (li == 0 && r < a.m_rows) {
+                    const int64_t e = r / a.r_in;
+                    const int loc = (int)(r - e * a.r_in);
+                    if (loc >= kGuard && loc < a.r_in - kGuard) {
+                        const float logit = s + a.head_b;
+                        a.prob[e * a.l_out + (loc - kGuard)] = 1.f / (1.f + expf(-logit));
+                    }
+                }
+            }
+        }
+        return;
+    }
+
+#pragma unroll
+    for (int j = 0; j < TNW; ++j) {
+        const int col = cbase + j * 16 + li;
+        if (col >= a.n) continue;
+        if constexpr (EPI == EPI_CONVT) {
+            const int tj = col / a.cout;           // which of the two output rows
+            const int o = col - tj * a.cout;
+            const float b = a.bias[o];
+#pragma unroll
+            for (int i = 0; i < TMW; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t r = rbase + i * 16 + 4 * lg + v;
+                    if (r >= a.m_rows) continue;
+                    const int64_t e = r / a.r_in;
+                    const int loc = (int)(r - e * a.r_in);
+                    if (loc < kGuard || loc >= a.r_in - kGuard) continue;
+                    const int64_t ro = e * a.r_out + kGuard + 2 * (loc - kGuard) + tj;
+                    a.out[ro * a.ld_out + o] = acc[i][j][v] + b;
+                }
+        } else {
+            const float b = a.bias[col];
+#pragma unroll
+            for (int i = 0; i < TMW; ++i) {
+                float y[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) y[v] = lrelu(acc[i][j][v] + b, a.slope);
+                const int64_t r0 = rbase + i * 16 + 4 * lg;   // multiple of 4
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t r = r0 + v;
+                    if (r >= a.m_rows) continue;
+                    const int64_t e = r / a.r_in;
+                    const int loc = (int)(r - e * a.r_in);
+                    if (loc < kGuard || loc >= a.r_in - kGuard) continue;
+                    a.out[r * a.ld_out + col] = y[v];
+                }
+                if constexpr (EPI == EPI_POOL) {
+                    // rows per event and the guard are even, so an even row is
+                    // the first of a pooling pair
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) {
+                        const int64_t r = r0 + 2 * p;
+                        if (r >= a.m_rows) continue;
+                        const int64_t e = r / a.r_in;
+                        const int loc = (int)(r - e * a.r_in);
+                        if (loc < kGuard || loc >= a.r_in - kGuard) continue;
+                        const int64_t rp = e * a.r_pool + kGuard + (loc - kGuard) / 2;
+                        a.pool_out[rp * a.ld_pool + col] = fmaxf(y[2 * p], y[2 * p + 1]);
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int WM, int WN, int TMW, int TNW, int TAPS, int EPI>
+hipError_t run(const ConvArgs& a, hipStream_t s)
+{
+    constexpr int BM = WM * TMW * 16;
+    constexpr int BN = WN * TNW * 16;
+    dim3 grid((unsigned)((a.m_rows + BM - 1) / BM), (unsigned)((a.n + BN - 1) / BN));
+    hipLaunchKernelGGL((conv_mfma_f32<WM, WN, TMW, TNW, TAPS, EPI>), grid, dim3(WM * WN * 64), 0, s, a);
+    return hipGetLastError();
+}
+
+// Tile shape per GEMM width: (waves in M, waves in N, 16x16 tiles per wave in
+// M, in N).  Every block covers 256 rows; one wave holds a 64 x (16*TNW) tile.
+struct Shape { int wm, wn, tmw, tnw; };
+
+Shape shape_for(int n, Epi epi)
+{
+    if (epi == EPI_HEAD || n <= 32) return {4, 1, 4, 2};
+    if (n <= 64) return {4, 1, 4, 4};
+    return {4, 2, 4, 4};
+}
+
+template <int TAPS, int EPI>
+hipError_t by_width(const ConvArgs& a, hipStream_t s)
+{
+    const Shape sh = shape_for(a.n, (Epi)EPI);
+    if (sh.wn == 1 && sh.tnw == 2) return run<4, 1, 4, 2, TAPS, EPI>(a, s);
+    if (sh.wn == 1 && sh.tnw == 4) return run<4, 1, 4, 4, TAPS, EPI>(a, s);
+    return run<4, 2, 4, 4, TAPS, EPI>(a, s);
+}
+
+}  // namespace
+
+std::string conv_kernel_name(int n, int taps, Epi epi)
+{
+    const Shape sh = shape_for(n, epi);
+    return "conv_mfma_f32<" + std::to_string(sh.wm) + ", " + std::to_string(sh.wn) + ", " +
+           std::to_string(sh.tmw) + ", " + std::to_string(sh.tnw) + ", " + std::to_string(taps) + ", " +
+           std::to_string((int)epi) + ">";
+}
+
+hipError_t launch_conv(const ConvArgs& a, int taps, Epi epi, hipStream_t s)
+{
+    if (a.cin % KC != 0 || a.m_rows <= 0) return hipErrorInvalidValue;
+    if (taps == 5) {
+        switch (epi) {
+        case EPI_STORE: return by_width<5, EPI_STORE>(a, s);
+        case EPI_POOL: return by_width<5, EPI_POOL>(a, s);
+        case EPI_HEAD:
+            if (a.n != 32) return hipErrorInvalidValue;
+            return by_width<5, EPI_HEAD>(a, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (taps == 1 && epi == EPI_CONVT) return by_width<1, EPI_CONVT>(a, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace pvf

@@ -1,0 +1,701 @@
+// Host side of the C ABI declared in include/pvf.h: spec validation, the
+// arena plan, weight unpacking and packing, and the launch sequence.
+//
+// Section 3 of arXiv:2602.19959 shapes this file: the specification is frozen
+// and checked once (Prepare), all memory is a caller-provided arena bound at
+// init, every launch goes to the one stream given at init (Execute), and the
+// outputs stay on the device where the consumers read them (Extract).  Only
+// pvf_init synchronises; pvf_execute enqueues and returns.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "pvf_internal.h"
+
+namespace pvf {
+namespace {
+
+constexpr int kMaxBins = 16384;
+constexpr int kMaxBinsPerInterval = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// ------------------------------------------------------------------ spec
+
+pvf_status validate_spec(const pvf_spec* s)
+{
+    if (s->abi_version != PVF_ABI_VERSION) return PVF_ERR_INVALID_ARGUMENT;
+    if (s->max_events < 1 || s->max_tracks_per_event < 0 || s->max_peaks_per_event < 1 ||
+        s->max_tracks_total < 0 || s->max_tracks_total > INT32_MAX)
+        return PVF_ERR_INVALID_ARGUMENT;
+    if (s->compute_dtype < PVF_FP32 || s->compute_dtype > PVF_FP8_E4M3) return PVF_ERR_INVALID_ARGUMENT;
+    if (s->compute_dtype != PVF_FP32) return PVF_ERR_UNSUPPORTED_DTYPE;
+    if (!(std::isfinite(s->z_min_mm) && std::isfinite(s->bin_width_mm) && s->bin_width_mm > 0 &&
+          std::isfinite(s->peak_min) && std::isfinite(s->integral_min)))
+        return PVF_ERR_INVALID_ARGUMENT;
+    if (s->half_window < 0) return PVF_ERR_INVALID_ARGUMENT;
+    if (s->n_levels < 2 || s->n_levels > kMaxLevels) return PVF_ERR_SHAPE;
+    // the head epilogue holds all level-0 channels in one 32-wide tile
+    if (s->base_channels != 32) return PVF_ERR_SHAPE;
+    if (s->n_bins < 4 || s->n_bins > kMaxBins) return PVF_ERR_SHAPE;
+    if (s->bins_per_interval < 1 || s->bins_per_interval > kMaxBinsPerInterval ||
+        s->n_bins % s->bins_per_interval != 0)
+        return PVF_ERR_SHAPE;
+    if (s->n_bins % (1 << (s->n_levels - 1)) != 0) return PVF_ERR_SHAPE;
+    if (s->max_peaks_per_event > s->n_bins) return PVF_ERR_SHAPE;
+    return PVF_OK;
+}
+
+void make_plan(const pvf_spec* s, size_t weight_floats, Plan* p)
+{
+    p->n_levels = s->n_levels;
+    p->c0 = s->base_channels;
+    p->max_events = s->max_events;
+    for (int l = 0; l < s->n_levels; ++l) {
+        p->lv[l].L = s->n_bins >> l;
+        p->lv[l].R = p->lv[l].L + 2 * kGuard;
+        p->lv[l].C = s->base_channels << l;
+    }
+    const size_t E = (size_t)s->max_events;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    p->weights_bytes = weight_floats * sizeof(float);
+    p->weights = take(p->weights_bytes);
+    p->zero_begin = off;
+    p->x0 = take(E * p->lv[0].R * sizeof(float));
+    const int n = s->n_levels;
+    for (int l = 0; l < n; ++l) {
+        const size_t rows = E * p->lv[l].R;
+        p->a[l] = take(rows * p->lv[l].C * sizeof(float));
+        if (l < n - 1) p->cat[l] = take(rows * 2 * p->lv[l].C * sizeof(float));
+        if (l >= 1) p->pool[l] = take(rows * p->lv[l - 1].C * sizeof(float));
+        if (l >= 1) p->d[l] = take(rows * p->lv[l].C * sizeof(float));
+    }
+    p->zero_end = off;
+    p->prob = take(E * p->lv[0].L * sizeof(float));
+    p->flags = take(E * sizeof(int32_t));
+    p->total = off;
+}
+
+// ------------------------------------------------------------------ weights
+
+struct NetShape {
+    int n_feat, hidden, n_hidden, n_out, n_levels, c0, ksize;
+};
+
+// Expected element counts of the blob's tensors, in blob (forward) order.
+std::vector<int64_t> blob_tensor_sizes(const NetShape& n)
+{
+    std::vector<int64_t> v;
+    int in = n.n_feat;
+    for (int l = 0; l < n.n_hidden; ++l) {
+        v.push_back((int64_t)n.hidden * in);
+        v.push_back(n.hidden);
+        in = n.hidden;
+    }
+    v.push_back((int64_t)n.n_out * n.hidden);
+    v.push_back(n.n_out);
+    int cin = 1;
+    for (int l = 0; l < n.n_levels; ++l) {
+        const int c = n.c0 << l;
+        v.push_back((int64_t)c * cin * n.ksize); v.push_back(c);
+        v.push_back((int64_t)c * c * n.ksize);   v.push_back(c);
+        cin = c;
+    }
+    for (int l = n.n_levels - 2; l >= 0; --l) {
+        const int c = n.c0 << l, cu = n.c0 << (l + 1);
+        v.push_back((int64_t)cu * c * 2);        v.push_back(c);
+        v.push_back((int64_t)c * 2 * c * n.ksize); v.push_back(c);
+        v.push_back((int64_t)c * c * n.ksize);   v.push_back(c);
+    }
+    v.push_back(n.c0);
+    v.push_back(1);
+    return v;
+}
+
+struct Blob {
+    NetShape shape;
+    float leaky, s_in;
+    float shift[kFeat], scale[kFeat];
+    std::vector<const float*> t;      // tensor pointers into `store`
+    std::vector<std::vector<float>> store;
+};
+
+template <class T>
+bool rd(const uint8_t*& p, const uint8_t* end, T* out)
+{
+    if ((size_t)(end - p) < sizeof(T)) return false;
+    std::memcpy(out, p, sizeof(T));
+    p += sizeof(T);
+    return true;
+}
+
+pvf_status parse_blob(const void* data, size_t bytes, const pvf_spec* s, Blob* b)
+{
+    const uint8_t* p = static_cast<const uint8_t*>(data);
+    const uint8_t* end = p + bytes;
+    uint32_t version;
+    if (bytes < 4 || std::memcmp(p, "PVFW", 4) != 0) return PVF_ERR_WEIGHTS;
+    p += 4;
+    if (!rd(p, end, &version) || version != 1) return PVF_ERR_WEIGHTS;
+    int32_t sh[7];
+    for (int i = 0; i < 7; ++i)
+        if (!rd(p, end, &sh[i])) return PVF_ERR_WEIGHTS;
+    b->shape = NetShape{sh[0], sh[1], sh[2], sh[3], sh[4], sh[5], sh[6]};
+    const NetShape& n = b->shape;
+    if (n.n_feat != kFeat || n.hidden != kHidden || n.n_hidden < 1 || n.n_hidden > kMaxHiddenLayers ||
+        n.ksize != kTaps)
+        return PVF_ERR_WEIGHTS;
+    if (n.n_out != s->bins_per_interval || n.n_levels != s->n_levels || n.c0 != s->base_channels)
+        return PVF_ERR_WEIGHTS;
+    if (!rd(p, end, &b->leaky) || !rd(p, end, &b->s_in)) return PVF_ERR_WEIGHTS;
+    for (int k = 0; k < kFeat; ++k)
+        if (!rd(p, end, &b->shift[k])) return PVF_ERR_WEIGHTS;
+    for (int k = 0; k < kFeat; ++k)
+        if (!rd(p, end, &b->scale[k])) return PVF_ERR_WEIGHTS;
+    int32_t nt;
+    if (!rd(p, end, &nt)) return PVF_ERR_WEIGHTS;
+    const std::vector<int64_t> want = blob_tensor_sizes(n);
+    if (nt != (int32_t)want.size()) return PVF_ERR_WEIGHTS;
+    for (int i = 0; i < nt; ++i) {
+        int32_t c;
+        if (!rd(p, end, &c) || c != want[i]) return PVF_ERR_WEIGHTS;
+    }
+    b->store.resize(nt);
+    for (int i = 0; i < nt; ++i) {
+        const size_t nb = (size_t)want[i] * sizeof(float);
+        if ((size_t)(end - p) < nb) return PVF_ERR_WEIGHTS;
+        b->store[i].resize(want[i]);
+        std::memcpy(b->store[i].data(), p, nb);
+        p += nb;
+        for (float v : b->store[i])
+            if (!std::isfinite(v)) return PVF_ERR_WEIGHTS;
+    }
+    if (p != end) return PVF_ERR_WEIGHTS;
+    b->t.resize(nt);
+    for (int i = 0; i < nt; ++i) b->t[i] = b->store[i].data();
+    return PVF_OK;
+}
+
+size_t weight_layout(const NetShape& n, WeightLayout* w)
+{
+    size_t off = 0;
+    auto take = [&](size_t floats) { size_t o = off; off += (floats + 63) / 64 * 64; return o; };
+    size_t mlp = (size_t)n.hidden * n.n_feat + n.hidden +
+                 (size_t)(n.n_hidden - 1) * (n.hidden * n.hidden + n.hidden) + (size_t)n.n_out * n.hidden + n.n_out;
+    w->mlp_count = mlp;
+    w->mlp = take(mlp);
+    w->first_w = take((size_t)n.c0 * n.ksize);
+    w->first_b = take(n.c0);
+    for (int l = 0; l < n.n_levels; ++l) {
+        const int c = n.c0 << l, cin = l == 0 ? 1 : (n.c0 << (l - 1));
+        if (l > 0) {
+            w->enc[l][0] = {take((size_t)c * n.ksize * cin), take(c), cin, c, n.ksize};
+        }
+        w->enc[l][1] = {take((size_t)c * n.ksize * c), take(c), c, c, n.ksize};
+    }
+    for (int l = n.n_levels - 2; l >= 0; --l) {
+        const int c = n.c0 << l, cu = n.c0 << (l + 1);
+        w->up[l] = {take((size_t)2 * c * cu), take(c), cu, c, 1};
+        w->dec[l][0] = {take((size_t)c * n.ksize * 2 * c), take(c), 2 * c, c, n.ksize};
+        w->dec[l][1] = {take((size_t)c * n.ksize * c), take(c), c, c, n.ksize};
+    }
+    w->head_w = take(n.c0);
+    w->head_b = take(1);
+    w->total = off;
+    return off;
+}
+
+// [Cout][Cin][k] -> [Cout][k][Cin]
+void pack_conv(const float* src, int cout, int cin, int k, float* dst)
+{
+    for (int o = 0; o < cout; ++o)
+        for (int j = 0; j < k; ++j)
+            for (int c = 0; c < cin; ++c)
+                dst[((size_t)o * k + j) * cin + c] = src[((size_t)o * cin + c) * k + j];
+}
+
+// transposed conv [Cin][Cout][2] -> GEMM rows n = j*Cout + o over k = Cin
+void pack_convT(const float* src, int cin, int cout, float* dst)
+{
+    for (int j = 0; j < 2; ++j)
+        for (int o = 0; o < cout; ++o)
+            for (int c = 0; c < cin; ++c)
+                dst[((size_t)j * cout + o) * cin + c] = src[((size_t)c * cout + o) * 2 + j];
+}
+
+void pack_weights(const Blob& b, const WeightLayout& w, std::vector<float>& out)
+{
+    const NetShape& n = b.shape;
+    out.assign(w.total, 0.f);
+    size_t ti = 0;
+    // MLP: blob order, contiguous
+    size_t pos = w.mlp;
+    for (int l = 0; l <= n.n_hidden; ++l) {
+        for (int q = 0; q < 2; ++q) {
+            const size_t cnt = b.store[ti].size();
+            std::memcpy(&out[pos], b.t[ti], cnt * sizeof(float));
+            pos += cnt;
+            ++ti;
+        }
+    }
+    for (int l = 0; l < n.n_levels; ++l) {
+        const int c = n.c0 << l, cin = l == 0 ? 1 : (n.c0 << (l - 1));
+        if (l == 0) {
+            std::memcpy(&out[w.first_w], b.t[ti], sizeof(float) * c * n.ksize);
+            std::memcpy(&out[w.first_b], b.t[ti + 1], sizeof(float) * c);
+        } else {
+            pack_conv(b.t[ti], c, cin, n.ksize, &out[w.enc[l][0].w]);
+            std::memcpy(&out[w.enc[l][0].b], b.t[ti + 1], sizeof(float) * c);
+        }
+        ti += 2;
+        pack_conv(b.t[ti], c, c, n.ksize, &out[w.enc[l][1].w]);
+        std::memcpy(&out[w.enc[l][1].b], b.t[ti + 1], sizeof(float) * c);
+        ti += 2;
+    }
+    for (int l = n.n_levels - 2; l >= 0; --l) {
+        const int c = n.c0 << l, cu = n.c0 << (l + 1);
+        pack_convT(b.t[ti], cu, c, &out[w.up[l].w]);
+        std::memcpy(&out[w.up[l].b], b.t[ti + 1], sizeof(float) * c);
+        ti += 2;
+        pack_conv(b.t[ti], c, 2 * c, n.ksize, &out[w.dec[l][0].w]);
+        std::memcpy(&out[w.dec[l][0].b], b.t[ti + 1], sizeof(float) * c);
+        ti += 2;
+        pack_conv(b.t[ti], c, c, n.ksize, &out[w.dec[l][1].w]);
+        std::memcpy(&out[w.dec[l][1].b], b.t[ti + 1], sizeof(float) * c);
+        ti += 2;
+    }
+    std::memcpy(&out[w.head_w], b.t[ti], sizeof(float) * n.c0);
+    std::memcpy(&out[w.head_b], b.t[ti + 1], sizeof(float));
+}
+
+size_t weight_floats_for(const pvf_spec* s)
+{
+    NetShape n{kFeat, kHidden, 6, s->bins_per_interval, s->n_levels, s->base_channels, kTaps};
+    // the MLP depth is read from the blob; reserve for the deepest supported
+    n.n_hidden = kMaxHiddenLayers;
+    WeightLayout w;
+    return weight_layout(n, &w);
+}
+
+}  // namespace
+}  // namespace pvf
+
+using namespace pvf;
+
+struct pvf_engine {
+    pvf_spec spec;
+    Plan plan;
+    WeightLayout wl;
+    int n_hidden = 0;
+    float leaky = 0.f, s_in = 0.f, head_b = 0.f;
+    float shift[kFeat] = {}, scale[kFeat] = {};
+    char* arena = nullptr;
+    hipStream_t stream = nullptr;
+    std::vector<std::string> names;      // one per launch of pvf_execute
+    std::vector<std::string> kernels;    // kernel instance of each launch
+    std::vector<hipEvent_t> events;      // launch boundaries when profiling
+    bool profiling = false;
+};
+
+namespace {
+
+template <class T>
+T* at(pvf_engine* e, size_t off) { return reinterpret_cast<T*>(e->arena + off); }
+
+void build_names(pvf_engine* e)
+{
+    const int n = e->spec.n_levels;
+    const int c0 = e->spec.base_channels;
+    auto add = [&](const std::string& name, const std::string& kernel) {
+        e->names.push_back(name);
+        e->kernels.push_back(kernel);
+    };
+    e->names.clear();
+    e->kernels.clear();
+    add("track", "track_stage");
+    for (int l = 0; l < n; ++l) {
+        const std::string L = std::to_string(l);
+        const int C = c0 << l;
+        add("enc" + L + ".c1", l == 0 ? "first_conv" : conv_kernel_name(C, kTaps, EPI_STORE));
+        add("enc" + L + ".c2", conv_kernel_name(C, kTaps, l < n - 1 ? EPI_POOL : EPI_STORE));
+    }
+    for (int l = n - 2; l >= 0; --l) {
+        const std::string L = std::to_string(l);
+        const int C = c0 << l;
+        add("up" + L, conv_kernel_name(2 * C, 1, EPI_CONVT));
+        add("dec" + L + ".c1", conv_kernel_name(C, kTaps, EPI_STORE));
+        add(l == 0 ? "dec0.c2+head" : "dec" + L + ".c2", conv_kernel_name(C, kTaps, l == 0 ? EPI_HEAD : EPI_STORE));
+    }
+    add("peaks", "peak_finder");
+}
+
+bool misaligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) != 0; }
+
+ConvArgs conv_args(pvf_engine* eng, const WeightLayout::Conv& c, const float* in, int ld_in, int rows_per_event,
+                   int n_events, float* out, int ld_out)
+{
+    ConvArgs a{};
+    const float* wbase = at<float>(eng, eng->plan.weights);
+    a.in = in;
+    a.ld_in = ld_in;
+    a.cin = c.cin;
+    a.m_rows = n_events * rows_per_event;
+    a.r_in = rows_per_event;
+    a.w = wbase + c.w;
+    a.bias = wbase + c.b;
+    a.n = c.cout;
+    a.slope = eng->leaky;
+    a.out = out;
+    a.ld_out = ld_out;
+    a.r_out = rows_per_event;
+    a.cout = c.cout;
+    return a;
+}
+
+pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* out, hipStream_t s)
+{
+    const int E = tr->n_events;
+    const Plan& P = eng->plan;
+    const WeightLayout& W = eng->wl;
+    const int n = P.n_levels;
+    const float* wbase = at<float>(eng, P.weights);
+    float* prob = out->d_prob_hist ? out->d_prob_hist : at<float>(eng, P.prob);
+    int32_t* flags = at<int32_t>(eng, P.flags);
+    int li = 0;
+    hipError_t err = hipSuccess;
+    auto mark = [&]() {
+        if (eng->profiling && err == hipSuccess) err = hipEventRecord(eng->events[li], s);
+        ++li;
+    };
+    auto check = [&](hipError_t e) { if (err == hipSuccess) err = e; mark(); };
+
+    li = 0;
+    if (eng->profiling) err = hipEventRecord(eng->events[0], s);
+    li = 1;
+
+    // ---- FC stage: tracks -> scaled histogram rows of level 0
+    TrackArgs ta{};
+    ta.offsets = tr->d_event_offsets;
+    static const float kDummy[1] = {0.f};
+    for (int k = 0; k < kFeat; ++k) ta.feat[k] = tr->d_feat[k] ? tr->d_feat[k] : kDummy;
+    ta.n_tracks_total = tr->n_tracks_total;
+    ta.max_tracks = eng->spec.max_tracks_per_event;
+    ta.mlp = wbase + W.mlp;
+    ta.n_hidden = eng->n_hidden;
+    ta.n_out = eng->spec.bins_per_interval;
+    ta.n_intervals = eng->spec.n_bins / eng->spec.bins_per_interval;
+    ta.z_min = eng->spec.z_min_mm;
+    ta.interval_mm = eng->spec.bin_width_mm * eng->spec.bins_per_interval;
+    for (int k = 0; k < kFeat; ++k) { ta.shift[k] = eng->shift[k]; ta.scale[k] = eng->scale[k]; }
+    ta.slope = eng->leaky;
+    ta.s_in = eng->s_in;
+    ta.x0 = at<float>(eng, P.x0);
+    ta.r0 = P.lv[0].R;
+    ta.flags = flags;
+    check(launch_track(ta, E, s));
+
+    // ---- encoder
+    FirstConvArgs fa{};
+    fa.x0 = at<float>(eng, P.x0);
+    fa.m_rows = E * P.lv[0].R;
+    fa.r0 = P.lv[0].R;
+    fa.w = wbase + W.first_w;
+    fa.b = wbase + W.first_b;
+    fa.c0 = P.lv[0].C;
+    fa.slope = eng->leaky;
+    fa.out = at<float>(eng, P.a[0]);
+    check(launch_first_conv(fa, s));
+
+    for (int l = 0; l < n; ++l) {
+        const Level& lv = P.lv[l];
+        if (l > 0) {
+            const Level& up = P.lv[l - 1];
+            ConvArgs a = conv_args(eng, W.enc[l][0], at<float>(eng, P.pool[l]), up.C, lv.R, E,
+                                   at<float>(eng, P.a[l]), lv.C);
+            check(launch_conv(a, kTaps, EPI_STORE, s));
+        }
+        if (l < n - 1) {
+            ConvArgs a = conv_args(eng, W.enc[l][1], at<float>(eng, P.a[l]), lv.C, lv.R, E,
+                                   at<float>(eng, P.cat[l]), 2 * lv.C);
+            a.pool_out = at<float>(eng, P.pool[l + 1]);
+            a.ld_pool = lv.C;
+            a.r_pool = P.lv[l + 1].R;
+            check(launch_conv(a, kTaps, EPI_POOL, s));
+        } else {
+            ConvArgs a = conv_args(eng, W.enc[l][1], at<float>(eng, P.a[l]), lv.C, lv.R, E,
+                                   at<float>(eng, P.d[l]), lv.C);
+            check(launch_conv(a, kTaps, EPI_STORE, s));
+        }
+    }
+    // ---- decoder
+    for (int l = n - 2; l >= 0; --l) {
+        const Level& lv = P.lv[l];
+        const Level& lo = P.lv[l + 1];
+        ConvArgs u = conv_args(eng, W.up[l], at<float>(eng, P.d[l + 1]), lo.C, lo.R, E,
+                               at<float>(eng, P.cat[l]) + lv.C, 2 * lv.C);
+        u.n = 2 * lv.C;
+        u.cout = lv.C;
+        u.r_out = lv.R;
+        check(launch_conv(u, 1, EPI_CONVT, s));
+        ConvArgs a = conv_args(eng, W.dec[l][0], at<float>(eng, P.cat[l]), 2 * lv.C, lv.R, E,
+                               at<float>(eng, P.a[l]), lv.C);
+        check(launch_conv(a, kTaps, EPI_STORE, s));
+        if (l > 0) {
+            ConvArgs b = conv_args(eng, W.dec[l][1], at<float>(eng, P.a[l]), lv.C, lv.R, E,
+                                   at<float>(eng, P.d[l]), lv.C);
+            check(launch_conv(b, kTaps, EPI_STORE, s));
+        } else {
+            ConvArgs b = conv_args(eng, W.dec[0][1], at<float>(eng, P.a[0]), lv.C, lv.R, E, nullptr, 0);
+            b.head_w = wbase + W.head_w;
+            b.head_b = eng->head_b;
+            b.prob = prob;
+            b.l_out = lv.L;
+            check(launch_conv(b, kTaps, EPI_HEAD, s));
+        }
+    }
+    // ---- peaks
+    PeakArgs pa{};
+    pa.prob = prob;
+    pa.L = P.lv[0].L;
+    pa.flags = flags;
+    pa.z_min = eng->spec.z_min_mm;
+    pa.bw = eng->spec.bin_width_mm;
+    pa.p_min = eng->spec.peak_min;
+    pa.s_min = eng->spec.integral_min;
+    pa.hw = eng->spec.half_window;
+    pa.max_peaks = eng->spec.max_peaks_per_event;
+    pa.n_vertices = out->d_n_vertices;
+    pa.z = out->d_z;
+    pa.peak_prob = out->d_peak_prob;
+    pa.integral = out->d_integral;
+    pa.status = out->d_event_status;
+    pa.bin = out->d_bin;
+    check(launch_peaks(pa, E, s));
+    return err == hipSuccess ? PVF_OK : PVF_ERR_DEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pvf_spec_default(pvf_spec* s)
+{
+    if (!s) return;
+    std::memset(s, 0, sizeof(*s));
+    s->abi_version = PVF_ABI_VERSION;
+    s->max_events = 1000;
+    s->max_tracks_per_event = 1500;
+    s->max_peaks_per_event = 2000;
+    s->max_tracks_total = 1500 * 1000;
+    s->compute_dtype = PVF_FP32;
+    s->n_levels = 4;
+    s->base_channels = 32;
+    s->n_bins = 4000;
+    s->bins_per_interval = 100;
+    s->half_window = 5;
+    s->z_min_mm = -100.0;
+    s->bin_width_mm = 0.1;
+    s->peak_min = 0.01;
+    s->integral_min = 0.2;
+}
+
+pvf_status pvf_arena_bytes(const pvf_spec* spec, size_t* out_bytes)
+{
+    if (!spec || !out_bytes) return PVF_ERR_INVALID_ARGUMENT;
+    pvf_status st = validate_spec(spec);
+    if (st != PVF_OK) return st;
+    Plan p;
+    make_plan(spec, weight_floats_for(spec), &p);
+    *out_bytes = p.total;
+    return PVF_OK;
+}
+
+pvf_status pvf_init(const pvf_spec* spec, const void* blob, size_t blob_bytes, void* d_arena, size_t arena_bytes,
+                    void* stream, pvf_engine** out)
+{
+    if (out) *out = nullptr;
+    if (!spec || !blob || !d_arena || !stream || !out) return PVF_ERR_INVALID_ARGUMENT;
+    if (misaligned(d_arena, kAlign)) return PVF_ERR_ALIGNMENT;
+    pvf_status st = validate_spec(spec);
+    if (st != PVF_OK) return st;
+    Plan plan;
+    make_plan(spec, weight_floats_for(spec), &plan);
+    if (arena_bytes < plan.total) return PVF_ERR_ARENA_TOO_SMALL;
+    Blob b;
+    st = parse_blob(blob, blob_bytes, spec, &b);
+    if (st != PVF_OK) return st;
+
+    pvf_engine* e = new (std::nothrow) pvf_engine();
+    if (!e) return PVF_ERR_INVALID_ARGUMENT;
+    e->spec = *spec;
+    e->plan = plan;
+    weight_layout(b.shape, &e->wl);
+    e->n_hidden = b.shape.n_hidden;
+    e->leaky = b.leaky;
+    e->s_in = b.s_in;
+    e->head_b = b.store.back()[0];
+    for (int k = 0; k < kFeat; ++k) { e->shift[k] = b.shift[k]; e->scale[k] = b.scale[k]; }
+    e->arena = static_cast<char*>(d_arena);
+    e->stream = static_cast<hipStream_t>(stream);
+    build_names(e);
+
+    std::vector<float> packed;
+    pack_weights(b, e->wl, packed);
+    hipError_t err = hipMemcpyAsync(e->arena + plan.weights, packed.data(), packed.size() * sizeof(float),
+                                    hipMemcpyHostToDevice, e->stream);
+    if (err == hipSuccess)
+        err = hipMemsetAsync(e->arena + plan.zero_begin, 0, plan.zero_end - plan.zero_begin, e->stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
+    if (err != hipSuccess) {
+        delete e;
+        return PVF_ERR_DEVICE;
+    }
+    *out = e;
+    return PVF_OK;
+}
+
+static pvf_status check_call(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* out)
+{
+    if (!eng || !tr || !out) return PVF_ERR_INVALID_ARGUMENT;
+    if (tr->n_events < 0 || tr->n_tracks_total < 0) return PVF_ERR_INVALID_ARGUMENT;
+    if (tr->n_events > eng->spec.max_events || tr->n_tracks_total > eng->spec.max_tracks_total)
+        return PVF_ERR_CAPACITY;
+    if (tr->n_events == 0) return PVF_OK;
+    if (!tr->d_event_offsets) return PVF_ERR_INVALID_ARGUMENT;
+    if (misaligned(tr->d_event_offsets, 4)) return PVF_ERR_ALIGNMENT;
+    for (int k = 0; k < kFeat; ++k) {
+        if (tr->n_tracks_total > 0 && !tr->d_feat[k]) return PVF_ERR_INVALID_ARGUMENT;
+        if (tr->d_feat[k] && misaligned(tr->d_feat[k], 4)) return PVF_ERR_ALIGNMENT;
+    }
+    if (!out->d_n_vertices || !out->d_z || !out->d_peak_prob || !out->d_integral || !out->d_event_status)
+        return PVF_ERR_INVALID_ARGUMENT;
+    if (misaligned(out->d_n_vertices, 4) || misaligned(out->d_z, 8) || misaligned(out->d_peak_prob, 4) ||
+        misaligned(out->d_integral, 8) || misaligned(out->d_event_status, 4) ||
+        (out->d_prob_hist && misaligned(out->d_prob_hist, 4)) || (out->d_bin && misaligned(out->d_bin, 4)))
+        return PVF_ERR_ALIGNMENT;
+    return PVF_OK;
+}
+
+pvf_status pvf_execute(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* out)
+{
+    pvf_status st = check_call(eng, tr, out);
+    if (st != PVF_OK || tr->n_events == 0) return st;
+    return enqueue(eng, tr, out, eng->stream);
+}
+
+pvf_status pvf_execute_on(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* out, void* stream)
+{
+    if (!stream) return PVF_ERR_INVALID_ARGUMENT;
+    pvf_status st = check_call(eng, tr, out);
+    if (st != PVF_OK || tr->n_events == 0) return st;
+    return enqueue(eng, tr, out, static_cast<hipStream_t>(stream));
+}
+
+pvf_status pvf_destroy(pvf_engine* eng)
+{
+    if (!eng) return PVF_ERR_INVALID_ARGUMENT;
+    for (hipEvent_t ev : eng->events) (void)hipEventDestroy(ev);
+    delete eng;
+    return PVF_OK;
+}
+
+const char* pvf_status_string(pvf_status s)
+{
+    switch (s) {
+    case PVF_OK: return "ok";
+    case PVF_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case PVF_ERR_SHAPE: return "unsupported shape";
+    case PVF_ERR_CAPACITY: return "batch exceeds the frozen capacity";
+    case PVF_ERR_ARENA_TOO_SMALL: return "arena too small";
+    case PVF_ERR_WEIGHTS: return "malformed weight blob or shape mismatch";
+    case PVF_ERR_UNSUPPORTED_DTYPE: return "compute dtype not supported";
+    case PVF_ERR_DEVICE: return "HIP runtime error";
+    case PVF_ERR_ALIGNMENT: return "misaligned buffer";
+    }
+    return "unknown status";
+}
+
+int pvf_launch_count(const pvf_engine* eng) { return eng ? (int)eng->names.size() : 0; }
+
+const char* pvf_launch_name(const pvf_engine* eng, int i)
+{
+    if (!eng || i < 0 || i >= (int)eng->names.size()) return nullptr;
+    return eng->names[i].c_str();
+}
+
+const char* pvf_launch_kernel(const pvf_engine* eng, int i)
+{
+    if (!eng || i < 0 || i >= (int)eng->kernels.size()) return nullptr;
+    return eng->kernels[i].c_str();
+}
+
+pvf_status pvf_profile_enable(pvf_engine* eng, int on)
+{
+    if (!eng) return PVF_ERR_INVALID_ARGUMENT;
+    if (on && !eng->profiling) {
+        eng->events.assign(eng->names.size() + 1, nullptr);
+        for (auto& ev : eng->events)
+            if (hipEventCreate(&ev) != hipSuccess) return PVF_ERR_DEVICE;
+        eng->profiling = true;
+    } else if (!on && eng->profiling) {
+        for (hipEvent_t ev : eng->events) (void)hipEventDestroy(ev);
+        eng->events.clear();
+        eng->profiling = false;
+    }
+    return PVF_OK;
+}
+
+pvf_status pvf_profile_read(pvf_engine* eng, float* ms, int n)
+{
+    if (!eng || !ms || !eng->profiling || n > (int)eng->names.size() || n < 0) return PVF_ERR_INVALID_ARGUMENT;
+    for (int i = 0; i < n; ++i)
+        if (hipEventElapsedTime(&ms[i], eng->events[i], eng->events[i + 1]) != hipSuccess) return PVF_ERR_DEVICE;
+    return PVF_OK;
+}
+
+pvf_status pvf_debug_tensor(pvf_engine* eng, const char* name, int32_t n_events, float* d_dst, int64_t* out_count)
+{
+    if (!eng || !name || !out_count || n_events < 0 || n_events > eng->spec.max_events)
+        return PVF_ERR_INVALID_ARGUMENT;
+    const Plan& P = eng->plan;
+    const int n = P.n_levels;
+    GatherArgs g{};
+    bool found = false;
+    auto set = [&](size_t off, int ld, int l, int C, int ch_off) {
+        g.src = at<float>(eng, off);
+        g.ld = ld;
+        g.r = P.lv[l].R;
+        g.guard = kGuard;
+        g.L = P.lv[l].L;
+        g.C = C;
+        g.ch_off = ch_off;
+        found = true;
+    };
+    const std::string s(name);
+    if (s == "hist") set(P.x0, 1, 0, 1, 0);
+    if (s == "prob") {
+        g.src = at<float>(eng, P.prob);
+        g.ld = 1; g.r = P.lv[0].L; g.guard = 0; g.L = P.lv[0].L; g.C = 1; g.ch_off = 0;
+        found = true;
+    }
+    for (int l = 0; l < n; ++l) {
+        const std::string L = std::to_string(l);
+        const int C = P.lv[l].C;
+        if (l < n - 1 && s == "enc" + L + ".c2") set(P.cat[l], 2 * C, l, C, 0);
+        if (l == n - 1 && s == "enc" + L + ".c2") set(P.d[l], C, l, C, 0);
+        if (l == n - 1 && s == "enc" + L + ".c1") set(P.a[l], C, l, C, 0);
+        if (l < n - 1 && s == "pool" + L) set(P.pool[l + 1], C, l + 1, C, 0);
+        if (l < n - 1 && s == "up" + L) set(P.cat[l], 2 * C, l, C, C);
+        if (l < n - 1 && s == "dec" + L + ".c1") set(P.a[l], C, l, C, 0);
+        if (l >= 1 && l < n - 1 && s == "dec" + L + ".c2") set(P.d[l], C, l, C, 0);
+    }
+    if (!found) return PVF_ERR_INVALID_ARGUMENT;
+    g.count = (int64_t)n_events * g.C * g.L;
+    *out_count = g.count;
+    if (!d_dst) return PVF_OK;
+    g.dst = d_dst;
+    return launch_gather(g, eng->stream) == hipSuccess ? PVF_OK : PVF_ERR_DEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,149 @@
+// Internal declarations of the PVFinder HIP library: arena plan, engine state
+// and kernel launchers.  Not part of the C ABI (see include/pvf.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pvf.h"
+
+namespace pvf {
+
+constexpr int kFeat = PVF_N_FEATURES;
+constexpr int kHidden = 20;       // width of the per-track hidden layers
+constexpr int kMaxHiddenLayers = 16;
+constexpr int kTaps = 5;          // UNet conv kernel size
+constexpr int kGuard = 2;         // zero rows before and after each event
+constexpr int kMaxLevels = 6;
+constexpr size_t kAlign = 256;
+
+// Activation layout: channels-last, one block of R = L + 2*kGuard rows per
+// event, rows [kGuard, kGuard + L) hold positions 0..L-1 and the guard rows
+// stay zero for the life of the engine, so a 5-tap window never reaches into
+// a neighbouring event and needs no branch.
+struct Level {
+    int L;      // positions
+    int R;      // rows per event (L + 2*kGuard)
+    int C;      // channels of this level
+};
+
+// Offsets (bytes from the arena base) of every buffer.
+struct Plan {
+    int n_levels = 0;
+    int c0 = 0;
+    int max_events = 0;
+    Level lv[kMaxLevels];
+    size_t weights = 0, weights_bytes = 0;
+    size_t x0 = 0;                 // [E][R0][1]      scaled histogram
+    size_t a[kMaxLevels] = {};     // [E][Rl][Cl]     conv1 outputs (enc, then dec)
+    size_t cat[kMaxLevels] = {};   // [E][Rl][2Cl]    skip | upsampled  (l < n-1)
+    size_t pool[kMaxLevels] = {};  // [E][Rl][C(l-1)] pooled input of level l (l >= 1)
+    size_t d[kMaxLevels] = {};     // [E][Rl][Cl]     decoder conv2 out (1 <= l <= n-2), deepest conv2 (l = n-1)
+    size_t prob = 0;               // [E][L0] float
+    size_t flags = 0;              // [E] int32 track-stage status
+    size_t zero_begin = 0, zero_end = 0;   // region cleared at init
+    size_t total = 0;
+};
+
+// Packed weights, as element offsets (floats) from the weight region.
+struct WeightLayout {
+    size_t mlp = 0, mlp_count = 0;          // MLP tensors as in the blob
+    size_t first_w = 0, first_b = 0;        // enc0.c1: [C0][5], [C0]
+    struct Conv { size_t w = 0, b = 0; int cin = 0, cout = 0, taps = 0; };
+    Conv enc[kMaxLevels][2];                // [l][0] conv1 (l > 0), [l][1] conv2
+    Conv up[kMaxLevels];                    // up[l]: from level l+1 into level l
+    Conv dec[kMaxLevels][2];
+    size_t head_w = 0, head_b = 0;
+    size_t total = 0;
+};
+
+enum Epi { EPI_STORE = 0, EPI_POOL = 1, EPI_CONVT = 2, EPI_HEAD = 3 };
+
+struct ConvArgs {
+    const float* in;     // input rows, channels-last
+    int ld_in;           // floats per input row
+    int cin;             // channels read (multiple of 16)
+    int m_rows;          // total input rows (= events * R_in)
+    int r_in;            // rows per event of the input level
+    const float* w;      // packed [N][taps][cin]
+    const float* bias;   // [Cout]
+    int n;               // GEMM N (Cout, or 2*Cout for the transposed conv)
+    float slope;         // LeakyReLU slope
+    float* out;          // output base (row 0, channel 0 of the destination)
+    int ld_out;          // floats per output row
+    int r_out;           // rows per event of the output level
+    int cout;            // output channels (transposed conv: n / 2)
+    float* pool_out;     // EPI_POOL: pooled destination
+    int ld_pool;
+    int r_pool;
+    const float* head_w; // EPI_HEAD: [C0] head weights
+    float head_b;
+    float* prob;         // EPI_HEAD: [E][L0]
+    int l_out;           // positions per event of the output (EPI_HEAD)
+};
+
+struct TrackArgs {
+    const int32_t* offsets;
+    const float* feat[kFeat];
+    int64_t n_tracks_total;
+    int max_tracks;
+    const float* mlp;        // MLP tensors in blob order
+    int n_hidden;
+    int n_out;               // bins per interval
+    int n_intervals;
+    double z_min;
+    double interval_mm;
+    float shift[kFeat];
+    float scale[kFeat];
+    float slope;
+    float s_in;
+    float* x0;               // [E][R0]
+    int r0;
+    int32_t* flags;          // [E]
+};
+
+struct FirstConvArgs {
+    const float* x0;         // [E][R0]
+    int m_rows;
+    int r0;
+    const float* w;          // [C0][5]
+    const float* b;          // [C0]
+    int c0;
+    float slope;
+    float* out;              // [E][R0][C0]
+};
+
+struct PeakArgs {
+    const float* prob;       // [E][L]
+    int L;
+    const int32_t* flags;    // [E] track-stage status
+    double z_min, bw, p_min, s_min;
+    int hw;
+    int max_peaks;
+    int32_t* n_vertices;
+    double* z;
+    float* peak_prob;
+    double* integral;
+    int32_t* status;
+    int32_t* bin;            // may be null
+};
+
+struct GatherArgs {          // debug copy of an internal activation
+    const float* src;
+    int ld, r, guard, L, C, ch_off;
+    float* dst;              // [E][C][L]
+    int64_t count;
+};
+
+hipError_t launch_track(const TrackArgs& a, int n_events, hipStream_t s);
+hipError_t launch_first_conv(const FirstConvArgs& a, hipStream_t s);
+hipError_t launch_conv(const ConvArgs& a, int taps, Epi epi, hipStream_t s);
+std::string conv_kernel_name(int n, int taps, Epi epi);   // instance launch_conv picks
+hipError_t launch_peaks(const PeakArgs& a, int n_events, hipStream_t s);
+hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
+
+}  // namespace pvf

@@ -1,0 +1,182 @@
+// FC stage: per-track network and histogram, one workgroup per event.
+//
+// Section 2 of arXiv:2602.19959: nine features per track go through six FC
+// layers, and every track's outputs are combined into the event's histogram
+// over 40 intervals of 100 bins; Section 3: a track feeds the interval that
+// holds it, and an event is processed by one block reading SoA buffers.
+//
+// Per chunk of 256 tracks (one per thread, coalesced SoA loads):
+//   A  bin the track (exact comparison with the interval edges in double),
+//      build its features and run the hidden layers in registers; the
+//      weights are wave-uniform, so they come through the scalar cache;
+//   B  per sub-chunk of 64 tracks, wave q computes outputs j = q, q+4, ...
+//      of all 64 tracks (softplus, positive), into LDS;
+//   C  thread j adds output j of the sub-chunk's tracks, in track order, to
+//      the LDS histogram.
+// Every bin is therefore a sequential sum in ascending track order: the
+// histogram is deterministic, with no atomics.  The block then writes the
+// scaled histogram, once, straight into the UNet's input rows.
+#include <cmath>
+
+#include "pvf_internal.h"
+
+namespace pvf {
+namespace {
+
+constexpr int NT = 256;   // tracks per chunk, one per thread
+constexpr int SUB = 64;   // tracks per output/scatter sub-chunk (one per lane)
+constexpr int HP = kHidden + 1;   // LDS pitch of the hidden activations
+
+__device__ __forceinline__ float lrelu(float x, float s) { return x >= 0.f ? x : s * x; }
+
+__device__ __forceinline__ float softplus(float x)
+{
+    return fmaxf(x, 0.f) + log1pf(expf(-fabsf(x)));
+}
+
+__global__ __launch_bounds__(NT) void track_stage(TrackArgs a)
+{
+    extern __shared__ float smem[];
+    const int n_bins = a.n_out * a.n_intervals;
+    float* H = smem;                                  // [n_bins]
+    float* hb = H + n_bins;                           // [NT][HP]
+    float* ob = hb + NT * HP;                         // [SUB][n_out + 1]
+    int* iv = reinterpret_cast<int*>(ob + SUB * (a.n_out + 1));   // [NT]
+    __shared__ int dropped_any;
+
+    const int tid = threadIdx.x;
+    const int e = blockIdx.x;
+    const int op = a.n_out + 1;
+
+    for (int b = tid; b < n_bins; b += NT) H[b] = 0.f;
+    if (tid == 0) dropped_any = 0;
+
+    const int64_t beg = a.offsets[e];
+    const int64_t end = a.offsets[e + 1];
+    int status = 0;
+    if (beg < 0 || end < beg || end > a.n_tracks_total) status = PVF_EV_BAD_INPUT;
+    else if (end - beg > a.max_tracks) status = PVF_EV_TOO_MANY_TRACKS;
+    __syncthreads();
+
+    const float* W1 = a.mlp;                               // [kHidden][kFeat]
+    const float* b1 = W1 + kHidden * kFeat;
+    const float* Wh = b1 + kHidden;                        // hidden layers 2.. : [W 20x20, b 20]
+    const float* Wo = Wh + (size_t)(a.n_hidden - 1) * (kHidden * kHidden + kHidden);  // [n_out][kHidden]
+    const float* bo = Wo + (size_t)a.n_out * kHidden;
+    const double z_max = a.z_min + a.interval_mm * a.n_intervals;
+
+    if (status == 0) {
+        for (int64_t base = beg; base < end; base += NT) {
+            // ---- A: bin, features, hidden layers
+            const int64_t t = base + tid;
+            int itv = -1;
+            float h[kHidden];
+#pragma unroll
+            for (int j = 0; j < kHidden; ++j) h[j] = 0.f;
+            if (t < end) {
+                float f[kFeat];
+                bool finite = true;
+#pragma unroll
+                for (int k = 0; k < kFeat; ++k) {
+                    f[k] = a.feat[k][t];
+                    finite = finite && isfinite(f[k]);
+                }
+                const double zd = (double)f[0];
+                if (finite && zd >= a.z_min && zd < z_max) {
+                    int i = (int)floor((zd - a.z_min) / a.interval_mm);
+                    i = i < 0 ? 0 : (i >= a.n_intervals ? a.n_intervals - 1 : i);
+                    if (zd < a.z_min + a.interval_mm * i) --i;
+                    else if (zd >= a.z_min + a.interval_mm * (i + 1)) ++i;
+                    if (i >= 0 && i < a.n_intervals) itv = i;
+                }
+                if (itv < 0) {
+                    dropped_any = 1;   // benign race: every writer stores 1
+                } else {
+                    float g[kFeat];
+                    const double lo = a.z_min + a.interval_mm * itv;
+                    g[0] = (float)((zd - lo) / (a.interval_mm * 0.5) - 1.0);
+#pragma unroll
+                    for (int k = 1; k < kFeat; ++k) g[k] = (f[k] - a.shift[k]) * a.scale[k];
+#pragma unroll
+                    for (int j = 0; j < kHidden; ++j) {
+                        float s = b1[j];
+#pragma unroll
+                        for (int k = 0; k < kFeat; ++k) s = fmaf(W1[j * kFeat + k], g[k], s);
+                        h[j] = lrelu(s, a.slope);
+                    }
+                    for (int l = 1; l < a.n_hidden; ++l) {
+                        const float* W = Wh + (size_t)(l - 1) * (kHidden * kHidden + kHidden);
+                        const float* bb = W + kHidden * kHidden;
+                        float hn[kHidden];
+#pragma unroll
+                        for (int j = 0; j < kHidden; ++j) {
+                            float s = bb[j];
+#pragma unroll
+                            for (int k = 0; k < kHidden; ++k) s = fmaf(W[j * kHidden + k], h[k], s);
+                            hn[j] = lrelu(s, a.slope);
+                        }
+#pragma unroll
+                        for (int j = 0; j < kHidden; ++j) h[j] = hn[j];
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kHidden; ++j) hb[tid * HP + j] = h[j];
+            iv[tid] = itv;
+            __syncthreads();
+
+            const int n_chunk = (int)((end - base) < NT ? (end - base) : NT);
+            for (int sub = 0; sub < n_chunk; sub += SUB) {
+                // ---- B: wave q computes outputs q, q+4, ... for the 64 tracks
+                const int lane = tid & 63, q = tid >> 6;
+                const int tt = sub + lane;
+                if (tt < n_chunk && iv[tt] >= 0) {
+                    float hl[kHidden];
+#pragma unroll
+                    for (int k = 0; k < kHidden; ++k) hl[k] = hb[tt * HP + k];
+                    for (int j = q; j < a.n_out; j += NT / 64) {
+                        float s = bo[j];
+#pragma unroll
+                        for (int k = 0; k < kHidden; ++k) s = fmaf(Wo[j * kHidden + k], hl[k], s);
+                        ob[lane * op + j] = softplus(s);
+                    }
+                }
+                __syncthreads();
+                // ---- C: ordered accumulation, thread j owns column j
+                if (tid < a.n_out) {
+                    const int lim = (n_chunk - sub) < SUB ? (n_chunk - sub) : SUB;
+                    for (int l = 0; l < lim; ++l) {
+                        const int i = iv[sub + l];
+                        if (i >= 0) H[i * a.n_out + tid] += ob[l * op + tid];
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    __syncthreads();
+    float* x0 = a.x0 + (int64_t)e * a.r0 + kGuard;
+    for (int b = tid; b < n_bins; b += NT) x0[b] = a.s_in * H[b];
+    if (tid == 0) a.flags[e] = status | (dropped_any ? PVF_EV_TRACKS_DROPPED : 0);
+}
+
+}  // namespace
+
+static size_t track_stage_lds_bytes(int n_out, int n_intervals)
+{
+    return sizeof(float) * ((size_t)n_out * n_intervals + NT * HP + SUB * (n_out + 1)) + sizeof(int) * NT;
+}
+
+hipError_t launch_track(const TrackArgs& a, int n_events, hipStream_t s)
+{
+    const size_t lds = track_stage_lds_bytes(a.n_out, a.n_intervals);
+    if (lds > 64 * 1024) {
+        hipError_t err = hipFuncSetAttribute((const void*)track_stage,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (err != hipSuccess) return err;
+    }
+    hipLaunchKernelGGL(track_stage, dim3(n_events), dim3(NT), lds, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace pvf

@@ -1,0 +1,59 @@
+"""Shared helpers of the GPU tests: engines, uploads, oracle references."""
+
+import functools
+
+import numpy as np
+
+import oracle
+from synth import make_events, make_weights, weights_to_blob
+
+
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        import pytest
+        pytest.skip("no GPU")
+    return torch
+
+
+@functools.lru_cache(maxsize=None)
+def weights(seed=0):
+    return make_weights(seed)
+
+
+@functools.lru_cache(maxsize=None)
+def blob(seed=0):
+    return weights_to_blob(weights(seed))
+
+
+def make_engine(max_events, **spec):
+    import paper_2602_19959_amd as pv
+    s = pv.default_spec(max_events=max_events, **spec)
+    if "max_tracks_total" not in spec:
+        s.max_tracks_total = max_events * 1500
+    return pv.Engine(blob(), s)
+
+
+def run(engine, batch, with_prob=True):
+    """Upload `batch`, execute, wait, return host numpy outputs."""
+    import paper_2602_19959_amd as pv
+    feat, off = pv.upload_events(batch)
+    out = engine.alloc_outputs(batch.n_events, with_prob=with_prob)
+    engine.execute(feat, off, out)
+    engine.synchronize()
+    return out.to_host()
+
+
+def geometry(engine):
+    s = engine.spec
+    return oracle.Geometry(z_min=s.z_min_mm, bin_width=s.bin_width_mm,
+                           n_intervals=s.n_bins // s.bins_per_interval,
+                           bins_per_interval=s.bins_per_interval, p_min=s.peak_min,
+                           s_min=s.integral_min, half_window=s.half_window,
+                           max_peaks=s.max_peaks_per_event)
+
+
+def event_vertices(host, e):
+    """(bins, z, height, window sum) of event e's vertices."""
+    n = int(host["n_vertices"][e])
+    return host["bin"][e, :n], host["z"][e, :n], host["peak_prob"][e, :n], host["integral"][e, :n]

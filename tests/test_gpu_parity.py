@@ -1,0 +1,194 @@
+"""GPU parity of the FP32 HIP path against the FP64 oracle, through the C ABI.
+
+Workloads (seeded, synthetic, see synth/): the 8-event parity batch
+(Poisson(180) tracks, Poisson(5.6) vertices), the 1000-event production
+batch, and heavy-tailed batches (log-normal track counts up to 1500).
+Bars (tests/parity.py): p within 1e-4 relative, identical peak sets on every
+robust decision, histogram exact where it is zero.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import make_events
+from synth.events import pack_events
+from tests import parity
+from tests.gpu_util import torch_cuda, make_engine, run, geometry, event_vertices, weights
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-parity]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def eng8():
+    torch_cuda()
+    say("engine max_events=8")
+    e = make_engine(8)
+    yield e
+    e.close()
+
+
+@pytest.fixture(scope="module")
+def batch8():
+    return make_events(8, seed=0)
+
+
+@pytest.fixture(scope="module")
+def ref8(batch8):
+    return oracle.run_batch(batch8, weights())
+
+
+@pytest.fixture(scope="module")
+def out8(eng8, batch8):
+    say("execute 8-event batch")
+    return run(eng8, batch8)
+
+
+def test_probability_parity(out8, ref8):
+    errs = [parity.max_rel(out8["prob"][e], ref8[e]["p"]) for e in range(8)]
+    say("max rel err p per event", ["%.2e" % x for x in errs])
+    assert max(errs) <= parity.P_REL
+
+
+def test_peak_parity(eng8, out8, ref8):
+    geo = geometry(eng8)
+    total_amb = 0
+    for e in range(8):
+        bins, z, h, S = event_vertices(out8, e)
+        assert out8["n_vertices"][e] == len(bins)
+        amb, n = parity.compare_peaks(bins, z, h, S, ref8[e], geo)
+        total_amb += amb
+    say("ambiguous decisions excluded:", total_amb)
+    assert total_amb < 100
+
+
+def test_status_ok(out8, ref8):
+    assert np.all(out8["status"] == 0)
+
+
+def test_histogram_parity(eng8, out8, ref8):
+    hist = eng8.debug_tensor("hist", 8).cpu().numpy().reshape(8, -1)
+    s_in = weights().s_in
+    for e in range(8):
+        ref = s_in * ref8[e]["H"]
+        nz = ref != 0
+        assert np.all(hist[e][~nz] == 0)
+        assert parity.max_rel(hist[e][nz], ref[nz]) <= parity.P_REL
+
+
+LAYERS = ["enc0.c2", "pool0", "enc1.c2", "pool1", "enc2.c2", "pool2", "enc3.c1", "enc3.c2",
+          "up2", "dec2.c1", "dec2.c2", "up1", "dec1.c1", "dec1.c2", "up0", "dec0.c1"]
+
+
+@pytest.mark.parametrize("name", LAYERS)
+def test_layer_parity(eng8, batch8, out8, name):
+    """Every stored activation of event 0 against the oracle's taps."""
+    w = weights()
+    ref = oracle.unet_taps(w.s_in * oracle.histogram(batch8.tracks_of(0), w)[0], w)[name]
+    got = eng8.debug_tensor(name, 1).cpu().numpy().reshape(ref.shape)
+    err = parity.tap_err(got, ref)
+    say(name, "normwise tap err %.2e" % err)
+    assert err <= parity.TAP_NORM
+
+
+def test_deterministic_rerun(eng8, batch8, out8):
+    again = run(eng8, batch8)
+    for k in ("prob", "z", "integral", "n_vertices", "bin"):
+        assert np.array_equal(again[k], out8[k]), k
+
+
+def test_batch_invariance(eng8, batch8, out8):
+    """An event alone gives the same bits as inside the batch."""
+    for e in (0, 5):
+        alone = run(eng8, batch8.subset([e]))
+        assert np.array_equal(alone["prob"][0], out8["prob"][e])
+        n = out8["n_vertices"][e]
+        assert alone["n_vertices"][0] == n
+        assert np.array_equal(alone["z"][0, :n], out8["z"][e, :n])
+
+
+def test_track_order_invariance(eng8, batch8, out8):
+    tr = batch8.tracks_of(2)
+    perm = np.random.default_rng(3).permutation(tr.shape[1])
+    out = run(eng8, pack_events([tr[:, perm]]))
+    assert parity.max_rel(out["prob"][0], out8["prob"][2]) <= 1e-5
+
+
+def test_edge_events(eng8):
+    """Zero tracks, one track, out-of-window and non-finite tracks, an event
+    over the track cap, and decreasing offsets (bypass) in one batch."""
+    import paper_2602_19959_amd as pv
+    torch = torch_cuda()
+    ev = make_events(4, seed=5)
+    t0 = ev.tracks_of(0).copy()
+    t0[0, :3] = [-150.0, 300.0, np.nan]
+    t0[5, 3] = np.inf
+    one = ev.tracks_of(1)[:, :1].copy()
+    lists = [np.zeros((9, 0), np.float32), one, t0, ev.tracks_of(3)]
+    batch = pack_events(lists)
+    say("edge batch")
+    out = run(eng8, batch)
+    w = weights()
+    refs = [oracle.run_event(t, w) for t in lists]
+    geo = geometry(eng8)
+    for e in range(4):
+        assert parity.max_rel(out["prob"][e], refs[e]["p"]) <= parity.P_REL, e
+        bins, z, h, S = event_vertices(out, e)
+        parity.compare_peaks(bins, z, h, S, refs[e], geo)
+    assert out["status"][0] == 0 and out["status"][1] == 0 and out["status"][3] == 0
+    assert out["status"][2] == pv.EV_TRACKS_DROPPED
+    # over the cap: bypassed, neighbours unchanged
+    big = make_engine(4, max_tracks_per_event=50)
+    res = run(big, batch)
+    assert res["status"][2] & pv.EV_TOO_MANY_TRACKS and res["n_vertices"][2] == 0
+    assert res["status"][3] & pv.EV_TOO_MANY_TRACKS
+    assert res["status"][0] == 0 and np.array_equal(res["prob"][0], out["prob"][0])
+    assert np.array_equal(res["prob"][1], out["prob"][1])
+    # decreasing offsets: bypass that event only
+    feat, off = pv.upload_events(batch)
+    bad = off.clone()
+    bad[2] = bad[1] - 1                  # event 1 ends before it starts
+    o = big.alloc_outputs(4)
+    big.execute(feat, bad, o)
+    big.synchronize()
+    h = o.to_host()
+    assert h["status"][1] & pv.EV_BAD_INPUT and h["n_vertices"][1] == 0
+    assert np.array_equal(h["prob"][0], out["prob"][0]) and h["status"][0] == 0
+    big.close()
+
+
+def test_peak_truncation():
+    import paper_2602_19959_amd as pv
+    torch_cuda()
+    e = make_engine(2, max_peaks_per_event=10)
+    batch = make_events(2, seed=0)
+    out = run(e, batch)
+    w = weights()
+    ref = oracle.run_event(batch.tracks_of(0), w)
+    assert out["n_vertices"][0] == 10 and out["status"][0] & pv.EV_PEAKS_TRUNCATED
+    assert np.array_equal(out["bin"][0, :10], ref["t"][:10])
+    e.close()
+
+
+def test_empty_batch(eng8):
+    torch = torch_cuda()
+    import paper_2602_19959_amd as pv
+    feat = torch.zeros(9, 0, dtype=torch.float32, device="cuda")
+    off = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = eng8.alloc_outputs(0)
+    eng8.execute(feat, off, out)
+    eng8.synchronize()
+
+
+def test_capacity_errors(eng8, batch8):
+    import paper_2602_19959_amd as pv
+    torch = torch_cuda()
+    big = make_events(9, seed=1)
+    feat, off = pv.upload_events(big)
+    with pytest.raises(pv.PvfError) as ei:
+        eng8.execute(feat, off, eng8.alloc_outputs(9))
+    assert ei.value.status == 3
