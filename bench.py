@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--dtype", default="fp32", choices=["fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in tile shapes instead of timing the variants first")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
 
@@ -124,6 +126,11 @@ def main():
     feat, off = pv.upload_events(batch)
     out = eng.alloc_outputs(E, with_prob=False)
     names = eng.launch_names()
+    if not args.no_autotune:
+        t_tune = time.perf_counter()
+        picked = eng.autotune(feat, off, eng.alloc_outputs(E, with_prob=False), reps=2)
+        print(f"[bench] autotuned in {time.perf_counter() - t_tune:.1f} s: "
+              + ", ".join(f"{n}={v}" for n, v in zip(names, picked) if v >= 0), file=sys.stderr, flush=True)
     kernels = eng.launch_kernels()
     print(f"[bench] E={E} mix={args.mix} tracks={int(T.sum())} arena={eng.arena_bytes / 1e9:.2f} GB "
           f"launches={len(names)}", file=sys.stderr, flush=True)
@@ -212,6 +219,7 @@ def main():
         "p99_us_per_event": p99,
         "stages_ms": stage,
         "unet_tflops": unet_flops / (stage["unet"] / 1e3) / 1e12,
+        "variants": dict((n, v) for n, v in zip(names, eng.variants()) if v >= 0),
         "roofline": {"bound": "mfma", "kernel": dom_name, "layers": dom["layers"],
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": traffic, "flops_per_launch": flops_per_launch,

@@ -180,6 +180,23 @@ const char *pvf_launch_name(const pvf_engine *eng, int i);
  * range.  Static storage for the engine's life. */
 const char *pvf_launch_kernel(const pvf_engine *eng, int i);
 
+/* Tile-shape variants (Section 5 of the paper: launch-geometry tuning).
+ * A UNet convolution launch can run any of several tile shapes; every
+ * shape accumulates each output in the same order, so the choice changes
+ * speed only, never a bit of the results.  Launches without variants report
+ * a count of 0 and variant -1. */
+int pvf_launch_variant_count(const pvf_engine *eng, int i);
+int pvf_launch_variant(const pvf_engine *eng, int i);
+/* PVF_ERR_INVALID_ARGUMENT if launch i has no variants or v does not fit
+ * its shape. */
+pvf_status pvf_set_launch_variant(pvf_engine *eng, int i, int v);
+
+/* Autotuner: runs the batch `tracks` (reps + 1 times per variant) on the
+ * engine's stream, timing every launch with HIP events, and keeps the
+ * fastest variant of each convolution launch.  A set-up call: it
+ * synchronises the stream and overwrites `out`.  Not for the hot path. */
+pvf_status pvf_autotune(pvf_engine *eng, const pvf_tracks *tracks, const pvf_vertices *out, int reps);
+
 /* on != 0: create one HIP event per launch boundary now, and from then on
  * record them around every launch that pvf_execute enqueues.  on == 0:
  * stop recording and destroy them.  Recording adds no synchronisation. */

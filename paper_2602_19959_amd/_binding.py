@@ -110,6 +110,14 @@ def load_library() -> C.CDLL:
     lib.pvf_launch_name.restype = C.c_char_p
     lib.pvf_launch_kernel.argtypes = [vp, C.c_int]
     lib.pvf_launch_kernel.restype = C.c_char_p
+    lib.pvf_launch_variant_count.argtypes = [vp, C.c_int]
+    lib.pvf_launch_variant_count.restype = C.c_int
+    lib.pvf_launch_variant.argtypes = [vp, C.c_int]
+    lib.pvf_launch_variant.restype = C.c_int
+    lib.pvf_set_launch_variant.argtypes = [vp, C.c_int, C.c_int]
+    lib.pvf_set_launch_variant.restype = C.c_int
+    lib.pvf_autotune.argtypes = [vp, C.POINTER(Tracks), C.POINTER(Vertices), C.c_int]
+    lib.pvf_autotune.restype = C.c_int
     lib.pvf_profile_enable.argtypes = [vp, C.c_int]
     lib.pvf_profile_enable.restype = C.c_int
     lib.pvf_profile_read.argtypes = [vp, C.POINTER(C.c_float), C.c_int]
@@ -270,6 +278,28 @@ class Engine:
     def launch_kernels(self) -> list:
         n = self.lib.pvf_launch_count(self.handle)
         return [self.lib.pvf_launch_kernel(self.handle, i).decode() for i in range(n)]
+
+    def variants(self) -> list:
+        """Current variant of each launch (-1 for launches without variants)."""
+        n = self.lib.pvf_launch_count(self.handle)
+        return [self.lib.pvf_launch_variant(self.handle, i) for i in range(n)]
+
+    def variant_count(self, i: int) -> int:
+        return self.lib.pvf_launch_variant_count(self.handle, i)
+
+    def set_variant(self, i: int, v: int) -> bool:
+        """Select variant v for launch i; False if it does not fit that launch."""
+        return self.lib.pvf_set_launch_variant(self.handle, i, v) == PVF_OK
+
+    def autotune(self, feat, offsets, out: Outputs | None = None, reps: int = 2) -> list:
+        """Time every variant on this batch and keep the fastest per launch."""
+        t = self._torch
+        if out is None:
+            out = self.alloc_outputs(offsets.shape[0] - 1)
+        tr, v = self._views(feat, offsets, out)
+        self.stream.wait_stream(t.cuda.current_stream(self.device))
+        _check("pvf_autotune", self.lib.pvf_autotune(self.handle, C.byref(tr), C.byref(v), reps))
+        return self.variants()
 
     def profile(self, on: bool = True):
         _check("pvf_profile_enable", self.lib.pvf_profile_enable(self.handle, 1 if on else 0))

@@ -38,7 +38,7 @@ constexpr int KPAD = KC + 4;   // LDS pitch in floats (80 B): 8 consecutive rows
 
 __device__ __forceinline__ float lrelu(float x, float s) { return x >= 0.f ? x : s * x; }
 
-template <int WM, int WN, int TMW, int TNW, int TAPS, int EPI>
+template <int WM, int WN, int TMW, int TNW, int PF, int TAPS, int EPI>
 __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32(ConvArgs a)
 {
     constexpr int NT = WM * WN * 64;
@@ -46,6 +46,10 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32(ConvArgs a)
     constexpr int BN = WN * TNW * 16;
     constexpr int RAD = (TAPS - 1) / 2;
     constexpr int XROWS = BM + TAPS - 1;
+    constexpr int XV = XROWS * (KC / 4);          // float4 per stage of the halo tile
+    constexpr int WV = BN * TAPS * (KC / 4);      // float4 per stage of the weight tile
+    constexpr int XPT = (XV + NT - 1) / NT;
+    constexpr int WPT = (WV + NT - 1) / NT;
 
     __shared__ float xs[XROWS * KPAD];
     __shared__ float ws[BN * TAPS * KPAD];
@@ -68,25 +72,61 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32(ConvArgs a)
 #pragma unroll
         for (int j = 0; j < TNW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // PF = 1: software pipeline, the next chunk's tiles are fetched into
+    // registers while the current chunk's MFMAs run from LDS.  PF = 0: fetch,
+    // stage and compute in turn (fewer registers, more blocks per CU).
+    f32x4 xr[XPT], wr[WPT];
+    auto fetch = [&](int c0) {
+#pragma unroll
+        for (int u = 0; u < XPT; ++u) {
+            const int idx = tid + u * NT;
+            xr[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (idx < XV) {
+                const int row = idx / (KC / 4), q = idx % (KC / 4);
+                const int64_t g = m0 - RAD + row;
+                if (g >= 0 && g < a.m_rows)
+                    xr[u] = *reinterpret_cast<const f32x4*>(a.in + g * a.ld_in + c0 + 4 * q);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) {
+            const int idx = tid + u * NT;
+            wr[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (idx < WV) {
+                const int q = idx % (KC / 4);
+                const int rest = idx / (KC / 4);
+                const int tap = rest % TAPS, nn = rest / TAPS;
+                if (n0 + nn < a.n)
+                    wr[u] = *reinterpret_cast<const f32x4*>(a.w + (int64_t)(n0 + nn) * kw + tap * a.cin + c0 + 4 * q);
+            }
+        }
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int u = 0; u < XPT; ++u) {
+            const int idx = tid + u * NT;
+            if (idx < XV) {
+                const int row = idx / (KC / 4), q = idx % (KC / 4);
+                *reinterpret_cast<f32x4*>(xs + row * KPAD + 4 * q) = xr[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) {
+            const int idx = tid + u * NT;
+            if (idx < WV) {
+                const int q = idx % (KC / 4);
+                const int rest = idx / (KC / 4);
+                *reinterpret_cast<f32x4*>(ws + rest * KPAD + 4 * q) = wr[u];
+            }
+        }
+    };
+
+    fetch(0);
+    stage();
+    __syncthreads();
     for (int c0 = 0; c0 < a.cin; c0 += KC) {
-        for (int idx = tid; idx < XROWS * (KC / 4); idx += NT) {
-            const int row = idx / (KC / 4), q = idx % (KC / 4);
-            const int64_t g = m0 - RAD + row;
-            f32x4 v = {0.f, 0.f, 0.f, 0.f};
-            if (g >= 0 && g < a.m_rows)
-                v = *reinterpret_cast<const f32x4*>(a.in + g * a.ld_in + c0 + 4 * q);
-            *reinterpret_cast<f32x4*>(xs + row * KPAD + 4 * q) = v;
-        }
-        for (int idx = tid; idx < BN * TAPS * (KC / 4); idx += NT) {
-            const int q = idx % (KC / 4);
-            const int rest = idx / (KC / 4);
-            const int tap = rest % TAPS, nn = rest / TAPS;
-            f32x4 v = {0.f, 0.f, 0.f, 0.f};
-            if (n0 + nn < a.n)
-                v = *reinterpret_cast<const f32x4*>(a.w + (int64_t)(n0 + nn) * kw + tap * a.cin + c0 + 4 * q);
-            *reinterpret_cast<f32x4*>(ws + (nn * TAPS + tap) * KPAD + 4 * q) = v;
-        }
-        __syncthreads();
+        const bool more = c0 + KC < a.cin;
+        if (PF && more) fetch(c0 + KC);
 #pragma unroll
         for (int tap = 0; tap < TAPS; ++tap) {
             f32x4 av[TMW], bv[TNW];
@@ -105,6 +145,11 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32(ConvArgs a)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][s], bv[j][s], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
+        if (more) {
+            if (!PF) fetch(c0 + KC);
+            stage();
+            __syncthreads();
+        }
     }
 
     // Output D layout of the 16x16 MFMA: lane holds rows 4*lg + v (v = 0..3)
@@ -198,60 +243,104 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32(ConvArgs a)
     }
 }
 
-template <int WM, int WN, int TMW, int TNW, int TAPS, int EPI>
+template <int WM, int WN, int TMW, int TNW, int PF, int TAPS, int EPI>
 hipError_t run(const ConvArgs& a, hipStream_t s)
 {
     constexpr int BM = WM * TMW * 16;
     constexpr int BN = WN * TNW * 16;
     dim3 grid((unsigned)((a.m_rows + BM - 1) / BM), (unsigned)((a.n + BN - 1) / BN));
-    hipLaunchKernelGGL((conv_mfma_f32<WM, WN, TMW, TNW, TAPS, EPI>), grid, dim3(WM * WN * 64), 0, s, a);
+    hipLaunchKernelGGL((conv_mfma_f32<WM, WN, TMW, TNW, PF, TAPS, EPI>), grid, dim3(WM * WN * 64), 0, s, a);
     return hipGetLastError();
 }
 
-// Tile shape per GEMM width: (waves in M, waves in N, 16x16 tiles per wave in
-// M, in N).  Every block covers 256 rows; one wave holds a 64 x (16*TNW) tile.
-struct Shape { int wm, wn, tmw, tnw; };
+// Tile-shape variants.  Every variant accumulates each output's k terms in
+// the same order (16-channel chunk, tap, MFMA step), so all of them give
+// bitwise-identical results; they differ only in speed.
+struct Variant { int wm, wn, tmw, tnw, pf; };
+constexpr Variant kVariants[] = {
+    {4, 1, 4, 2, 0}, {4, 1, 4, 2, 1}, {2, 1, 4, 2, 0},
+    {4, 1, 4, 4, 0}, {4, 1, 4, 4, 1}, {4, 1, 2, 4, 0},
+    {2, 2, 4, 4, 0}, {2, 2, 4, 4, 1}, {4, 2, 4, 4, 0}, {4, 2, 4, 4, 1},
+    {2, 4, 4, 4, 0},
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-Shape shape_for(int n, Epi epi)
-{
-    if (epi == EPI_HEAD || n <= 32) return {4, 1, 4, 2};
-    if (n <= 64) return {4, 1, 4, 4};
-    return {4, 2, 4, 4};
-}
+#define PVF_VARIANT_CASE(V, TAPS, EPI)                                                                  \
+    case V:                                                                                             \
+        return run<kVariants[V].wm, kVariants[V].wn, kVariants[V].tmw, kVariants[V].tnw, kVariants[V].pf, \
+                   TAPS, EPI>(a, s);
 
 template <int TAPS, int EPI>
-hipError_t by_width(const ConvArgs& a, hipStream_t s)
+hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
 {
-    const Shape sh = shape_for(a.n, (Epi)EPI);
-    if (sh.wn == 1 && sh.tnw == 2) return run<4, 1, 4, 2, TAPS, EPI>(a, s);
-    if (sh.wn == 1 && sh.tnw == 4) return run<4, 1, 4, 4, TAPS, EPI>(a, s);
-    return run<4, 2, 4, 4, TAPS, EPI>(a, s);
+    if constexpr (EPI == EPI_HEAD) {
+        switch (v) {
+            PVF_VARIANT_CASE(0, TAPS, EPI)
+            PVF_VARIANT_CASE(1, TAPS, EPI)
+            PVF_VARIANT_CASE(2, TAPS, EPI)
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (v) {
+            PVF_VARIANT_CASE(0, TAPS, EPI)
+            PVF_VARIANT_CASE(1, TAPS, EPI)
+            PVF_VARIANT_CASE(2, TAPS, EPI)
+            PVF_VARIANT_CASE(3, TAPS, EPI)
+            PVF_VARIANT_CASE(4, TAPS, EPI)
+            PVF_VARIANT_CASE(5, TAPS, EPI)
+            PVF_VARIANT_CASE(6, TAPS, EPI)
+            PVF_VARIANT_CASE(7, TAPS, EPI)
+            PVF_VARIANT_CASE(8, TAPS, EPI)
+            PVF_VARIANT_CASE(9, TAPS, EPI)
+            PVF_VARIANT_CASE(10, TAPS, EPI)
+        default: return hipErrorInvalidValue;
+        }
+    }
 }
 
 }  // namespace
 
-std::string conv_kernel_name(int n, int taps, Epi epi)
+int conv_variant_count() { return kNumVariants; }
+
+bool conv_variant_ok(int v, int n, int taps, Epi epi)
 {
-    const Shape sh = shape_for(n, epi);
-    return "conv_mfma_f32<" + std::to_string(sh.wm) + ", " + std::to_string(sh.wn) + ", " +
-           std::to_string(sh.tmw) + ", " + std::to_string(sh.tnw) + ", " + std::to_string(taps) + ", " +
+    if (v < 0 || v >= kNumVariants) return false;
+    const Variant& x = kVariants[v];
+    const int bn = x.wn * x.tnw * 16;
+    if (epi == EPI_HEAD) return v <= 2 && bn == n && x.wn == 1;
+    (void)taps;
+    return bn <= (n < 32 ? 32 : n);
+}
+
+// Defaults from a sweep on MI355X at 1000 events: the 256 x 32 tile with the
+// fewest registers (most blocks per CU) wins every 5-tap layer; the
+// transposed convs prefer wider N tiles.
+int conv_default_variant(int n, int taps, Epi epi)
+{
+    if (epi == EPI_CONVT && taps == 1) return n >= 128 ? 9 : (n >= 64 ? 5 : 0);
+    return 0;
+}
+
+std::string conv_kernel_name(int v, int taps, Epi epi)
+{
+    const Variant& x = kVariants[v];
+    return "conv_mfma_f32<" + std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " + std::to_string(x.tmw) +
+           ", " + std::to_string(x.tnw) + ", " + std::to_string(x.pf) + ", " + std::to_string(taps) + ", " +
            std::to_string((int)epi) + ">";
 }
 
-hipError_t launch_conv(const ConvArgs& a, int taps, Epi epi, hipStream_t s)
+hipError_t launch_conv(const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s)
 {
-    if (a.cin % KC != 0 || a.m_rows <= 0) return hipErrorInvalidValue;
+    if (a.cin % KC != 0 || a.m_rows <= 0 || !conv_variant_ok(variant, a.n, taps, epi)) return hipErrorInvalidValue;
     if (taps == 5) {
         switch (epi) {
-        case EPI_STORE: return by_width<5, EPI_STORE>(a, s);
-        case EPI_POOL: return by_width<5, EPI_POOL>(a, s);
-        case EPI_HEAD:
-            if (a.n != 32) return hipErrorInvalidValue;
-            return by_width<5, EPI_HEAD>(a, s);
+        case EPI_STORE: return dispatch<5, EPI_STORE>(variant, a, s);
+        case EPI_POOL: return dispatch<5, EPI_POOL>(variant, a, s);
+        case EPI_HEAD: return dispatch<5, EPI_HEAD>(variant, a, s);
         default: return hipErrorInvalidValue;
         }
     }
-    if (taps == 1 && epi == EPI_CONVT) return by_width<1, EPI_CONVT>(a, s);
+    if (taps == 1 && epi == EPI_CONVT) return dispatch<1, EPI_CONVT>(variant, a, s);
     return hipErrorInvalidValue;
 }
 

@@ -294,6 +294,8 @@ struct pvf_engine {
     hipStream_t stream = nullptr;
     std::vector<std::string> names;      // one per launch of pvf_execute
     std::vector<std::string> kernels;    // kernel instance of each launch
+    struct ConvLaunch { int n = 0, taps = 0; Epi epi = EPI_STORE; int variant = -1; };
+    std::vector<ConvLaunch> conv;        // per launch; variant -1 = not a conv launch
     std::vector<hipEvent_t> events;      // launch boundaries when profiling
     bool profiling = false;
 };
@@ -307,27 +309,40 @@ void build_names(pvf_engine* e)
 {
     const int n = e->spec.n_levels;
     const int c0 = e->spec.base_channels;
-    auto add = [&](const std::string& name, const std::string& kernel) {
-        e->names.push_back(name);
-        e->kernels.push_back(kernel);
-    };
     e->names.clear();
     e->kernels.clear();
-    add("track", "track_stage");
+    e->conv.clear();
+    auto plain = [&](const std::string& name, const std::string& kernel) {
+        e->names.push_back(name);
+        e->kernels.push_back(kernel);
+        e->conv.push_back({});
+    };
+    auto conv = [&](const std::string& name, int gemm_n, int taps, Epi epi) {
+        pvf_engine::ConvLaunch c;
+        c.n = gemm_n;
+        c.taps = taps;
+        c.epi = epi;
+        c.variant = conv_default_variant(gemm_n, taps, epi);
+        e->names.push_back(name);
+        e->kernels.push_back(conv_kernel_name(c.variant, taps, epi));
+        e->conv.push_back(c);
+    };
+    plain("track", "track_stage");
     for (int l = 0; l < n; ++l) {
         const std::string L = std::to_string(l);
         const int C = c0 << l;
-        add("enc" + L + ".c1", l == 0 ? "first_conv" : conv_kernel_name(C, kTaps, EPI_STORE));
-        add("enc" + L + ".c2", conv_kernel_name(C, kTaps, l < n - 1 ? EPI_POOL : EPI_STORE));
+        if (l == 0) plain("enc0.c1", "first_conv");
+        else conv("enc" + L + ".c1", C, kTaps, EPI_STORE);
+        conv("enc" + L + ".c2", C, kTaps, l < n - 1 ? EPI_POOL : EPI_STORE);
     }
     for (int l = n - 2; l >= 0; --l) {
         const std::string L = std::to_string(l);
         const int C = c0 << l;
-        add("up" + L, conv_kernel_name(2 * C, 1, EPI_CONVT));
-        add("dec" + L + ".c1", conv_kernel_name(C, kTaps, EPI_STORE));
-        add(l == 0 ? "dec0.c2+head" : "dec" + L + ".c2", conv_kernel_name(C, kTaps, l == 0 ? EPI_HEAD : EPI_STORE));
+        conv("up" + L, 2 * C, 1, EPI_CONVT);
+        conv("dec" + L + ".c1", C, kTaps, EPI_STORE);
+        conv(l == 0 ? "dec0.c2+head" : "dec" + L + ".c2", C, kTaps, l == 0 ? EPI_HEAD : EPI_STORE);
     }
-    add("peaks", "peak_finder");
+    plain("peaks", "peak_finder");
 }
 
 bool misaligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) != 0; }
@@ -362,17 +377,15 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
     const float* wbase = at<float>(eng, P.weights);
     float* prob = out->d_prob_hist ? out->d_prob_hist : at<float>(eng, P.prob);
     int32_t* flags = at<int32_t>(eng, P.flags);
-    int li = 0;
+    int li = 0;                       // index of the launch about to be enqueued
     hipError_t err = hipSuccess;
-    auto mark = [&]() {
-        if (eng->profiling && err == hipSuccess) err = hipEventRecord(eng->events[li], s);
+    if (eng->profiling) err = hipEventRecord(eng->events[0], s);
+    auto check = [&](hipError_t e) {
+        if (err == hipSuccess) err = e;
+        if (eng->profiling && err == hipSuccess) err = hipEventRecord(eng->events[li + 1], s);
         ++li;
     };
-    auto check = [&](hipError_t e) { if (err == hipSuccess) err = e; mark(); };
-
-    li = 0;
-    if (eng->profiling) err = hipEventRecord(eng->events[0], s);
-    li = 1;
+    auto var = [&]() { return eng->conv[li].variant; };
 
     // ---- FC stage: tracks -> scaled histogram rows of level 0
     TrackArgs ta{};
@@ -413,7 +426,7 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
             const Level& up = P.lv[l - 1];
             ConvArgs a = conv_args(eng, W.enc[l][0], at<float>(eng, P.pool[l]), up.C, lv.R, E,
                                    at<float>(eng, P.a[l]), lv.C);
-            check(launch_conv(a, kTaps, EPI_STORE, s));
+            check(launch_conv(a, kTaps, EPI_STORE, var(), s));
         }
         if (l < n - 1) {
             ConvArgs a = conv_args(eng, W.enc[l][1], at<float>(eng, P.a[l]), lv.C, lv.R, E,
@@ -421,11 +434,11 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
             a.pool_out = at<float>(eng, P.pool[l + 1]);
             a.ld_pool = lv.C;
             a.r_pool = P.lv[l + 1].R;
-            check(launch_conv(a, kTaps, EPI_POOL, s));
+            check(launch_conv(a, kTaps, EPI_POOL, var(), s));
         } else {
             ConvArgs a = conv_args(eng, W.enc[l][1], at<float>(eng, P.a[l]), lv.C, lv.R, E,
                                    at<float>(eng, P.d[l]), lv.C);
-            check(launch_conv(a, kTaps, EPI_STORE, s));
+            check(launch_conv(a, kTaps, EPI_STORE, var(), s));
         }
     }
     // ---- decoder
@@ -437,21 +450,21 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
         u.n = 2 * lv.C;
         u.cout = lv.C;
         u.r_out = lv.R;
-        check(launch_conv(u, 1, EPI_CONVT, s));
+        check(launch_conv(u, 1, EPI_CONVT, var(), s));
         ConvArgs a = conv_args(eng, W.dec[l][0], at<float>(eng, P.cat[l]), 2 * lv.C, lv.R, E,
                                at<float>(eng, P.a[l]), lv.C);
-        check(launch_conv(a, kTaps, EPI_STORE, s));
+        check(launch_conv(a, kTaps, EPI_STORE, var(), s));
         if (l > 0) {
             ConvArgs b = conv_args(eng, W.dec[l][1], at<float>(eng, P.a[l]), lv.C, lv.R, E,
                                    at<float>(eng, P.d[l]), lv.C);
-            check(launch_conv(b, kTaps, EPI_STORE, s));
+            check(launch_conv(b, kTaps, EPI_STORE, var(), s));
         } else {
             ConvArgs b = conv_args(eng, W.dec[0][1], at<float>(eng, P.a[0]), lv.C, lv.R, E, nullptr, 0);
             b.head_w = wbase + W.head_w;
             b.head_b = eng->head_b;
             b.prob = prob;
             b.l_out = lv.L;
-            check(launch_conv(b, kTaps, EPI_HEAD, s));
+            check(launch_conv(b, kTaps, EPI_HEAD, var(), s));
         }
     }
     // ---- peaks
@@ -628,6 +641,67 @@ const char* pvf_launch_kernel(const pvf_engine* eng, int i)
 {
     if (!eng || i < 0 || i >= (int)eng->kernels.size()) return nullptr;
     return eng->kernels[i].c_str();
+}
+
+int pvf_launch_variant_count(const pvf_engine* eng, int i)
+{
+    if (!eng || i < 0 || i >= (int)eng->conv.size() || eng->conv[i].variant < 0) return 0;
+    return conv_variant_count();
+}
+
+int pvf_launch_variant(const pvf_engine* eng, int i)
+{
+    if (!eng || i < 0 || i >= (int)eng->conv.size()) return -1;
+    return eng->conv[i].variant;
+}
+
+pvf_status pvf_set_launch_variant(pvf_engine* eng, int i, int v)
+{
+    if (!eng || i < 0 || i >= (int)eng->conv.size() || eng->conv[i].variant < 0) return PVF_ERR_INVALID_ARGUMENT;
+    auto& c = eng->conv[i];
+    if (!conv_variant_ok(v, c.n, c.taps, c.epi)) return PVF_ERR_INVALID_ARGUMENT;
+    c.variant = v;
+    eng->kernels[i] = conv_kernel_name(v, c.taps, c.epi);
+    return PVF_OK;
+}
+
+pvf_status pvf_autotune(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* out, int reps)
+{
+    pvf_status st = check_call(eng, tr, out);
+    if (st != PVF_OK) return st;
+    if (tr->n_events == 0 || reps < 1) return PVF_ERR_INVALID_ARGUMENT;
+    const bool was = eng->profiling;
+    if (!was && (st = pvf_profile_enable(eng, 1)) != PVF_OK) return st;
+    const int nl = (int)eng->names.size();
+    std::vector<float> best(nl, 1e30f), ms(nl);
+    std::vector<int> pick(nl, -1);
+    for (int i = 0; i < nl; ++i) pick[i] = eng->conv[i].variant;
+    const std::vector<pvf_engine::ConvLaunch> saved = eng->conv;
+    for (int v = 0; v < conv_variant_count() && st == PVF_OK; ++v) {
+        // try variant v on every conv launch that accepts it, all in one pass
+        bool any = false;
+        for (int i = 0; i < nl; ++i) {
+            auto& c = eng->conv[i];
+            if (c.variant < 0) continue;
+            if (conv_variant_ok(v, c.n, c.taps, c.epi)) { c.variant = v; any = true; }
+            else c.variant = saved[i].variant;
+        }
+        if (!any) continue;
+        for (int r = 0; r < reps + 1 && st == PVF_OK; ++r) {       // first pass warms up
+            st = enqueue(eng, tr, out, eng->stream);
+            if (st == PVF_OK && hipStreamSynchronize(eng->stream) != hipSuccess) st = PVF_ERR_DEVICE;
+            if (st == PVF_OK && r > 0) st = pvf_profile_read(eng, ms.data(), nl);
+            if (st != PVF_OK || r == 0) continue;
+            for (int i = 0; i < nl; ++i)
+                if (eng->conv[i].variant == v && ms[i] < best[i]) { best[i] = ms[i]; pick[i] = v; }
+        }
+    }
+    for (int i = 0; i < nl; ++i) {
+        eng->conv[i] = saved[i];
+        if (saved[i].variant >= 0 && st == PVF_OK) pvf_set_launch_variant(eng, i, pick[i]);
+    }
+    if (!was) pvf_profile_enable(eng, 0);
+    return st;
 }
 
 pvf_status pvf_profile_enable(pvf_engine* eng, int on)

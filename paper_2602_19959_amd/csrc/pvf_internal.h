@@ -141,8 +141,12 @@ struct GatherArgs {          // debug copy of an internal activation
 
 hipError_t launch_track(const TrackArgs& a, int n_events, hipStream_t s);
 hipError_t launch_first_conv(const FirstConvArgs& a, hipStream_t s);
-hipError_t launch_conv(const ConvArgs& a, int taps, Epi epi, hipStream_t s);
-std::string conv_kernel_name(int n, int taps, Epi epi);   // instance launch_conv picks
+// Conv launches run one of several tile-shape variants; all give identical bits.
+hipError_t launch_conv(const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s);
+int conv_variant_count();
+bool conv_variant_ok(int variant, int n, int taps, Epi epi);
+int conv_default_variant(int n, int taps, Epi epi);
+std::string conv_kernel_name(int variant, int taps, Epi epi);
 hipError_t launch_peaks(const PeakArgs& a, int n_events, hipStream_t s);
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
 

@@ -192,3 +192,34 @@ def test_capacity_errors(eng8, batch8):
     with pytest.raises(pv.PvfError) as ei:
         eng8.execute(feat, off, eng8.alloc_outputs(9))
     assert ei.value.status == 3
+
+
+def test_every_variant_gives_identical_bits(eng8, batch8, out8):
+    """Tile-shape variants only change speed: each one reproduces the
+    default configuration's outputs bit for bit, and the autotuner's pick
+    does too."""
+    base = eng8.variants()
+    n = len(base)
+    tried = 0
+    for v in range(eng8.variant_count(2)):
+        changed = [i for i in range(n) if base[i] >= 0 and eng8.set_variant(i, v)]
+        if not changed:
+            continue
+        tried += 1
+        say(f"variant {v} on launches {changed}")
+        got = run(eng8, batch8)
+        for k in ("prob", "z", "integral", "n_vertices", "bin"):
+            assert np.array_equal(got[k], out8[k]), (v, k)
+        for i in range(n):
+            if base[i] >= 0:
+                eng8.set_variant(i, base[i])
+    assert tried >= 8
+    import paper_2602_19959_amd as pv
+    feat, off = pv.upload_events(batch8)
+    picked = eng8.autotune(feat, off, reps=1)
+    say("autotuned variants", picked)
+    got = run(eng8, batch8)
+    assert np.array_equal(got["prob"], out8["prob"])
+    for i in range(n):
+        if base[i] >= 0:
+            eng8.set_variant(i, base[i])
