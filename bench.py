@@ -29,7 +29,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "events/sec on 1 MI355X (FP32 vs BF16/FP8 at stated tol); p99 µs/event"
-PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2516.6, "fp16": 2516.6, "fp8_e4m3": 5033.2}
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "fp8_e4m3": 5000.0}
+DTYPE_TAG = {"fp32": "f32", "bf16": "bf16", "fp16": "f16", "fp8_e4m3": "fp8_e4m3"}
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -51,6 +52,27 @@ def layer_macs(spec, n_hidden=6, hidden=20, n_feat=9):
         key = "dec0.c2+head" if l == 0 else f"dec{l}.c2"
         out[key] = L * C * C * 5 + (L * C if l == 0 else 0)
     out["peaks"] = 0
+    return out
+
+
+def layer_bytes(spec, eb):
+    """Algorithmic HBM bytes per event of each launch: every input activation
+    read once, every output written once (eb bytes per element, the compute
+    dtype; the histogram and the probability are FP32).  The track stage's
+    figure is per track for its input (36 B) plus the histogram write."""
+    n, c0, L0 = spec.n_levels, spec.base_channels, spec.n_bins
+    out = {"track": None, "enc0.c1": L0 * 4 + L0 * c0 * eb}
+    for l in range(n):
+        L, C = L0 >> l, c0 << l
+        if l > 0:
+            out[f"enc{l}.c1"] = L * (c0 << (l - 1)) * eb + L * C * eb
+        out[f"enc{l}.c2"] = L * C * eb + L * C * eb + ((L // 2) * C * eb if l < n - 1 else 0)
+    for l in range(n - 2, -1, -1):
+        L, C = L0 >> l, c0 << l
+        out[f"up{l}"] = (L // 2) * (2 * C) * eb + L * C * eb
+        out[f"dec{l}.c1"] = L * 2 * C * eb + L * C * eb
+        out["dec0.c2+head" if l == 0 else f"dec{l}.c2"] = L * C * eb + (L * 4 if l == 0 else L * C * eb)
+    out["peaks"] = L0 * 4
     return out
 
 
@@ -95,7 +117,7 @@ def main():
     ap.add_argument("--events", type=int, default=1000)
     ap.add_argument("--mix", default="poisson", choices=["poisson", "lognormal"])
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--dtype", default="fp32", choices=["fp32"])
+    ap.add_argument("--dtype", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in tile shapes instead of timing the variants first")
@@ -184,11 +206,20 @@ def main():
     dom_name, dom = max(by_kernel.items(), key=lambda kv: kv[1]["ms"])
     avg_dur_s = dom["ms"] / dom["launches"] / 1e3
     flops_per_launch = dom["flops"] / dom["launches"]
-    achieved = flops_per_launch / avg_dur_s / 1e12
+    eb = 4 if args.dtype == "fp32" else 2
+    lbytes = layer_bytes(spec, eb)
+    lbytes["track"] = (36.0 * valid_tracks + E * spec.n_bins * 4) / E
+    bytes_per_launch = sum(lbytes[n] * E for n in dom["layers"]) / dom["launches"]
     peak = PEAK_TFLOPS[args.dtype]
+    ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)          # flop per byte
+    intensity = flops_per_launch / bytes_per_launch
+    if intensity >= ridge:
+        bound, achieved, peak_v, unit = "mfma", flops_per_launch / avg_dur_s / 1e12, peak, "TFLOP/s"
+    else:
+        bound, achieved, peak_v, unit = "hbm", bytes_per_launch / avg_dur_s / 1e9, HBM_PEAK_GBS, "GB/s"
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
-        tr = json.load(open(TRAFFIC_FILE)).get(f"{dom_name}|E={E}|{args.dtype}")
+        tr = json.load(open(TRAFFIC_FILE)).get(f"{dom_name}|E={E}")
         if tr:
             traffic = tr.get("bytes_per_launch")
 
@@ -210,20 +241,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": DTYPE_TAG[args.dtype],
         "data": "synthetic: seeded events (Poisson(5.6) PVs, Poisson(180) tracks) and seeded He-init weights",
         "config": {"workload": f"{E} events per batch, {args.mix} track counts (mean {T.mean():.1f}), "
-                               f"UNet 32/64/128/256 over 4000 bins, FP32, seed {args.seed}",
+                               f"UNet 32/64/128/256 over 4000 bins, {args.dtype.upper()} convolutions (FP32 accumulate), seed {args.seed}",
                    "events_per_batch": E, "tracks_total": int(T.sum())},
         "p50_us_per_event": p50,
         "p99_us_per_event": p99,
         "stages_ms": stage,
         "unet_tflops": unet_flops / (stage["unet"] / 1e3) / 1e12,
         "variants": dict((n, v) for n, v in zip(names, eng.variants()) if v >= 0),
-        "roofline": {"bound": "mfma", "kernel": dom_name, "layers": dom["layers"],
-                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+        "roofline": {"bound": bound, "kernel": dom_name, "layers": dom["layers"],
+                     "achieved": achieved, "peak": peak_v, "unit": unit, "frac": achieved / peak_v,
                      "traffic": traffic, "flops_per_launch": flops_per_launch,
-                     "avg_launch_ms": avg_dur_s * 1e3},
+                     "algorithmic_bytes_per_launch": bytes_per_launch, "intensity_flop_per_byte": intensity,
+                     "ridge_flop_per_byte": ridge, "avg_launch_ms": avg_dur_s * 1e3},
     }
     if not args.no_cpu_baseline:
         print("[bench] CPU baseline (FP64 oracle)...", file=sys.stderr, flush=True)

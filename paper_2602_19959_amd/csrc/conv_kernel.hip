@@ -65,6 +65,10 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32(ConvArgs a)
     const int64_t m0 = (int64_t)blockIdx.x * BM;
     const int n0 = blockIdx.y * BN;
     const int kw = TAPS * a.cin;
+    const float* in = static_cast<const float*>(a.in);
+    const float* wt = static_cast<const float*>(a.w);
+    float* out = static_cast<float*>(a.out);
+    float* pout = static_cast<float*>(a.pool_out);
 
     f32x4 acc[TMW][TNW];
 #pragma unroll
@@ -85,7 +89,7 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32(ConvArgs a)
                 const int row = idx / (KC / 4), q = idx % (KC / 4);
                 const int64_t g = m0 - RAD + row;
                 if (g >= 0 && g < a.m_rows)
-                    xr[u] = *reinterpret_cast<const f32x4*>(a.in + g * a.ld_in + c0 + 4 * q);
+                    xr[u] = *reinterpret_cast<const f32x4*>(in + g * a.ld_in + c0 + 4 * q);
             }
         }
 #pragma unroll
@@ -97,7 +101,7 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32(ConvArgs a)
                 const int rest = idx / (KC / 4);
                 const int tap = rest % TAPS, nn = rest / TAPS;
                 if (n0 + nn < a.n)
-                    wr[u] = *reinterpret_cast<const f32x4*>(a.w + (int64_t)(n0 + nn) * kw + tap * a.cin + c0 + 4 * q);
+                    wr[u] = *reinterpret_cast<const f32x4*>(wt + (int64_t)(n0 + nn) * kw + tap * a.cin + c0 + 4 * q);
             }
         }
     };
@@ -205,7 +209,7 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32(ConvArgs a)
                     const int loc = (int)(r - e * a.r_in);
                     if (loc < kGuard || loc >= a.r_in - kGuard) continue;
                     const int64_t ro = e * a.r_out + kGuard + 2 * (loc - kGuard) + tj;
-                    a.out[ro * a.ld_out + o] = acc[i][j][v] + b;
+                    out[ro * a.ld_out + o] = acc[i][j][v] + b;
                 }
         } else {
             const float b = a.bias[col];
@@ -222,7 +226,7 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32(ConvArgs a)
                     const int64_t e = r / a.r_in;
                     const int loc = (int)(r - e * a.r_in);
                     if (loc < kGuard || loc >= a.r_in - kGuard) continue;
-                    a.out[r * a.ld_out + col] = y[v];
+                    out[r * a.ld_out + col] = y[v];
                 }
                 if constexpr (EPI == EPI_POOL) {
                     // rows per event and the guard are even, so an even row is
@@ -235,7 +239,7 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32(ConvArgs a)
                         const int loc = (int)(r - e * a.r_in);
                         if (loc < kGuard || loc >= a.r_in - kGuard) continue;
                         const int64_t rp = e * a.r_pool + kGuard + (loc - kGuard) / 2;
-                        a.pool_out[rp * a.ld_pool + col] = fmaxf(y[2 * p], y[2 * p + 1]);
+                        pout[rp * a.ld_pool + col] = fmaxf(y[2 * p], y[2 * p + 1]);
                     }
                 }
             }
@@ -300,9 +304,9 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
 
 }  // namespace
 
-int conv_variant_count() { return kNumVariants; }
+int f32_variant_count() { return kNumVariants; }
 
-bool conv_variant_ok(int v, int n, int taps, Epi epi)
+bool f32_variant_ok(int v, int n, int taps, Epi epi)
 {
     if (v < 0 || v >= kNumVariants) return false;
     const Variant& x = kVariants[v];
@@ -315,13 +319,13 @@ bool conv_variant_ok(int v, int n, int taps, Epi epi)
 // Defaults from a sweep on MI355X at 1000 events: the 256 x 32 tile with the
 // fewest registers (most blocks per CU) wins every 5-tap layer; the
 // transposed convs prefer wider N tiles.
-int conv_default_variant(int n, int taps, Epi epi)
+int f32_default_variant(int n, int taps, Epi epi)
 {
     if (epi == EPI_CONVT && taps == 1) return n >= 128 ? 9 : (n >= 64 ? 5 : 0);
     return 0;
 }
 
-std::string conv_kernel_name(int v, int taps, Epi epi)
+std::string f32_kernel_name(int v, int taps, Epi epi)
 {
     const Variant& x = kVariants[v];
     return "conv_mfma_f32<" + std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " + std::to_string(x.tmw) +
@@ -329,9 +333,9 @@ std::string conv_kernel_name(int v, int taps, Epi epi)
            std::to_string((int)epi) + ">";
 }
 
-hipError_t launch_conv(const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s)
+hipError_t launch_conv_f32(const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s)
 {
-    if (a.cin % KC != 0 || a.m_rows <= 0 || !conv_variant_ok(variant, a.n, taps, epi)) return hipErrorInvalidValue;
+    if (a.cin % KC != 0 || a.m_rows <= 0 || !f32_variant_ok(variant, a.n, taps, epi)) return hipErrorInvalidValue;
     if (taps == 5) {
         switch (epi) {
         case EPI_STORE: return dispatch<5, EPI_STORE>(variant, a, s);

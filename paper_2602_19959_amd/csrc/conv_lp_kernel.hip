@@ -1,0 +1,309 @@
+// UNet convolutions as implicit GEMM on the matrix cores in BF16 or FP16,
+// accumulated in FP32 (mixed-precision inference, Section 5 of
+// arXiv:2602.19959: FP16 on the matrix units).
+//
+// Same GEMM view as the FP32 kernel (m = event row, n = output channel,
+// k = (tap, input channel)), with 16-bit activations and weights:
+//   * one stage = 32 input channels: the (BM + 4) x 32 halo tile and the
+//     BN x 5 x 32 weight tile go to LDS once and all five taps read them;
+//   * v_mfma_f32_16x16x32_{bf16,f16}: each lane feeds 8 consecutive
+//     channels of its row (A) and of its column (B) with one 16-byte LDS
+//     read; A and B use the same lane-to-k map, so the MFMA sums the whole
+//     32-channel step;
+//   * the k order (stage, tap, MFMA) is fixed by the kernel alone, so every
+//     tile-shape variant gives the same bits and results do not depend on
+//     the batch;
+//   * epilogue: bias (+ LeakyReLU) in FP32, one rounding to 16 bits, then
+//     the tile is staged in LDS and written back as whole 16-byte row chunks
+//     (channels-last rows are contiguous), with the fused max-pool or the
+//     transposed-conv row interleave; the head epilogue works on the FP32
+//     accumulators and writes the FP32 probability.
+#include "pvf_internal.h"
+
+namespace pvf {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+template <class T> struct Lp;
+template <> struct Lp<__bf16> {
+    using vec8 = bf16x8;
+    __device__ static f32x4 mfma(vec8 a, vec8 b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+};
+template <> struct Lp<_Float16> {
+    using vec8 = f16x8;
+    __device__ static f32x4 mfma(vec8 a, vec8 b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+};
+
+constexpr int KC = 32;        // input channels per stage (one MFMA k step per tap)
+constexpr int KP = KC + 8;    // LDS pitch in elements: 80 B, 8 consecutive rows'
+                              // 16-byte reads land on distinct bank groups
+
+__device__ __forceinline__ float lrelu(float x, float s) { return x >= 0.f ? x : s * x; }
+
+template <int A, int B> struct Max { static constexpr int v = A > B ? A : B; };
+
+template <class T, int WM, int WN, int TMW, int TNW, int TAPS, int EPI>
+__global__ __launch_bounds__(WM * WN * 64) void conv_mfma_lp(ConvArgs a)
+{
+    using V = typename Lp<T>::vec8;
+    constexpr int NT = WM * WN * 64;
+    constexpr int BM = WM * TMW * 16;
+    constexpr int BN = WN * TNW * 16;
+    constexpr int RAD = (TAPS - 1) / 2;
+    constexpr int XROWS = BM + TAPS - 1;
+    constexpr int XV = XROWS * (KC / 8);        // 16-byte chunks per stage
+    constexpr int WV = BN * TAPS * (KC / 8);
+    constexpr int OP = BN + 8;                  // epilogue tile pitch (elements)
+    constexpr int STAGE = XROWS * KP + BN * TAPS * KP;
+    constexpr int SMEM = Max<STAGE, (EPI == EPI_HEAD ? 0 : BM * OP)>::v;
+
+    __shared__ __attribute__((aligned(16))) T smem[SMEM];
+    T* xs = smem;
+    T* ws = smem + XROWS * KP;
+
+    const T* in = static_cast<const T*>(a.in);
+    const T* wt = static_cast<const T*>(a.w);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave % WM;
+    const int wn = wave / WM;
+    const int li = lane & 15;
+    const int lg = lane >> 4;
+    const int64_t m0 = (int64_t)blockIdx.x * BM;
+    const int n0 = blockIdx.y * BN;
+    const int kw = TAPS * a.cin;
+
+    f32x4 acc[TMW][TNW];
+#pragma unroll
+    for (int i = 0; i < TMW; ++i)
+#pragma unroll
+        for (int j = 0; j < TNW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int c0 = 0; c0 < a.cin; c0 += KC) {
+        for (int idx = tid; idx < XV; idx += NT) {
+            const int row = idx / (KC / 8), q = idx % (KC / 8);
+            const int64_t g = m0 - RAD + row;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if (g >= 0 && g < a.m_rows) v = *reinterpret_cast<const uint4*>(in + g * a.ld_in + c0 + 8 * q);
+            *reinterpret_cast<uint4*>(xs + row * KP + 8 * q) = v;
+        }
+        for (int idx = tid; idx < WV; idx += NT) {
+            const int q = idx % (KC / 8);
+            const int rest = idx / (KC / 8);
+            const int tap = rest % TAPS, nn = rest / TAPS;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if (n0 + nn < a.n)
+                v = *reinterpret_cast<const uint4*>(wt + (int64_t)(n0 + nn) * kw + tap * a.cin + c0 + 8 * q);
+            *reinterpret_cast<uint4*>(ws + rest * KP + 8 * q) = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tap = 0; tap < TAPS; ++tap) {
+            V av[TMW], bv[TNW];
+#pragma unroll
+            for (int i = 0; i < TMW; ++i)
+                av[i] = *reinterpret_cast<const V*>(xs + (wm * TMW * 16 + i * 16 + li + tap) * KP + 8 * lg);
+#pragma unroll
+            for (int j = 0; j < TNW; ++j)
+                bv[j] = *reinterpret_cast<const V*>(ws + ((wn * TNW * 16 + j * 16 + li) * TAPS + tap) * KP + 8 * lg);
+#pragma unroll
+            for (int i = 0; i < TMW; ++i)
+#pragma unroll
+                for (int j = 0; j < TNW; ++j) acc[i][j] = Lp<T>::mfma(av[i], bv[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+
+    // D layout of a 16x16 MFMA: lane holds rows 4*lg + v of column li.
+    const int rw = wm * TMW * 16;
+    const int cw = wn * TNW * 16;
+
+    if constexpr (EPI == EPI_HEAD) {
+#pragma unroll
+        for (int i = 0; i < TMW; ++i) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                float s = 0.f;
+#pragma unroll
+                for (int j = 0; j < TNW; ++j) {
+                    const int col = n0 + cw + j * 16 + li;
+                    s += lrelu(acc[i][j][v] + a.bias[col], a.slope) * a.head_w[col];
+                }
+                s += __shfl_xor(s, 8);
+                s += __shfl_xor(s, 4);
+                s += __shfl_xor(s, 2);
+                s += __shfl_xor(s, 1);
+                const int64_t r = m0 + rw + i * 16 + 4 * lg + v;
+                if (li == 0 && r < a.m_rows) {
+                    const int64_t e = r / a.r_in;
+                    const int loc = (int)(r - e * a.r_in);
+                    if (loc >= kGuard && loc < a.r_in - kGuard)
+                        a.prob[e * a.l_out + (loc - kGuard)] = 1.f / (1.f + expf(-(s + a.head_b)));
+                }
+            }
+        }
+        return;
+    } else {
+        T* ot = smem;   // [BM][OP], reuses the stage buffers after the last barrier
+#pragma unroll
+        for (int j = 0; j < TNW; ++j) {
+            const int col = cw + j * 16 + li;
+            const int n = n0 + col;
+            const float b = n < a.n ? a.bias[EPI == EPI_CONVT ? n % a.cout : n] : 0.f;
+#pragma unroll
+            for (int i = 0; i < TMW; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    float y = acc[i][j][v] + b;
+                    if (EPI != EPI_CONVT) y = lrelu(y, a.slope);
+                    ot[(rw + i * 16 + 4 * lg + v) * OP + col] = (T)y;
+                }
+        }
+        __syncthreads();
+        T* out = static_cast<T*>(a.out);
+        constexpr int CH = BN / 8;                  // 16-byte chunks per tile row
+        const int n_valid = a.n - n0 < BN ? a.n - n0 : BN;
+        for (int idx = tid; idx < BM * CH; idx += NT) {
+            const int row = idx / CH, q = idx % CH;
+            const int64_t r = m0 + row;
+            if (8 * q >= n_valid || r >= a.m_rows) continue;
+            const int64_t e = r / a.r_in;
+            const int loc = (int)(r - e * a.r_in);
+            if (loc < kGuard || loc >= a.r_in - kGuard) continue;
+            const uint4 v = *reinterpret_cast<const uint4*>(ot + row * OP + 8 * q);
+            if constexpr (EPI == EPI_CONVT) {
+                const int n = n0 + 8 * q;
+                const int tj = n / a.cout, o = n - tj * a.cout;
+                const int64_t ro = e * a.r_out + kGuard + 2 * (loc - kGuard) + tj;
+                *reinterpret_cast<uint4*>(out + ro * a.ld_out + o) = v;
+            } else {
+                *reinterpret_cast<uint4*>(out + r * a.ld_out + n0 + 8 * q) = v;
+            }
+        }
+        if constexpr (EPI == EPI_POOL) {
+            T* pout = static_cast<T*>(a.pool_out);
+            for (int idx = tid; idx < (BM / 2) * CH; idx += NT) {
+                const int pr = idx / CH, q = idx % CH;
+                const int64_t r = m0 + 2 * pr;       // even: first row of a pooling pair
+                if (8 * q >= n_valid || r >= a.m_rows) continue;
+                const int64_t e = r / a.r_in;
+                const int loc = (int)(r - e * a.r_in);
+                if (loc < kGuard || loc >= a.r_in - kGuard) continue;
+                const T* x0 = ot + (2 * pr) * OP + 8 * q;
+                const T* x1 = x0 + OP;
+                T y[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) y[u] = (float)x0[u] >= (float)x1[u] ? x0[u] : x1[u];
+                const int64_t rp = e * a.r_pool + kGuard + (loc - kGuard) / 2;
+                *reinterpret_cast<uint4*>(pout + rp * a.ld_pool + n0 + 8 * q) = *reinterpret_cast<const uint4*>(y);
+            }
+        }
+    }
+}
+
+template <class T, int WM, int WN, int TMW, int TNW, int TAPS, int EPI>
+hipError_t run(const ConvArgs& a, hipStream_t s)
+{
+    constexpr int BM = WM * TMW * 16;
+    constexpr int BN = WN * TNW * 16;
+    dim3 grid((unsigned)((a.m_rows + BM - 1) / BM), (unsigned)((a.n + BN - 1) / BN));
+    hipLaunchKernelGGL((conv_mfma_lp<T, WM, WN, TMW, TNW, TAPS, EPI>), grid, dim3(WM * WN * 64), 0, s, a);
+    return hipGetLastError();
+}
+
+struct Variant { int wm, wn, tmw, tnw; };
+constexpr Variant kVariants[] = {
+    {4, 1, 4, 2},   // 256 x 32
+    {4, 1, 4, 4},   // 256 x 64
+    {2, 2, 4, 4},   // 128 x 128
+    {4, 2, 4, 4},   // 256 x 128 (512 threads)
+    {4, 1, 2, 4},   // 128 x 64
+    {2, 1, 4, 2},   // 128 x 32 (128 threads)
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+#define PVF_LP_CASE(V)                                                                                       \
+    case V:                                                                                                  \
+        return run<T, kVariants[V].wm, kVariants[V].wn, kVariants[V].tmw, kVariants[V].tnw, TAPS, EPI>(a, s);
+
+template <class T, int TAPS, int EPI>
+hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
+{
+    if constexpr (EPI == EPI_HEAD) {
+        switch (v) {
+            PVF_LP_CASE(0)
+            PVF_LP_CASE(5)
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (v) {
+            PVF_LP_CASE(0)
+            PVF_LP_CASE(1)
+            PVF_LP_CASE(2)
+            PVF_LP_CASE(3)
+            PVF_LP_CASE(4)
+            PVF_LP_CASE(5)
+        default: return hipErrorInvalidValue;
+        }
+    }
+}
+
+template <class T>
+hipError_t launch_typed(const ConvArgs& a, int taps, Epi epi, int v, hipStream_t s)
+{
+    if (taps == 5) {
+        switch (epi) {
+        case EPI_STORE: return dispatch<T, 5, EPI_STORE>(v, a, s);
+        case EPI_POOL: return dispatch<T, 5, EPI_POOL>(v, a, s);
+        case EPI_HEAD: return dispatch<T, 5, EPI_HEAD>(v, a, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (taps == 1 && epi == EPI_CONVT) return dispatch<T, 1, EPI_CONVT>(v, a, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int lp_variant_count() { return kNumVariants; }
+
+bool lp_variant_ok(int v, int n, int taps, Epi epi)
+{
+    if (v < 0 || v >= kNumVariants) return false;
+    (void)taps;
+    const Variant& x = kVariants[v];
+    const int bn = x.wn * x.tnw * 16;
+    if (epi == EPI_HEAD) return (v == 0 || v == 5) && bn == n;
+    return bn <= (n < 32 ? 32 : n);
+}
+
+int lp_default_variant(int n, int taps, Epi epi)
+{
+    (void)taps;
+    if (epi == EPI_HEAD || n <= 32) return 0;
+    if (n <= 64) return 1;
+    return 2;
+}
+
+std::string lp_kernel_name(int dtype, int v, int taps, Epi epi)
+{
+    const Variant& x = kVariants[v];
+    return std::string("conv_mfma_lp<") + (dtype == PVF_BF16 ? "__bf16" : "_Float16") + ", " +
+           std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " + std::to_string(x.tmw) + ", " +
+           std::to_string(x.tnw) + ", " + std::to_string(taps) + ", " + std::to_string((int)epi) + ">";
+}
+
+hipError_t launch_conv_lp(int dtype, const ConvArgs& a, int taps, Epi epi, int v, hipStream_t s)
+{
+    if (a.cin % KC != 0 || a.m_rows <= 0 || !lp_variant_ok(v, a.n, taps, epi)) return hipErrorInvalidValue;
+    if (epi == EPI_CONVT && a.cout % 8 != 0) return hipErrorInvalidValue;
+    if (dtype == PVF_BF16) return launch_typed<__bf16>(a, taps, epi, v, s);
+    if (dtype == PVF_FP16) return launch_typed<_Float16>(a, taps, epi, v, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace pvf

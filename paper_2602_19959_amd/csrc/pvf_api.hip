@@ -29,7 +29,7 @@ pvf_status validate_spec(const pvf_spec* s)
         s->max_tracks_total < 0 || s->max_tracks_total > INT32_MAX)
         return PVF_ERR_INVALID_ARGUMENT;
     if (s->compute_dtype < PVF_FP32 || s->compute_dtype > PVF_FP8_E4M3) return PVF_ERR_INVALID_ARGUMENT;
-    if (s->compute_dtype != PVF_FP32) return PVF_ERR_UNSUPPORTED_DTYPE;
+    if (s->compute_dtype == PVF_FP8_E4M3) return PVF_ERR_UNSUPPORTED_DTYPE;
     if (!(std::isfinite(s->z_min_mm) && std::isfinite(s->bin_width_mm) && s->bin_width_mm > 0 &&
           std::isfinite(s->peak_min) && std::isfinite(s->integral_min)))
         return PVF_ERR_INVALID_ARGUMENT;
@@ -48,6 +48,7 @@ pvf_status validate_spec(const pvf_spec* s)
 
 void make_plan(const pvf_spec* s, size_t weight_floats, Plan* p)
 {
+    const size_t eb = (size_t)act_bytes(s->compute_dtype);
     p->n_levels = s->n_levels;
     p->c0 = s->base_channels;
     p->max_events = s->max_events;
@@ -61,15 +62,17 @@ void make_plan(const pvf_spec* s, size_t weight_floats, Plan* p)
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     p->weights_bytes = weight_floats * sizeof(float);
     p->weights = take(p->weights_bytes);
+    // 16-bit copy of the conv weights, same element offsets as the FP32 layout
+    p->weights_lp = s->compute_dtype == PVF_FP32 ? 0 : take(weight_floats * 2);
     p->zero_begin = off;
     p->x0 = take(E * p->lv[0].R * sizeof(float));
     const int n = s->n_levels;
     for (int l = 0; l < n; ++l) {
         const size_t rows = E * p->lv[l].R;
-        p->a[l] = take(rows * p->lv[l].C * sizeof(float));
-        if (l < n - 1) p->cat[l] = take(rows * 2 * p->lv[l].C * sizeof(float));
-        if (l >= 1) p->pool[l] = take(rows * p->lv[l - 1].C * sizeof(float));
-        if (l >= 1) p->d[l] = take(rows * p->lv[l].C * sizeof(float));
+        p->a[l] = take(rows * p->lv[l].C * eb);
+        if (l < n - 1) p->cat[l] = take(rows * 2 * p->lv[l].C * eb);
+        if (l >= 1) p->pool[l] = take(rows * p->lv[l - 1].C * eb);
+        if (l >= 1) p->d[l] = take(rows * p->lv[l].C * eb);
     }
     p->zero_end = off;
     p->prob = take(E * p->lv[0].L * sizeof(float));
@@ -269,6 +272,45 @@ void pack_weights(const Blob& b, const WeightLayout& w, std::vector<float>& out)
     std::memcpy(&out[w.head_b], b.t[ti + 1], sizeof(float));
 }
 
+// float -> bfloat16, round to nearest even (NaN kept quiet)
+uint16_t to_bf16(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+uint16_t to_f16(float f)
+{
+    _Float16 h = (_Float16)f;      // IEEE round to nearest even
+    uint16_t u;
+    std::memcpy(&u, &h, 2);
+    return u;
+}
+
+// 16-bit copy of every conv weight tensor the matrix-core kernels read
+void pack_weights_lp(const WeightLayout& w, const NetShape& n, const std::vector<float>& f32, int dtype,
+                     std::vector<uint16_t>& out)
+{
+    out.assign(w.total, 0);
+    auto conv = [&](const WeightLayout::Conv& c) {
+        const size_t cnt = (size_t)c.cout * (c.taps == 1 ? 2 : c.taps) * c.cin;
+        for (size_t i = 0; i < cnt; ++i)
+            out[c.w + i] = dtype == PVF_BF16 ? to_bf16(f32[c.w + i]) : to_f16(f32[c.w + i]);
+    };
+    for (int l = 0; l < n.n_levels; ++l) {
+        if (l > 0) conv(w.enc[l][0]);
+        conv(w.enc[l][1]);
+    }
+    for (int l = n.n_levels - 2; l >= 0; --l) {
+        conv(w.up[l]);
+        conv(w.dec[l][0]);
+        conv(w.dec[l][1]);
+    }
+}
+
 size_t weight_floats_for(const pvf_spec* s)
 {
     NetShape n{kFeat, kHidden, 6, s->bins_per_interval, s->n_levels, s->base_channels, kTaps};
@@ -322,9 +364,9 @@ void build_names(pvf_engine* e)
         c.n = gemm_n;
         c.taps = taps;
         c.epi = epi;
-        c.variant = conv_default_variant(gemm_n, taps, epi);
+        c.variant = conv_default_variant(e->spec.compute_dtype, gemm_n, taps, epi);
         e->names.push_back(name);
-        e->kernels.push_back(conv_kernel_name(c.variant, taps, epi));
+        e->kernels.push_back(conv_kernel_name(e->spec.compute_dtype, c.variant, taps, epi));
         e->conv.push_back(c);
     };
     plain("track", "track_stage");
@@ -347,8 +389,8 @@ void build_names(pvf_engine* e)
 
 bool misaligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) != 0; }
 
-ConvArgs conv_args(pvf_engine* eng, const WeightLayout::Conv& c, const float* in, int ld_in, int rows_per_event,
-                   int n_events, float* out, int ld_out)
+ConvArgs conv_args(pvf_engine* eng, const WeightLayout::Conv& c, const void* in, int ld_in, int rows_per_event,
+                   int n_events, void* out, int ld_out)
 {
     ConvArgs a{};
     const float* wbase = at<float>(eng, eng->plan.weights);
@@ -357,7 +399,8 @@ ConvArgs conv_args(pvf_engine* eng, const WeightLayout::Conv& c, const float* in
     a.cin = c.cin;
     a.m_rows = n_events * rows_per_event;
     a.r_in = rows_per_event;
-    a.w = wbase + c.w;
+    if (eng->spec.compute_dtype == PVF_FP32) a.w = wbase + c.w;
+    else a.w = at<uint16_t>(eng, eng->plan.weights_lp) + c.w;
     a.bias = wbase + c.b;
     a.n = c.cout;
     a.slope = eng->leaky;
@@ -371,7 +414,10 @@ ConvArgs conv_args(pvf_engine* eng, const WeightLayout::Conv& c, const float* in
 pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* out, hipStream_t s)
 {
     const int E = tr->n_events;
+    const int dt = eng->spec.compute_dtype;
+    const size_t eb = (size_t)act_bytes(dt);
     const Plan& P = eng->plan;
+    auto act = [&](size_t off) { return eng->arena + off; };
     const WeightLayout& W = eng->wl;
     const int n = P.n_levels;
     const float* wbase = at<float>(eng, P.weights);
@@ -417,54 +463,54 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
     fa.b = wbase + W.first_b;
     fa.c0 = P.lv[0].C;
     fa.slope = eng->leaky;
-    fa.out = at<float>(eng, P.a[0]);
-    check(launch_first_conv(fa, s));
+    fa.out = act(P.a[0]);
+    check(launch_first_conv(fa, dt, s));
 
     for (int l = 0; l < n; ++l) {
         const Level& lv = P.lv[l];
         if (l > 0) {
             const Level& up = P.lv[l - 1];
-            ConvArgs a = conv_args(eng, W.enc[l][0], at<float>(eng, P.pool[l]), up.C, lv.R, E,
-                                   at<float>(eng, P.a[l]), lv.C);
-            check(launch_conv(a, kTaps, EPI_STORE, var(), s));
+            ConvArgs a = conv_args(eng, W.enc[l][0], act(P.pool[l]), up.C, lv.R, E,
+                                   act(P.a[l]), lv.C);
+            check(launch_conv(dt, a, kTaps, EPI_STORE, var(), s));
         }
         if (l < n - 1) {
-            ConvArgs a = conv_args(eng, W.enc[l][1], at<float>(eng, P.a[l]), lv.C, lv.R, E,
-                                   at<float>(eng, P.cat[l]), 2 * lv.C);
-            a.pool_out = at<float>(eng, P.pool[l + 1]);
+            ConvArgs a = conv_args(eng, W.enc[l][1], act(P.a[l]), lv.C, lv.R, E,
+                                   act(P.cat[l]), 2 * lv.C);
+            a.pool_out = act(P.pool[l + 1]);
             a.ld_pool = lv.C;
             a.r_pool = P.lv[l + 1].R;
-            check(launch_conv(a, kTaps, EPI_POOL, var(), s));
+            check(launch_conv(dt, a, kTaps, EPI_POOL, var(), s));
         } else {
-            ConvArgs a = conv_args(eng, W.enc[l][1], at<float>(eng, P.a[l]), lv.C, lv.R, E,
-                                   at<float>(eng, P.d[l]), lv.C);
-            check(launch_conv(a, kTaps, EPI_STORE, var(), s));
+            ConvArgs a = conv_args(eng, W.enc[l][1], act(P.a[l]), lv.C, lv.R, E,
+                                   act(P.d[l]), lv.C);
+            check(launch_conv(dt, a, kTaps, EPI_STORE, var(), s));
         }
     }
     // ---- decoder
     for (int l = n - 2; l >= 0; --l) {
         const Level& lv = P.lv[l];
         const Level& lo = P.lv[l + 1];
-        ConvArgs u = conv_args(eng, W.up[l], at<float>(eng, P.d[l + 1]), lo.C, lo.R, E,
-                               at<float>(eng, P.cat[l]) + lv.C, 2 * lv.C);
+        ConvArgs u = conv_args(eng, W.up[l], act(P.d[l + 1]), lo.C, lo.R, E,
+                               act(P.cat[l]) + (size_t)lv.C * eb, 2 * lv.C);
         u.n = 2 * lv.C;
         u.cout = lv.C;
         u.r_out = lv.R;
-        check(launch_conv(u, 1, EPI_CONVT, var(), s));
-        ConvArgs a = conv_args(eng, W.dec[l][0], at<float>(eng, P.cat[l]), 2 * lv.C, lv.R, E,
-                               at<float>(eng, P.a[l]), lv.C);
-        check(launch_conv(a, kTaps, EPI_STORE, var(), s));
+        check(launch_conv(dt, u, 1, EPI_CONVT, var(), s));
+        ConvArgs a = conv_args(eng, W.dec[l][0], act(P.cat[l]), 2 * lv.C, lv.R, E,
+                               act(P.a[l]), lv.C);
+        check(launch_conv(dt, a, kTaps, EPI_STORE, var(), s));
         if (l > 0) {
-            ConvArgs b = conv_args(eng, W.dec[l][1], at<float>(eng, P.a[l]), lv.C, lv.R, E,
-                                   at<float>(eng, P.d[l]), lv.C);
-            check(launch_conv(b, kTaps, EPI_STORE, var(), s));
+            ConvArgs b = conv_args(eng, W.dec[l][1], act(P.a[l]), lv.C, lv.R, E,
+                                   act(P.d[l]), lv.C);
+            check(launch_conv(dt, b, kTaps, EPI_STORE, var(), s));
         } else {
-            ConvArgs b = conv_args(eng, W.dec[0][1], at<float>(eng, P.a[0]), lv.C, lv.R, E, nullptr, 0);
+            ConvArgs b = conv_args(eng, W.dec[0][1], act(P.a[0]), lv.C, lv.R, E, nullptr, 0);
             b.head_w = wbase + W.head_w;
             b.head_b = eng->head_b;
             b.prob = prob;
             b.l_out = lv.L;
-            check(launch_conv(b, kTaps, EPI_HEAD, var(), s));
+            check(launch_conv(dt, b, kTaps, EPI_HEAD, var(), s));
         }
     }
     // ---- peaks
@@ -557,6 +603,12 @@ pvf_status pvf_init(const pvf_spec* spec, const void* blob, size_t blob_bytes, v
     pack_weights(b, e->wl, packed);
     hipError_t err = hipMemcpyAsync(e->arena + plan.weights, packed.data(), packed.size() * sizeof(float),
                                     hipMemcpyHostToDevice, e->stream);
+    std::vector<uint16_t> packed_lp;
+    if (err == hipSuccess && spec->compute_dtype != PVF_FP32) {
+        pack_weights_lp(e->wl, b.shape, packed, spec->compute_dtype, packed_lp);
+        err = hipMemcpyAsync(e->arena + plan.weights_lp, packed_lp.data(), packed_lp.size() * sizeof(uint16_t),
+                             hipMemcpyHostToDevice, e->stream);
+    }
     if (err == hipSuccess)
         err = hipMemsetAsync(e->arena + plan.zero_begin, 0, plan.zero_end - plan.zero_begin, e->stream);
     if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
@@ -646,7 +698,7 @@ const char* pvf_launch_kernel(const pvf_engine* eng, int i)
 int pvf_launch_variant_count(const pvf_engine* eng, int i)
 {
     if (!eng || i < 0 || i >= (int)eng->conv.size() || eng->conv[i].variant < 0) return 0;
-    return conv_variant_count();
+    return conv_variant_count(eng->spec.compute_dtype);
 }
 
 int pvf_launch_variant(const pvf_engine* eng, int i)
@@ -659,9 +711,9 @@ pvf_status pvf_set_launch_variant(pvf_engine* eng, int i, int v)
 {
     if (!eng || i < 0 || i >= (int)eng->conv.size() || eng->conv[i].variant < 0) return PVF_ERR_INVALID_ARGUMENT;
     auto& c = eng->conv[i];
-    if (!conv_variant_ok(v, c.n, c.taps, c.epi)) return PVF_ERR_INVALID_ARGUMENT;
+    if (!conv_variant_ok(eng->spec.compute_dtype, v, c.n, c.taps, c.epi)) return PVF_ERR_INVALID_ARGUMENT;
     c.variant = v;
-    eng->kernels[i] = conv_kernel_name(v, c.taps, c.epi);
+    eng->kernels[i] = conv_kernel_name(eng->spec.compute_dtype, v, c.taps, c.epi);
     return PVF_OK;
 }
 
@@ -677,13 +729,13 @@ pvf_status pvf_autotune(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertice
     std::vector<int> pick(nl, -1);
     for (int i = 0; i < nl; ++i) pick[i] = eng->conv[i].variant;
     const std::vector<pvf_engine::ConvLaunch> saved = eng->conv;
-    for (int v = 0; v < conv_variant_count() && st == PVF_OK; ++v) {
+    for (int v = 0; v < conv_variant_count(eng->spec.compute_dtype) && st == PVF_OK; ++v) {
         // try variant v on every conv launch that accepts it, all in one pass
         bool any = false;
         for (int i = 0; i < nl; ++i) {
             auto& c = eng->conv[i];
             if (c.variant < 0) continue;
-            if (conv_variant_ok(v, c.n, c.taps, c.epi)) { c.variant = v; any = true; }
+            if (conv_variant_ok(eng->spec.compute_dtype, v, c.n, c.taps, c.epi)) { c.variant = v; any = true; }
             else c.variant = saved[i].variant;
         }
         if (!any) continue;
@@ -736,8 +788,11 @@ pvf_status pvf_debug_tensor(pvf_engine* eng, const char* name, int32_t n_events,
     const int n = P.n_levels;
     GatherArgs g{};
     bool found = false;
-    auto set = [&](size_t off, int ld, int l, int C, int ch_off) {
-        g.src = at<float>(eng, off);
+    const int eb = act_bytes(eng->spec.compute_dtype);
+    g.dtype = eng->spec.compute_dtype;
+    auto set = [&](size_t off, int ld, int l, int C, int ch_off, int bytes) {
+        g.src = eng->arena + off;
+        g.src_bytes = bytes;
         g.ld = ld;
         g.r = P.lv[l].R;
         g.guard = kGuard;
@@ -747,22 +802,23 @@ pvf_status pvf_debug_tensor(pvf_engine* eng, const char* name, int32_t n_events,
         found = true;
     };
     const std::string s(name);
-    if (s == "hist") set(P.x0, 1, 0, 1, 0);
+    if (s == "hist") set(P.x0, 1, 0, 1, 0, 4);
     if (s == "prob") {
         g.src = at<float>(eng, P.prob);
+        g.src_bytes = 4;
         g.ld = 1; g.r = P.lv[0].L; g.guard = 0; g.L = P.lv[0].L; g.C = 1; g.ch_off = 0;
         found = true;
     }
     for (int l = 0; l < n; ++l) {
         const std::string L = std::to_string(l);
         const int C = P.lv[l].C;
-        if (l < n - 1 && s == "enc" + L + ".c2") set(P.cat[l], 2 * C, l, C, 0);
-        if (l == n - 1 && s == "enc" + L + ".c2") set(P.d[l], C, l, C, 0);
-        if (l == n - 1 && s == "enc" + L + ".c1") set(P.a[l], C, l, C, 0);
-        if (l < n - 1 && s == "pool" + L) set(P.pool[l + 1], C, l + 1, C, 0);
-        if (l < n - 1 && s == "up" + L) set(P.cat[l], 2 * C, l, C, C);
-        if (l < n - 1 && s == "dec" + L + ".c1") set(P.a[l], C, l, C, 0);
-        if (l >= 1 && l < n - 1 && s == "dec" + L + ".c2") set(P.d[l], C, l, C, 0);
+        if (l < n - 1 && s == "enc" + L + ".c2") set(P.cat[l], 2 * C, l, C, 0, eb);
+        if (l == n - 1 && s == "enc" + L + ".c2") set(P.d[l], C, l, C, 0, eb);
+        if (l == n - 1 && s == "enc" + L + ".c1") set(P.a[l], C, l, C, 0, eb);
+        if (l < n - 1 && s == "pool" + L) set(P.pool[l + 1], C, l + 1, C, 0, eb);
+        if (l < n - 1 && s == "up" + L) set(P.cat[l], 2 * C, l, C, C, eb);
+        if (l < n - 1 && s == "dec" + L + ".c1") set(P.a[l], C, l, C, 0, eb);
+        if (l >= 1 && l < n - 1 && s == "dec" + L + ".c2") set(P.d[l], C, l, C, 0, eb);
     }
     if (!found) return PVF_ERR_INVALID_ARGUMENT;
     g.count = (int64_t)n_events * g.C * g.L;

@@ -31,14 +31,16 @@ struct Level {
     int C;      // channels of this level
 };
 
-// Offsets (bytes from the arena base) of every buffer.
+// Offsets (bytes from the arena base) of every buffer.  Activations a, cat,
+// pool, d hold the compute dtype (4 or 2 bytes per element).
 struct Plan {
     int n_levels = 0;
     int c0 = 0;
     int max_events = 0;
     Level lv[kMaxLevels];
     size_t weights = 0, weights_bytes = 0;
-    size_t x0 = 0;                 // [E][R0][1]      scaled histogram
+    size_t weights_lp = 0;         // 16-bit conv weights (BF16/FP16 engines)
+    size_t x0 = 0;                 // [E][R0][1]      scaled histogram (always FP32)
     size_t a[kMaxLevels] = {};     // [E][Rl][Cl]     conv1 outputs (enc, then dec)
     size_t cat[kMaxLevels] = {};   // [E][Rl][2Cl]    skip | upsampled  (l < n-1)
     size_t pool[kMaxLevels] = {};  // [E][Rl][C(l-1)] pooled input of level l (l >= 1)
@@ -64,20 +66,20 @@ struct WeightLayout {
 enum Epi { EPI_STORE = 0, EPI_POOL = 1, EPI_CONVT = 2, EPI_HEAD = 3 };
 
 struct ConvArgs {
-    const float* in;     // input rows, channels-last
+    const void* in;      // input rows, channels-last (element type = compute dtype)
     int ld_in;           // floats per input row
     int cin;             // channels read (multiple of 16)
     int m_rows;          // total input rows (= events * R_in)
     int r_in;            // rows per event of the input level
-    const float* w;      // packed [N][taps][cin]
+    const void* w;       // packed [N][taps][cin] (element type = compute dtype)
     const float* bias;   // [Cout]
     int n;               // GEMM N (Cout, or 2*Cout for the transposed conv)
     float slope;         // LeakyReLU slope
-    float* out;          // output base (row 0, channel 0 of the destination)
+    void* out;           // output base (row 0, channel 0 of the destination)
     int ld_out;          // floats per output row
     int r_out;           // rows per event of the output level
     int cout;            // output channels (transposed conv: n / 2)
-    float* pool_out;     // EPI_POOL: pooled destination
+    void* pool_out;      // EPI_POOL: pooled destination
     int ld_pool;
     int r_pool;
     const float* head_w; // EPI_HEAD: [C0] head weights
@@ -114,7 +116,7 @@ struct FirstConvArgs {
     const float* b;          // [C0]
     int c0;
     float slope;
-    float* out;              // [E][R0][C0]
+    void* out;               // [E][R0][C0], element type = compute dtype
 };
 
 struct PeakArgs {
@@ -133,20 +135,38 @@ struct PeakArgs {
 };
 
 struct GatherArgs {          // debug copy of an internal activation
-    const float* src;
+    const void* src;
+    int src_bytes;           // 4 = float, 2 = 16-bit compute dtype (see dtype)
+    int dtype;
     int ld, r, guard, L, C, ch_off;
     float* dst;              // [E][C][L]
     int64_t count;
 };
 
 hipError_t launch_track(const TrackArgs& a, int n_events, hipStream_t s);
-hipError_t launch_first_conv(const FirstConvArgs& a, hipStream_t s);
-// Conv launches run one of several tile-shape variants; all give identical bits.
-hipError_t launch_conv(const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s);
-int conv_variant_count();
-bool conv_variant_ok(int variant, int n, int taps, Epi epi);
-int conv_default_variant(int n, int taps, Epi epi);
-std::string conv_kernel_name(int variant, int taps, Epi epi);
+hipError_t launch_first_conv(const FirstConvArgs& a, int dtype, hipStream_t s);
+// Conv launches run one of several tile-shape variants of the kernel for
+// the compute dtype; all variants of a dtype give identical bits.
+hipError_t launch_conv(int dtype, const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s);
+int conv_variant_count(int dtype);
+bool conv_variant_ok(int dtype, int variant, int n, int taps, Epi epi);
+int conv_default_variant(int dtype, int n, int taps, Epi epi);
+std::string conv_kernel_name(int dtype, int variant, int taps, Epi epi);
+
+// per-precision implementations behind the functions above
+hipError_t launch_conv_f32(const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s);
+int f32_variant_count();
+bool f32_variant_ok(int variant, int n, int taps, Epi epi);
+int f32_default_variant(int n, int taps, Epi epi);
+std::string f32_kernel_name(int variant, int taps, Epi epi);
+hipError_t launch_conv_lp(int dtype, const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s);
+int lp_variant_count();
+bool lp_variant_ok(int variant, int n, int taps, Epi epi);
+int lp_default_variant(int n, int taps, Epi epi);
+std::string lp_kernel_name(int dtype, int variant, int taps, Epi epi);
+
+inline int act_bytes(int dtype) { return dtype == PVF_FP32 ? 4 : 2; }
+
 hipError_t launch_peaks(const PeakArgs& a, int n_events, hipStream_t s);
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
 

@@ -87,3 +87,34 @@ def compare_peaks(gpu_t, gpu_z, gpu_prob, gpu_S, ref, geo):
         assert abs(gpu_S[k] - ref["integral"][i]) <= P_REL * ref["integral"][i]
         assert abs(gpu_prob[k] - ref["prob"][i]) <= P_REL * ref["prob"][i]
     return len(amb), len(rset | gset)
+
+
+# Reduced-precision paths (BF16/FP16 storage and weights, FP32 accumulation).
+# Bounds frozen from a CPU emulation against the oracle on 16 seed-0 events
+# (BF16: max|dp| 1.4e-2, 99.9% of vertices matched; FP16: 1.6e-3, 99.996%):
+#   max |p - p_ref| <= P_ABS[dtype]; vertices matched one-to-one within
+#   |dz| <= 0.05 mm: at least MATCH_MIN[dtype] of the oracle's, and at most
+#   EXTRA_MAX[dtype] (as a fraction of the oracle's count) unmatched extras.
+P_ABS = {"bf16": 2e-2, "fp16": 5e-3}
+MATCH_MIN = {"bf16": 0.995, "fp16": 0.999}
+EXTRA_MAX = {"bf16": 0.005, "fp16": 0.001}
+DZ_MATCH = 0.05
+
+
+def match_vertices(z_gpu, z_ref, tol=DZ_MATCH):
+    """One-to-one matching of two sorted vertex lists by |dz| <= tol
+    (two-pointer sweep).  Returns the number of matched pairs."""
+    a = np.sort(np.asarray(z_gpu, np.float64))
+    b = np.sort(np.asarray(z_ref, np.float64))
+    i = j = m = 0
+    while i < len(a) and j < len(b):
+        d = a[i] - b[j]
+        if abs(d) <= tol:
+            m += 1
+            i += 1
+            j += 1
+        elif d < 0:
+            i += 1
+        else:
+            j += 1
+    return m

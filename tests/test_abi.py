@@ -70,8 +70,8 @@ def test_arena_bytes_scales_with_events():
 
 @pytest.mark.parametrize("field,value,status", [
     ("abi_version", 7, 1), ("max_events", 0, 1), ("max_peaks_per_event", 0, 1),
-    ("max_tracks_total", -1, 1), ("compute_dtype", 9, 1), ("compute_dtype", 1, 6),
-    ("n_levels", 1, 2), ("base_channels", 48, 2), ("n_bins", 4001, 2),
+    ("max_tracks_total", -1, 1), ("compute_dtype", 9, 1),
+    ("compute_dtype", 3, 6), ("n_levels", 1, 2), ("base_channels", 48, 2), ("n_bins", 4001, 2),
     ("bins_per_interval", 300, 2), ("bin_width_mm", 0.0, 1), ("half_window", -1, 1),
     ("max_peaks_per_event", 5000, 2),
 ])

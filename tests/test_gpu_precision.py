@@ -1,0 +1,118 @@
+"""Reduced-precision UNet (BF16, FP16 on the matrix cores, FP32 accumulation)
+against the FP64 oracle, through the C ABI.  Section 5 of the paper proposes
+FP16 on the matrix units; the bounds are stated in tests/parity.py."""
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import make_events
+from tests import parity
+from tests.gpu_util import torch_cuda, make_engine, run, weights
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = ["bf16", "fp16"]
+
+
+def say(*a):
+    print("[gpu-precision]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def batch16():
+    return make_events(16, seed=0)
+
+
+@pytest.fixture(scope="module")
+def ref16(batch16):
+    return oracle.run_batch(batch16, weights())
+
+
+@pytest.fixture(scope="module", params=DTYPES)
+def lp(request, batch16):
+    torch_cuda()
+    say("engine", request.param)
+    eng = make_engine(16, compute_dtype=request.param)
+    out = run(eng, batch16)
+    yield request.param, eng, out
+    eng.close()
+
+
+def test_probability_within_stated_bound(lp, ref16):
+    dt, eng, out = lp
+    dp = max(float(np.max(np.abs(out["prob"][e] - ref16[e]["p"]))) for e in range(16))
+    say(dt, "max |dp| %.3e (bound %.0e)" % (dp, parity.P_ABS[dt]))
+    assert dp <= parity.P_ABS[dt]
+
+
+def test_vertices_agree(lp, ref16):
+    dt, eng, out = lp
+    matched = extra = total = 0
+    for e in range(16):
+        n = int(out["n_vertices"][e])
+        m = parity.match_vertices(out["z"][e, :n], ref16[e]["z"])
+        matched += m
+        extra += n - m
+        total += len(ref16[e]["z"])
+    say(dt, f"vertices matched {matched}/{total}, extra {extra}")
+    assert matched >= parity.MATCH_MIN[dt] * total
+    assert extra <= parity.EXTRA_MAX[dt] * total
+
+
+def test_deterministic_and_batch_invariant(lp, batch16):
+    dt, eng, out = lp
+    again = run(eng, batch16)
+    assert np.array_equal(again["prob"], out["prob"])
+    alone = run(eng, batch16.subset([7]))
+    assert np.array_equal(alone["prob"][0], out["prob"][7])
+
+
+def test_variants_identical(lp, batch16):
+    dt, eng, out = lp
+    base = eng.variants()
+    n = len(base)
+    tried = 0
+    for v in range(eng.variant_count(2)):
+        changed = [i for i in range(n) if base[i] >= 0 and eng.set_variant(i, v)]
+        if not changed:
+            continue
+        tried += 1
+        got = run(eng, batch16)
+        assert np.array_equal(got["prob"], out["prob"]), (dt, v)
+        for i in range(n):
+            if base[i] >= 0:
+                eng.set_variant(i, base[i])
+    assert tried >= 4
+
+
+def test_layer_taps_close_to_fp32(lp, batch16):
+    """Per-layer activations stay within 16-bit rounding of the oracle's
+    (normwise 3e-2 for BF16's 8-bit mantissa, 5e-3 for FP16), so a wrong
+    layer is located, not just a wrong output."""
+    dt, eng, out = lp
+    w = weights()
+    taps = oracle.unet_taps(w.s_in * oracle.histogram(batch16.tracks_of(0), w)[0], w)
+    bound = {"bf16": 3e-2, "fp16": 5e-3}[dt]
+    # re-run event 0 alone so the debug buffers hold it
+    run(eng, batch16.subset([0]))
+    for name in ("enc0.c2", "pool1", "enc3.c2", "up2", "dec1.c1", "dec0.c1"):
+        got = eng.debug_tensor(name, 1).cpu().numpy().reshape(taps[name].shape)
+        err = parity.tap_err(got, taps[name])
+        say(dt, name, "normwise %.2e" % err)
+        assert err <= bound, name
+
+
+def test_full_batch_sampled(lp):
+    """1000 events in one call (the production slice), sampled against the oracle."""
+    dt, _, _ = lp
+    batch = make_events(1000, seed=0)
+    eng = make_engine(1000, compute_dtype=dt)
+    out = run(eng, batch)
+    sample = [0, 333, 999]
+    ref = oracle.run_batch(batch.subset(sample), weights())
+    for k, e in enumerate(sample):
+        dp = float(np.max(np.abs(out["prob"][e] - ref[k]["p"])))
+        say(dt, f"event {e} max |dp| {dp:.3e}")
+        assert dp <= parity.P_ABS[dt]
+    eng.close()
