@@ -11,14 +11,14 @@ hipError_t launch_conv(int dtype, const ConvArgs& a, int taps, Epi epi, int vari
 
 int conv_variant_count(int dtype) { return dtype == PVF_FP32 ? f32_variant_count() : lp_variant_count(); }
 
-bool conv_variant_ok(int dtype, int variant, int n, int taps, Epi epi)
+bool conv_variant_ok(int dtype, int variant, int n, int cin, int taps, Epi epi)
 {
-    return dtype == PVF_FP32 ? f32_variant_ok(variant, n, taps, epi) : lp_variant_ok(variant, n, taps, epi);
+    return dtype == PVF_FP32 ? f32_variant_ok(variant, n, taps, epi) : lp_variant_ok(variant, n, cin, taps, epi);
 }
 
-int conv_default_variant(int dtype, int n, int taps, Epi epi)
+int conv_default_variant(int dtype, int n, int cin, int taps, Epi epi)
 {
-    return dtype == PVF_FP32 ? f32_default_variant(n, taps, epi) : lp_default_variant(n, taps, epi);
+    return dtype == PVF_FP32 ? f32_default_variant(n, taps, epi) : lp_default_variant(n, cin, taps, epi);
 }
 
 std::string conv_kernel_name(int dtype, int variant, int taps, Epi epi)

@@ -7,7 +7,7 @@
 //   k = (tap, input channel).
 // A is never materialised: a block stages the (BM + 4) x 16 halo tile of input
 // rows once per 16-channel chunk in LDS and all five taps read it with a row
-// shift.  The packed weights are [N][taps][Cin], so one 16-byte LDS read gives
+// shift.  LDS tiles are unpadded and XOR-swizzled per 16-byte chunk.  The packed weights are [N][taps][Cin], so one 16-byte LDS read gives
 // a lane four consecutive k of its column.
 //
 // MFMA: v_mfma_f32_16x16x4_f32.  For one 16-wide k chunk, lane group g = lane/16
@@ -32,9 +32,14 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int KC = 16;         // input channels per LDS stage
-constexpr int KPAD = KC + 4;   // LDS pitch in floats (80 B): 8 consecutive rows'
-                               // 16-byte reads fall on distinct bank groups
+constexpr int KC = 16;         // input channels per LDS stage = 4 chunks of 16 B
+
+// LDS rows are KC floats (4 chunks of 16 B) with no padding; chunk q of row r
+// is stored at position q ^ swz(r).  The 32 lanes a 16-byte LDS read serves
+// at once (16 consecutive rows x 2 chunks) then hit 32 distinct chunk slots,
+// for the halo tile, the weight tile and the staging writes alike.
+__device__ __forceinline__ int swz(int r) { return (r >> 2) & 2; }
+__device__ __forceinline__ int lds_at(int r, int q) { return (r * 4 + (q ^ swz(r))) * 4; }   // in floats
 
 __device__ __forceinline__ float lrelu(float x, float s) { return x >= 0.f ? x : s * x; }
 
@@ -51,8 +56,8 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32(ConvArgs a)
     constexpr int XPT = (XV + NT - 1) / NT;
     constexpr int WPT = (WV + NT - 1) / NT;
 
-    __shared__ float xs[XROWS * KPAD];
-    __shared__ float ws[BN * TAPS * KPAD];
+    __shared__ float xs[XROWS * KC];
+    __shared__ float ws[BN * TAPS * KC];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -62,8 +67,16 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32(ConvArgs a)
     const int li = lane & 15;
     const int lg = lane >> 4;
 
-    const int64_t m0 = (int64_t)blockIdx.x * BM;
-    const int n0 = blockIdx.y * BN;
+    // XCD-aware tile order: block b runs on XCD b % 8; every N tile of one M
+    // tile goes to the same XCD back to back, so the halo rows (and the
+    // weights) are served from that XCD's L2 instead of HBM.
+    const int n_tiles = (a.n + BN - 1) / BN;
+    const int m_tiles = (int)((a.m_rows + BM - 1) / BM);
+    const int xcd = (int)(blockIdx.x % kXcds), slot = (int)(blockIdx.x / kXcds);
+    const int m_tile = (slot / n_tiles) * kXcds + xcd;
+    if (m_tile >= m_tiles) return;
+    const int64_t m0 = (int64_t)m_tile * BM;
+    const int n0 = (slot % n_tiles) * BN;
     const int kw = TAPS * a.cin;
     const float* in = static_cast<const float*>(a.in);
     const float* wt = static_cast<const float*>(a.w);
@@ -111,7 +124,7 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32(ConvArgs a)
             const int idx = tid + u * NT;
             if (idx < XV) {
                 const int row = idx / (KC / 4), q = idx % (KC / 4);
-                *reinterpret_cast<f32x4*>(xs + row * KPAD + 4 * q) = xr[u];
+                *reinterpret_cast<f32x4*>(xs + lds_at(row, q)) = xr[u];
             }
         }
 #pragma unroll
@@ -120,7 +133,7 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32(ConvArgs a)
             if (idx < WV) {
                 const int q = idx % (KC / 4);
                 const int rest = idx / (KC / 4);
-                *reinterpret_cast<f32x4*>(ws + rest * KPAD + 4 * q) = wr[u];
+                *reinterpret_cast<f32x4*>(ws + lds_at(rest, q)) = wr[u];
             }
         }
     };
@@ -136,10 +149,10 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32(ConvArgs a)
             f32x4 av[TMW], bv[TNW];
 #pragma unroll
             for (int i = 0; i < TMW; ++i)
-                av[i] = *reinterpret_cast<const f32x4*>(xs + (wm * TMW * 16 + i * 16 + li + tap) * KPAD + 4 * lg);
+                av[i] = *reinterpret_cast<const f32x4*>(xs + lds_at(wm * TMW * 16 + i * 16 + li + tap, lg));
 #pragma unroll
             for (int j = 0; j < TNW; ++j)
-                bv[j] = *reinterpret_cast<const f32x4*>(ws + ((wn * TNW * 16 + j * 16 + li) * TAPS + tap) * KPAD + 4 * lg);
+                bv[j] = *reinterpret_cast<const f32x4*>(ws + lds_at((wn * TNW * 16 + j * 16 + li) * TAPS + tap, lg));
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -252,7 +265,9 @@ hipError_t run(const ConvArgs& a, hipStream_t s)
 {
     constexpr int BM = WM * TMW * 16;
     constexpr int BN = WN * TNW * 16;
-    dim3 grid((unsigned)((a.m_rows + BM - 1) / BM), (unsigned)((a.n + BN - 1) / BN));
+    const unsigned m_tiles = (unsigned)((a.m_rows + BM - 1) / BM);
+    const unsigned n_tiles = (unsigned)((a.n + BN - 1) / BN);
+    dim3 grid((m_tiles + kXcds - 1) / kXcds * kXcds * n_tiles);
     hipLaunchKernelGGL((conv_mfma_f32<WM, WN, TMW, TNW, PF, TAPS, EPI>), grid, dim3(WM * WN * 64), 0, s, a);
     return hipGetLastError();
 }

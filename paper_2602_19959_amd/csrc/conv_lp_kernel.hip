@@ -5,7 +5,8 @@
 // Same GEMM view as the FP32 kernel (m = event row, n = output channel,
 // k = (tap, input channel)), with 16-bit activations and weights:
 //   * one stage = 32 input channels: the (BM + 4) x 32 halo tile and the
-//     BN x 5 x 32 weight tile go to LDS once and all five taps read them;
+//     BN x 5 x 32 weight tile go to LDS once (unpadded, XOR-swizzled per
+//     16-byte chunk) and all five taps read them;
 //   * v_mfma_f32_16x16x32_{bf16,f16}: each lane feeds 8 consecutive
 //     channels of its row (A) and of its column (B) with one 16-byte LDS
 //     read; A and B use the same lane-to-k map, so the MFMA sums the whole
@@ -37,32 +38,47 @@ template <> struct Lp<_Float16> {
     __device__ static f32x4 mfma(vec8 a, vec8 b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
 };
 
-constexpr int KC = 32;        // input channels per stage (one MFMA k step per tap)
-constexpr int KP = KC + 8;    // LDS pitch in elements: 80 B, 8 consecutive rows'
-                              // 16-byte reads land on distinct bank groups
+// LDS rows hold one stage's KC channels as NCH = KC/8 chunks of 16 B, with no
+// padding; chunk c of row r sits at position c ^ swz(r).  A 16-byte LDS read
+// serves 32 lanes at once (16 consecutive rows x 2 chunks); the swizzle spreads
+// the rows that share a bank offset over distinct chunk slots.
+template <int NCH>
+__device__ __forceinline__ int swz(int r)
+{
+    return NCH == 4 ? ((r >> 2) & 2) : (((r >> 2) & 3) << 1);
+}
+template <int NCH>
+__device__ __forceinline__ int lds_at(int r, int c) { return (r * NCH + (c ^ swz<NCH>(r))) * 8; }   // elements
 
 __device__ __forceinline__ float lrelu(float x, float s) { return x >= 0.f ? x : s * x; }
 
 template <int A, int B> struct Max { static constexpr int v = A > B ? A : B; };
 
-template <class T, int WM, int WN, int TMW, int TNW, int TAPS, int EPI>
+// KC: input channels per LDS stage (32 or 64); within a stage the k order is
+// (32-channel chunk, tap, MFMA), the same as with KC = 32, so KC does not
+// change a bit of the result.  PF = 1: the next stage is fetched into
+// registers while the current one computes.
+template <class T, int WM, int WN, int TMW, int TNW, int KC, int PF, int TAPS, int EPI>
 __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_lp(ConvArgs a)
 {
     using V = typename Lp<T>::vec8;
     constexpr int NT = WM * WN * 64;
     constexpr int BM = WM * TMW * 16;
     constexpr int BN = WN * TNW * 16;
+    constexpr int NCH = KC / 8;                 // 16-byte chunks per row and stage
     constexpr int RAD = (TAPS - 1) / 2;
     constexpr int XROWS = BM + TAPS - 1;
-    constexpr int XV = XROWS * (KC / 8);        // 16-byte chunks per stage
-    constexpr int WV = BN * TAPS * (KC / 8);
+    constexpr int XV = XROWS * NCH;
+    constexpr int WV = BN * TAPS * NCH;
+    constexpr int XPT = (XV + NT - 1) / NT;
+    constexpr int WPT = (WV + NT - 1) / NT;
     constexpr int OP = BN + 8;                  // epilogue tile pitch (elements)
-    constexpr int STAGE = XROWS * KP + BN * TAPS * KP;
+    constexpr int STAGE = XROWS * KC + BN * TAPS * KC;
     constexpr int SMEM = Max<STAGE, (EPI == EPI_HEAD ? 0 : BM * OP)>::v;
 
     __shared__ __attribute__((aligned(16))) T smem[SMEM];
     T* xs = smem;
-    T* ws = smem + XROWS * KP;
+    T* ws = smem + XROWS * KC;
 
     const T* in = static_cast<const T*>(a.in);
     const T* wt = static_cast<const T*>(a.w);
@@ -73,8 +89,16 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_lp(ConvArgs a)
     const int wn = wave / WM;
     const int li = lane & 15;
     const int lg = lane >> 4;
-    const int64_t m0 = (int64_t)blockIdx.x * BM;
-    const int n0 = blockIdx.y * BN;
+    // XCD-aware tile order: block b runs on XCD b % 8; every N tile of one M
+    // tile goes to the same XCD back to back, so the halo rows (and the
+    // weights) are served from that XCD's L2 instead of HBM.
+    const int n_tiles = (a.n + BN - 1) / BN;
+    const int m_tiles = (int)((a.m_rows + BM - 1) / BM);
+    const int xcd = (int)(blockIdx.x % kXcds), slot = (int)(blockIdx.x / kXcds);
+    const int m_tile = (slot / n_tiles) * kXcds + xcd;
+    if (m_tile >= m_tiles) return;
+    const int64_t m0 = (int64_t)m_tile * BM;
+    const int n0 = (slot % n_tiles) * BN;
     const int kw = TAPS * a.cin;
 
     f32x4 acc[TMW][TNW];
@@ -83,39 +107,97 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_lp(ConvArgs a)
 #pragma unroll
         for (int j = 0; j < TNW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int c0 = 0; c0 < a.cin; c0 += KC) {
+    uint4 xr[PF ? XPT : 1], wr[PF ? WPT : 1];
+    auto fetch = [&](int c0) {
+#pragma unroll
+        for (int u = 0; u < XPT; ++u) {
+            const int idx = tid + u * NT;
+            xr[u] = uint4{0u, 0u, 0u, 0u};
+            if (idx < XV) {
+                const int row = idx / NCH, q = idx % NCH;
+                const int64_t g = m0 - RAD + row;
+                if (g >= 0 && g < a.m_rows) xr[u] = *reinterpret_cast<const uint4*>(in + g * a.ld_in + c0 + 8 * q);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) {
+            const int idx = tid + u * NT;
+            wr[u] = uint4{0u, 0u, 0u, 0u};
+            if (idx < WV) {
+                const int q = idx % NCH, rest = idx / NCH;
+                const int tap = rest % TAPS, nn = rest / TAPS;
+                if (n0 + nn < a.n)
+                    wr[u] = *reinterpret_cast<const uint4*>(wt + (int64_t)(n0 + nn) * kw + tap * a.cin + c0 + 8 * q);
+            }
+        }
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int u = 0; u < XPT; ++u) {
+            const int idx = tid + u * NT;
+            if (idx < XV) *reinterpret_cast<uint4*>(xs + lds_at<NCH>(idx / NCH, idx % NCH)) = xr[u];
+        }
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) {
+            const int idx = tid + u * NT;
+            if (idx < WV) *reinterpret_cast<uint4*>(ws + lds_at<NCH>(idx / NCH, idx % NCH)) = wr[u];
+        }
+    };
+
+    // PF = 0: load and store each chunk in turn (fewest live registers)
+    auto copy_direct = [&](int c0) {
         for (int idx = tid; idx < XV; idx += NT) {
-            const int row = idx / (KC / 8), q = idx % (KC / 8);
+            const int row = idx / NCH, q = idx % NCH;
             const int64_t g = m0 - RAD + row;
             uint4 v = {0u, 0u, 0u, 0u};
             if (g >= 0 && g < a.m_rows) v = *reinterpret_cast<const uint4*>(in + g * a.ld_in + c0 + 8 * q);
-            *reinterpret_cast<uint4*>(xs + row * KP + 8 * q) = v;
+            *reinterpret_cast<uint4*>(xs + lds_at<NCH>(row, q)) = v;
         }
         for (int idx = tid; idx < WV; idx += NT) {
-            const int q = idx % (KC / 8);
-            const int rest = idx / (KC / 8);
+            const int q = idx % NCH, rest = idx / NCH;
             const int tap = rest % TAPS, nn = rest / TAPS;
             uint4 v = {0u, 0u, 0u, 0u};
             if (n0 + nn < a.n)
                 v = *reinterpret_cast<const uint4*>(wt + (int64_t)(n0 + nn) * kw + tap * a.cin + c0 + 8 * q);
-            *reinterpret_cast<uint4*>(ws + rest * KP + 8 * q) = v;
+            *reinterpret_cast<uint4*>(ws + lds_at<NCH>(rest, q)) = v;
+        }
+    };
+
+    if constexpr (PF) {
+        fetch(0);
+        stage();
+    } else {
+        copy_direct(0);
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < a.cin; c0 += KC) {
+        const bool more = c0 + KC < a.cin;
+        if constexpr (PF) {
+            if (more) fetch(c0 + KC);
+        }
+#pragma unroll
+        for (int sub = 0; sub < KC / 32; ++sub) {
+#pragma unroll
+            for (int tap = 0; tap < TAPS; ++tap) {
+                V av[TMW], bv[TNW];
+#pragma unroll
+                for (int i = 0; i < TMW; ++i)
+                    av[i] = *reinterpret_cast<const V*>(xs + lds_at<NCH>(wm * TMW * 16 + i * 16 + li + tap, 4 * sub + lg));
+#pragma unroll
+                for (int j = 0; j < TNW; ++j)
+                    bv[j] = *reinterpret_cast<const V*>(ws + lds_at<NCH>((wn * TNW * 16 + j * 16 + li) * TAPS + tap, 4 * sub + lg));
+#pragma unroll
+                for (int i = 0; i < TMW; ++i)
+#pragma unroll
+                    for (int j = 0; j < TNW; ++j) acc[i][j] = Lp<T>::mfma(av[i], bv[j], acc[i][j]);
+            }
         }
         __syncthreads();
-#pragma unroll
-        for (int tap = 0; tap < TAPS; ++tap) {
-            V av[TMW], bv[TNW];
-#pragma unroll
-            for (int i = 0; i < TMW; ++i)
-                av[i] = *reinterpret_cast<const V*>(xs + (wm * TMW * 16 + i * 16 + li + tap) * KP + 8 * lg);
-#pragma unroll
-            for (int j = 0; j < TNW; ++j)
-                bv[j] = *reinterpret_cast<const V*>(ws + ((wn * TNW * 16 + j * 16 + li) * TAPS + tap) * KP + 8 * lg);
-#pragma unroll
-            for (int i = 0; i < TMW; ++i)
-#pragma unroll
-                for (int j = 0; j < TNW; ++j) acc[i][j] = Lp<T>::mfma(av[i], bv[j], acc[i][j]);
+        if (more) {
+            if constexpr (PF) stage();
+            else copy_direct(c0 + KC);
+            __syncthreads();
         }
-        __syncthreads();
     }
 
     // D layout of a 16x16 MFMA: lane holds rows 4*lg + v of column li.
@@ -205,30 +287,40 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_lp(ConvArgs a)
     }
 }
 
-template <class T, int WM, int WN, int TMW, int TNW, int TAPS, int EPI>
+template <class T, int WM, int WN, int TMW, int TNW, int KC, int PF, int TAPS, int EPI>
 hipError_t run(const ConvArgs& a, hipStream_t s)
 {
     constexpr int BM = WM * TMW * 16;
     constexpr int BN = WN * TNW * 16;
-    dim3 grid((unsigned)((a.m_rows + BM - 1) / BM), (unsigned)((a.n + BN - 1) / BN));
-    hipLaunchKernelGGL((conv_mfma_lp<T, WM, WN, TMW, TNW, TAPS, EPI>), grid, dim3(WM * WN * 64), 0, s, a);
+    const unsigned m_tiles = (unsigned)((a.m_rows + BM - 1) / BM);
+    const unsigned n_tiles = (unsigned)((a.n + BN - 1) / BN);
+    dim3 grid((m_tiles + kXcds - 1) / kXcds * kXcds * n_tiles);
+    hipLaunchKernelGGL((conv_mfma_lp<T, WM, WN, TMW, TNW, KC, PF, TAPS, EPI>), grid, dim3(WM * WN * 64), 0, s, a);
     return hipGetLastError();
 }
 
-struct Variant { int wm, wn, tmw, tnw; };
+// Tile-shape / staging variants; all give identical bits.
+struct Variant { int wm, wn, tmw, tnw, kc, pf; };
 constexpr Variant kVariants[] = {
-    {4, 1, 4, 2},   // 256 x 32
-    {4, 1, 4, 4},   // 256 x 64
-    {2, 2, 4, 4},   // 128 x 128
-    {4, 2, 4, 4},   // 256 x 128 (512 threads)
-    {4, 1, 2, 4},   // 128 x 64
-    {2, 1, 4, 2},   // 128 x 32 (128 threads)
+    {4, 1, 4, 2, 32, 0},   //  0: 256 x 32
+    {4, 1, 4, 4, 32, 0},   //  1: 256 x 64
+    {2, 2, 4, 4, 32, 0},   //  2: 128 x 128
+    {4, 2, 4, 4, 32, 0},   //  3: 256 x 128 (512 threads)
+    {4, 1, 2, 4, 32, 0},   //  4: 128 x 64
+    {2, 1, 4, 2, 32, 0},   //  5: 128 x 32 (128 threads)
+    {4, 2, 4, 4, 32, 1},   //  6: 256 x 128, register prefetch
+    {4, 2, 4, 4, 64, 0},   //  7: 256 x 128, 64-channel stages
+    {4, 1, 4, 2, 64, 0},   //  8: 256 x 32, 64-channel stages
+    {4, 1, 4, 4, 64, 1},   //  9: 256 x 64, 64-channel stages, prefetch
+    {2, 2, 4, 4, 32, 1},   // 10: 128 x 128, prefetch
+    {4, 1, 4, 2, 32, 1},   // 11: 256 x 32, prefetch
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-#define PVF_LP_CASE(V)                                                                                       \
-    case V:                                                                                                  \
-        return run<T, kVariants[V].wm, kVariants[V].wn, kVariants[V].tmw, kVariants[V].tnw, TAPS, EPI>(a, s);
+#define PVF_LP_CASE(V)                                                                                     \
+    case V:                                                                                                \
+        return run<T, kVariants[V].wm, kVariants[V].wn, kVariants[V].tmw, kVariants[V].tnw, kVariants[V].kc, \
+                   kVariants[V].pf, TAPS, EPI>(a, s);
 
 template <class T, int TAPS, int EPI>
 hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
@@ -237,6 +329,7 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
         switch (v) {
             PVF_LP_CASE(0)
             PVF_LP_CASE(5)
+            PVF_LP_CASE(11)
         default: return hipErrorInvalidValue;
         }
     } else {
@@ -247,6 +340,12 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_LP_CASE(3)
             PVF_LP_CASE(4)
             PVF_LP_CASE(5)
+            PVF_LP_CASE(6)
+            PVF_LP_CASE(7)
+            PVF_LP_CASE(8)
+            PVF_LP_CASE(9)
+            PVF_LP_CASE(10)
+            PVF_LP_CASE(11)
         default: return hipErrorInvalidValue;
         }
     }
@@ -271,22 +370,25 @@ hipError_t launch_typed(const ConvArgs& a, int taps, Epi epi, int v, hipStream_t
 
 int lp_variant_count() { return kNumVariants; }
 
-bool lp_variant_ok(int v, int n, int taps, Epi epi)
+bool lp_variant_ok(int v, int n, int cin, int taps, Epi epi)
 {
     if (v < 0 || v >= kNumVariants) return false;
     (void)taps;
     const Variant& x = kVariants[v];
     const int bn = x.wn * x.tnw * 16;
-    if (epi == EPI_HEAD) return (v == 0 || v == 5) && bn == n;
+    if (cin % x.kc != 0) return false;
+    if (epi == EPI_HEAD) return (v == 0 || v == 5 || v == 11) && bn == n;
     return bn <= (n < 32 ? 32 : n);
 }
 
-int lp_default_variant(int n, int taps, Epi epi)
+// Defaults from a BF16 sweep on MI355X at 1000 events.
+int lp_default_variant(int n, int cin, int taps, Epi epi)
 {
-    (void)taps;
-    if (epi == EPI_HEAD || n <= 32) return 0;
-    if (n <= 64) return 1;
-    return 2;
+    if (epi == EPI_HEAD) return 0;
+    if (epi == EPI_CONVT && taps == 1) return n >= 128 ? 6 : 4;
+    if (n <= 32) return 11;
+    if (n <= 64) return cin <= 32 ? 4 : 11;
+    return 3;
 }
 
 std::string lp_kernel_name(int dtype, int v, int taps, Epi epi)
@@ -294,12 +396,13 @@ std::string lp_kernel_name(int dtype, int v, int taps, Epi epi)
     const Variant& x = kVariants[v];
     return std::string("conv_mfma_lp<") + (dtype == PVF_BF16 ? "__bf16" : "_Float16") + ", " +
            std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " + std::to_string(x.tmw) + ", " +
-           std::to_string(x.tnw) + ", " + std::to_string(taps) + ", " + std::to_string((int)epi) + ">";
+           std::to_string(x.tnw) + ", " + std::to_string(x.kc) + ", " + std::to_string(x.pf) + ", " +
+           std::to_string(taps) + ", " + std::to_string((int)epi) + ">";
 }
 
 hipError_t launch_conv_lp(int dtype, const ConvArgs& a, int taps, Epi epi, int v, hipStream_t s)
 {
-    if (a.cin % KC != 0 || a.m_rows <= 0 || !lp_variant_ok(v, a.n, taps, epi)) return hipErrorInvalidValue;
+    if (a.cin % 32 != 0 || a.m_rows <= 0 || !lp_variant_ok(v, a.n, a.cin, taps, epi)) return hipErrorInvalidValue;
     if (epi == EPI_CONVT && a.cout % 8 != 0) return hipErrorInvalidValue;
     if (dtype == PVF_BF16) return launch_typed<__bf16>(a, taps, epi, v, s);
     if (dtype == PVF_FP16) return launch_typed<_Float16>(a, taps, epi, v, s);

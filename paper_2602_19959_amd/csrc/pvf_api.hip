@@ -336,7 +336,7 @@ struct pvf_engine {
     hipStream_t stream = nullptr;
     std::vector<std::string> names;      // one per launch of pvf_execute
     std::vector<std::string> kernels;    // kernel instance of each launch
-    struct ConvLaunch { int n = 0, taps = 0; Epi epi = EPI_STORE; int variant = -1; };
+    struct ConvLaunch { int n = 0, cin = 0, taps = 0; Epi epi = EPI_STORE; int variant = -1; };
     std::vector<ConvLaunch> conv;        // per launch; variant -1 = not a conv launch
     std::vector<hipEvent_t> events;      // launch boundaries when profiling
     bool profiling = false;
@@ -359,12 +359,13 @@ void build_names(pvf_engine* e)
         e->kernels.push_back(kernel);
         e->conv.push_back({});
     };
-    auto conv = [&](const std::string& name, int gemm_n, int taps, Epi epi) {
+    auto conv = [&](const std::string& name, int gemm_n, int cin, int taps, Epi epi) {
         pvf_engine::ConvLaunch c;
         c.n = gemm_n;
+        c.cin = cin;
         c.taps = taps;
         c.epi = epi;
-        c.variant = conv_default_variant(e->spec.compute_dtype, gemm_n, taps, epi);
+        c.variant = conv_default_variant(e->spec.compute_dtype, gemm_n, cin, taps, epi);
         e->names.push_back(name);
         e->kernels.push_back(conv_kernel_name(e->spec.compute_dtype, c.variant, taps, epi));
         e->conv.push_back(c);
@@ -374,15 +375,15 @@ void build_names(pvf_engine* e)
         const std::string L = std::to_string(l);
         const int C = c0 << l;
         if (l == 0) plain("enc0.c1", "first_conv");
-        else conv("enc" + L + ".c1", C, kTaps, EPI_STORE);
-        conv("enc" + L + ".c2", C, kTaps, l < n - 1 ? EPI_POOL : EPI_STORE);
+        else conv("enc" + L + ".c1", C, C / 2, kTaps, EPI_STORE);
+        conv("enc" + L + ".c2", C, C, kTaps, l < n - 1 ? EPI_POOL : EPI_STORE);
     }
     for (int l = n - 2; l >= 0; --l) {
         const std::string L = std::to_string(l);
         const int C = c0 << l;
-        conv("up" + L, 2 * C, 1, EPI_CONVT);
-        conv("dec" + L + ".c1", C, kTaps, EPI_STORE);
-        conv(l == 0 ? "dec0.c2+head" : "dec" + L + ".c2", C, kTaps, l == 0 ? EPI_HEAD : EPI_STORE);
+        conv("up" + L, 2 * C, 2 * C, 1, EPI_CONVT);
+        conv("dec" + L + ".c1", C, 2 * C, kTaps, EPI_STORE);
+        conv(l == 0 ? "dec0.c2+head" : "dec" + L + ".c2", C, C, kTaps, l == 0 ? EPI_HEAD : EPI_STORE);
     }
     plain("peaks", "peak_finder");
 }
@@ -711,7 +712,7 @@ pvf_status pvf_set_launch_variant(pvf_engine* eng, int i, int v)
 {
     if (!eng || i < 0 || i >= (int)eng->conv.size() || eng->conv[i].variant < 0) return PVF_ERR_INVALID_ARGUMENT;
     auto& c = eng->conv[i];
-    if (!conv_variant_ok(eng->spec.compute_dtype, v, c.n, c.taps, c.epi)) return PVF_ERR_INVALID_ARGUMENT;
+    if (!conv_variant_ok(eng->spec.compute_dtype, v, c.n, c.cin, c.taps, c.epi)) return PVF_ERR_INVALID_ARGUMENT;
     c.variant = v;
     eng->kernels[i] = conv_kernel_name(eng->spec.compute_dtype, v, c.taps, c.epi);
     return PVF_OK;
@@ -735,7 +736,7 @@ pvf_status pvf_autotune(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertice
         for (int i = 0; i < nl; ++i) {
             auto& c = eng->conv[i];
             if (c.variant < 0) continue;
-            if (conv_variant_ok(eng->spec.compute_dtype, v, c.n, c.taps, c.epi)) { c.variant = v; any = true; }
+            if (conv_variant_ok(eng->spec.compute_dtype, v, c.n, c.cin, c.taps, c.epi)) { c.variant = v; any = true; }
             else c.variant = saved[i].variant;
         }
         if (!any) continue;

@@ -20,6 +20,7 @@ constexpr int kTaps = 5;          // UNet conv kernel size
 constexpr int kGuard = 2;         // zero rows before and after each event
 constexpr int kMaxLevels = 6;
 constexpr size_t kAlign = 256;
+constexpr int kXcds = 8;          // MI355X: workgroups go round-robin over 8 XCDs
 
 // Activation layout: channels-last, one block of R = L + 2*kGuard rows per
 // event, rows [kGuard, kGuard + L) hold positions 0..L-1 and the guard rows
@@ -149,8 +150,8 @@ hipError_t launch_first_conv(const FirstConvArgs& a, int dtype, hipStream_t s);
 // the compute dtype; all variants of a dtype give identical bits.
 hipError_t launch_conv(int dtype, const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s);
 int conv_variant_count(int dtype);
-bool conv_variant_ok(int dtype, int variant, int n, int taps, Epi epi);
-int conv_default_variant(int dtype, int n, int taps, Epi epi);
+bool conv_variant_ok(int dtype, int variant, int n, int cin, int taps, Epi epi);
+int conv_default_variant(int dtype, int n, int cin, int taps, Epi epi);
 std::string conv_kernel_name(int dtype, int variant, int taps, Epi epi);
 
 // per-precision implementations behind the functions above
@@ -161,8 +162,8 @@ int f32_default_variant(int n, int taps, Epi epi);
 std::string f32_kernel_name(int variant, int taps, Epi epi);
 hipError_t launch_conv_lp(int dtype, const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s);
 int lp_variant_count();
-bool lp_variant_ok(int variant, int n, int taps, Epi epi);
-int lp_default_variant(int n, int taps, Epi epi);
+bool lp_variant_ok(int variant, int n, int cin, int taps, Epi epi);
+int lp_default_variant(int n, int cin, int taps, Epi epi);
 std::string lp_kernel_name(int dtype, int variant, int taps, Epi epi);
 
 inline int act_bytes(int dtype) { return dtype == PVF_FP32 ? 4 : 2; }
