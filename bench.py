@@ -123,6 +123,43 @@ def cpu_baseline(batch, w, target_s):
                       f"{dt:.1f} s wall on {cpu}"}
 
 
+def serve_bench(args):
+    """Continuous-batching serving: capacity with every request queued at
+    once, then Poisson arrivals at fractions of that capacity."""
+    import numpy as np
+    from paper_2602_19959_amd.serve import Server, poisson_requests
+    from synth import make_events, make_weights, weights_to_blob
+
+    blob = weights_to_blob(make_weights(args.seed))
+    pool_events = make_events(8000, seed=args.seed + 1, mix="lognormal")
+    srv = Server(blob, pool_bytes=int(args.pool_gb * (1 << 30)), lanes=args.lanes, compute_dtype=args.dtype)
+    print(f"[serve] {args.dtype} pool {args.pool_gb} GB, {args.lanes} lanes x {srv.lane_events} events",
+          file=sys.stderr, flush=True)
+    warm = poisson_requests(1e9, 4, args.seed + 7, pool_events)
+    srv.run(warm, realtime=False)
+    reqs = poisson_requests(1e9, args.serve_requests, args.seed + 8, pool_events)
+    cap = srv.run(reqs, realtime=False).summary()
+    print(f"[serve] capacity {cap['events_per_s']:.0f} events/s", file=sys.stderr, flush=True)
+    mean_size = float(np.mean([r.n_events for r in reqs]))
+    loads = {}
+    for f in [float(x) for x in args.serve_loads.split(",")]:
+        rate = f * cap["events_per_s"] / mean_size
+        rq = poisson_requests(rate, args.serve_requests, args.seed + 9, pool_events)
+        loads[f"{f:.2f}"] = dict(srv.run(rq, realtime=True).summary(), offered_requests_per_s=rate)
+        print(f"[serve] load {f:.2f}: {loads[f'{f:.2f}']}", file=sys.stderr, flush=True)
+    srv.close()
+    print(json.dumps({
+        "metric": METRIC, "value": cap["events_per_s"], "unit": "events/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": DTYPE_TAG[args.dtype], "data": "synthetic",
+        "config": {"workload": f"serving: slices of U{{100..2000}} events (log-normal track counts), "
+                               f"Poisson arrivals, {args.pool_gb} GB HBM pool, {args.lanes} lanes of "
+                               f"{srv.lane_events} events, continuous batching",
+                   "requests": args.serve_requests},
+        "capacity": cap, "loads": loads,
+        "budget_us_per_event": 400.0,
+    }), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +170,18 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--dtype", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--schedule", default="queue", choices=["queue", "block"],
+                    help="track stage: persistent work queue (default) or one block per event")
+    ap.add_argument("--graph", action="store_true",
+                    help="time replays of one captured HIP graph (per-launch times then come from an "
+                         "eager pass after the timed region)")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving benchmark instead: Poisson arrivals of event slices into a fixed HBM pool "
+                         "with continuous batching; prints one JSON line with latency percentiles per load")
+    ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
+    ap.add_argument("--pool-gb", type=float, default=8.0)
+    ap.add_argument("--lanes", type=int, default=2)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in tile shapes instead of timing the variants first")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -156,12 +205,17 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs an MI355X", file=sys.stderr)
         sys.exit(1)
+    if args.serve:
+        serve_bench(args)
+        return
     E = args.events
     batch = make_events(E, seed=args.seed, mix=args.mix)
     w = make_weights(args.seed)
     T = np.diff(batch.offsets)
-    spec = pv.default_spec(max_events=E, max_tracks_total=int(max(T.sum(), 1)), compute_dtype=args.dtype)
+    spec = pv.default_spec(max_events=E, max_tracks_total=int(max(T.sum(), 1)), compute_dtype=args.dtype,
+                           max_tracks_per_event=max(1500, int(T.max())))
     eng = pv.Engine(weights_to_blob(w), spec)
+    eng.set_track_schedule(args.schedule == "queue")
     feat, off = pv.upload_events(batch)
     out = eng.alloc_outputs(E, with_prob=False)
     names = eng.launch_names()
@@ -189,25 +243,49 @@ def main():
     eng.synchronize()
     torch.cuda.synchronize()
 
-    eng.profile(True)
     per_launch = [[] for _ in names]
     step_ms = []
     s = eng.stream
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record(s)
-        eng.execute(feat, off, out)
-        ev1.record(s)
-        s.synchronize()
-        step_ms.append(ev0.elapsed_time(ev1))
-        for i, ms in enumerate(eng.profile_read()):
-            per_launch[i].append(ms)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    eng.profile(False)
+    if args.graph:
+        eng.graph_capture(feat, off, out)
+        eng.graph_launch()
+        eng.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(s)
+            eng.graph_launch()
+            ev1.record(s)
+            s.synchronize()
+            step_ms.append(ev0.elapsed_time(ev1))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        eng.profile(True)                       # per-launch split from eager passes
+        for _ in range(3):
+            eng.execute(feat, off, out)
+            s.synchronize()
+            for i, ms in enumerate(eng.profile_read()):
+                per_launch[i].append(ms)
+        eng.profile(False)
+    else:
+        eng.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(s)
+            eng.execute(feat, off, out)
+            ev1.record(s)
+            s.synchronize()
+            step_ms.append(ev0.elapsed_time(ev1))
+            for i, ms in enumerate(eng.profile_read()):
+                per_launch[i].append(ms)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        eng.profile(False)
 
     host = out.to_host()
     if np.any(host["status"] & (pv.EV_TOO_MANY_TRACKS | pv.EV_BAD_INPUT)):
@@ -272,7 +350,8 @@ def main():
         "data": "synthetic: seeded events (Poisson(5.6) PVs, Poisson(180) tracks) and seeded He-init weights",
         "config": {"workload": f"{E} events per batch, {args.mix} track counts (mean {T.mean():.1f}), "
                                f"UNet 32/64/128/256 over 4000 bins, {args.dtype.upper()} convolutions (FP32 accumulate), seed {args.seed}",
-                   "events_per_batch": E, "tracks_total": int(T.sum())},
+                   "events_per_batch": E, "tracks_total": int(T.sum()), "max_tracks": int(T.max()),
+                   "track_schedule": args.schedule, "hip_graph": bool(args.graph)},
         "p50_us_per_event": p50,
         "p99_us_per_event": p99,
         "stages_ms": stage,

@@ -166,6 +166,26 @@ pvf_status pvf_destroy(pvf_engine *eng);
 /* Static English text of a status code. */
 const char *pvf_status_string(pvf_status s);
 
+/* ---- scheduling and graphs ------------------------------------------------ */
+
+/* Track-stage schedule.  persistent = 1 (default): a counting-sort kernel
+ * orders the batch's events by descending track count and a fixed grid of
+ * blocks (two per compute unit) takes them from a device work queue, so
+ * heavy-tailed batches do not end on their largest events; persistent = 0:
+ * one block per event.  Results are identical either way. */
+pvf_status pvf_set_track_schedule(pvf_engine *eng, int persistent);
+
+/* Capture the whole path for this batch view (its pointers and counts are
+ * frozen into the graph) into one HIP graph owned by the engine, replacing
+ * any earlier one.  Nothing runs during capture.  Refill the same input
+ * buffers and call pvf_graph_launch to run it: one launch on the engine's
+ * stream instead of one per kernel. */
+pvf_status pvf_graph_capture(pvf_engine *eng, const pvf_tracks *tracks, const pvf_vertices *out);
+
+/* Replay the captured graph on the engine's stream (asynchronous).
+ * PVF_ERR_INVALID_ARGUMENT if nothing was captured. */
+pvf_status pvf_graph_launch(pvf_engine *eng);
+
 /* ---- instrumentation (not on the hot path) ---------------------------- */
 
 /* Number of kernel launches one pvf_execute enqueues for this engine. */

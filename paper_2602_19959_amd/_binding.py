@@ -118,6 +118,12 @@ def load_library() -> C.CDLL:
     lib.pvf_set_launch_variant.restype = C.c_int
     lib.pvf_autotune.argtypes = [vp, C.POINTER(Tracks), C.POINTER(Vertices), C.c_int]
     lib.pvf_autotune.restype = C.c_int
+    lib.pvf_set_track_schedule.argtypes = [vp, C.c_int]
+    lib.pvf_set_track_schedule.restype = C.c_int
+    lib.pvf_graph_capture.argtypes = [vp, C.POINTER(Tracks), C.POINTER(Vertices)]
+    lib.pvf_graph_capture.restype = C.c_int
+    lib.pvf_graph_launch.argtypes = [vp]
+    lib.pvf_graph_launch.restype = C.c_int
     lib.pvf_profile_enable.argtypes = [vp, C.c_int]
     lib.pvf_profile_enable.restype = C.c_int
     lib.pvf_profile_read.argtypes = [vp, C.POINTER(C.c_float), C.c_int]
@@ -300,6 +306,22 @@ class Engine:
         self.stream.wait_stream(t.cuda.current_stream(self.device))
         _check("pvf_autotune", self.lib.pvf_autotune(self.handle, C.byref(tr), C.byref(v), reps))
         return self.variants()
+
+    def set_track_schedule(self, persistent: bool):
+        _check("pvf_set_track_schedule", self.lib.pvf_set_track_schedule(self.handle, 1 if persistent else 0))
+
+    def graph_capture(self, feat, offsets, out: Outputs):
+        """Freeze this batch view (buffers and counts) into one HIP graph."""
+        tr, v = self._views(feat, offsets, out)
+        self._graph_refs = (feat, offsets, out)      # the graph holds these pointers
+        self.synchronize()
+        _check("pvf_graph_capture", self.lib.pvf_graph_capture(self.handle, C.byref(tr), C.byref(v)))
+
+    def graph_launch(self):
+        """Replay the captured graph on the engine's stream (after the current stream's work)."""
+        t = self._torch
+        self.stream.wait_stream(t.cuda.current_stream(self.device))
+        _check("pvf_graph_launch", self.lib.pvf_graph_launch(self.handle))
 
     def profile(self, on: bool = True):
         _check("pvf_profile_enable", self.lib.pvf_profile_enable(self.handle, 1 if on else 0))

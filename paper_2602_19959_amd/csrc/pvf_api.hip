@@ -77,6 +77,8 @@ void make_plan(const pvf_spec* s, size_t weight_floats, Plan* p)
     p->zero_end = off;
     p->prob = take(E * p->lv[0].L * sizeof(float));
     p->flags = take(E * sizeof(int32_t));
+    p->order = take(E * sizeof(int32_t));
+    p->queue = take(((size_t)s->max_tracks_per_event + 3) * sizeof(int32_t));
     p->total = off;
 }
 
@@ -340,6 +342,10 @@ struct pvf_engine {
     std::vector<ConvLaunch> conv;        // per launch; variant -1 = not a conv launch
     std::vector<hipEvent_t> events;      // launch boundaries when profiling
     bool profiling = false;
+    int track_blocks = 0;                // > 0: persistent work-queue track stage
+    int cu_count = 0;
+    hipGraph_t graph = nullptr;          // pvf_graph_capture
+    hipGraphExec_t graph_exec = nullptr;
 };
 
 namespace {
@@ -370,7 +376,7 @@ void build_names(pvf_engine* e)
         e->kernels.push_back(conv_kernel_name(e->spec.compute_dtype, c.variant, taps, epi));
         e->conv.push_back(c);
     };
-    plain("track", "track_stage");
+    plain("track", e->track_blocks > 0 ? "track_stage_queue" : "track_stage");
     for (int l = 0; l < n; ++l) {
         const std::string L = std::to_string(l);
         const int C = c0 << l;
@@ -453,7 +459,9 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
     ta.x0 = at<float>(eng, P.x0);
     ta.r0 = P.lv[0].R;
     ta.flags = flags;
-    check(launch_track(ta, E, s));
+    ta.order = at<int32_t>(eng, P.order);
+    ta.queue_counter = at<int32_t>(eng, P.queue);
+    check(launch_track(ta, E, eng->track_blocks, at<int32_t>(eng, P.queue) + 1, s));
 
     // ---- encoder
     FirstConvArgs fa{};
@@ -598,6 +606,13 @@ pvf_status pvf_init(const pvf_spec* spec, const void* blob, size_t blob_bytes, v
     for (int k = 0; k < kFeat; ++k) { e->shift[k] = b.shift[k]; e->scale[k] = b.scale[k]; }
     e->arena = static_cast<char*>(d_arena);
     e->stream = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&e->cu_count, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        delete e;
+        return PVF_ERR_DEVICE;
+    }
+    e->track_blocks = 2 * e->cu_count;   // two 64 KB-LDS blocks per CU
     build_names(e);
 
     std::vector<float> packed;
@@ -661,6 +676,8 @@ pvf_status pvf_execute_on(pvf_engine* eng, const pvf_tracks* tr, const pvf_verti
 pvf_status pvf_destroy(pvf_engine* eng)
 {
     if (!eng) return PVF_ERR_INVALID_ARGUMENT;
+    if (eng->graph_exec) (void)hipGraphExecDestroy(eng->graph_exec);
+    if (eng->graph) (void)hipGraphDestroy(eng->graph);
     for (hipEvent_t ev : eng->events) (void)hipEventDestroy(ev);
     delete eng;
     return PVF_OK;
@@ -755,6 +772,51 @@ pvf_status pvf_autotune(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertice
     }
     if (!was) pvf_profile_enable(eng, 0);
     return st;
+}
+
+pvf_status pvf_set_track_schedule(pvf_engine* eng, int persistent)
+{
+    if (!eng || (persistent != 0 && persistent != 1)) return PVF_ERR_INVALID_ARGUMENT;
+    eng->track_blocks = persistent ? 2 * eng->cu_count : 0;
+    eng->kernels[0] = persistent ? "track_stage_queue" : "track_stage";
+    return PVF_OK;
+}
+
+pvf_status pvf_graph_capture(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* out)
+{
+    pvf_status st = check_call(eng, tr, out);
+    if (st != PVF_OK) return st;
+    if (tr->n_events == 0) return PVF_ERR_INVALID_ARGUMENT;
+    if (eng->graph_exec) { (void)hipGraphExecDestroy(eng->graph_exec); eng->graph_exec = nullptr; }
+    if (eng->graph) { (void)hipGraphDestroy(eng->graph); eng->graph = nullptr; }
+    const bool was = eng->profiling;
+    eng->profiling = false;                   // no event records inside the graph
+    if (hipStreamBeginCapture(eng->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        eng->profiling = was;
+        return PVF_ERR_DEVICE;
+    }
+    st = enqueue(eng, tr, out, eng->stream);
+    hipGraph_t g = nullptr;
+    const hipError_t end = hipStreamEndCapture(eng->stream, &g);
+    eng->profiling = was;
+    if (st != PVF_OK || end != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return st != PVF_OK ? st : PVF_ERR_DEVICE;
+    }
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return PVF_ERR_DEVICE;
+    }
+    eng->graph = g;
+    eng->graph_exec = x;
+    return PVF_OK;
+}
+
+pvf_status pvf_graph_launch(pvf_engine* eng)
+{
+    if (!eng || !eng->graph_exec) return PVF_ERR_INVALID_ARGUMENT;
+    return hipGraphLaunch(eng->graph_exec, eng->stream) == hipSuccess ? PVF_OK : PVF_ERR_DEVICE;
 }
 
 pvf_status pvf_profile_enable(pvf_engine* eng, int on)

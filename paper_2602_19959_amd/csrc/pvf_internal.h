@@ -48,6 +48,8 @@ struct Plan {
     size_t d[kMaxLevels] = {};     // [E][Rl][Cl]     decoder conv2 out (1 <= l <= n-2), deepest conv2 (l = n-1)
     size_t prob = 0;               // [E][L0] float
     size_t flags = 0;              // [E] int32 track-stage status
+    size_t order = 0;              // [E] int32 event order of the track work queue
+    size_t queue = 0;              // int32 ticket counter + order histogram
     size_t zero_begin = 0, zero_end = 0;   // region cleared at init
     size_t total = 0;
 };
@@ -107,6 +109,8 @@ struct TrackArgs {
     float* x0;               // [E][R0]
     int r0;
     int32_t* flags;          // [E]
+    int32_t* order;          // [E] queue order (persistent form), or null
+    int32_t* queue_counter;  // ticket counter (persistent form), or null
 };
 
 struct FirstConvArgs {
@@ -144,7 +148,10 @@ struct GatherArgs {          // debug copy of an internal activation
     int64_t count;
 };
 
-hipError_t launch_track(const TrackArgs& a, int n_events, hipStream_t s);
+// persistent_blocks > 0: the work-queue form (order kernel + persistent
+// blocks); order_scratch holds max_tracks + 2 ints.  Otherwise one block per event.
+hipError_t launch_track(const TrackArgs& a, int n_events, int persistent_blocks, int* order_scratch,
+                        hipStream_t s);
 hipError_t launch_first_conv(const FirstConvArgs& a, int dtype, hipStream_t s);
 // Conv launches run one of several tile-shape variants of the kernel for
 // the compute dtype; all variants of a dtype give identical bits.

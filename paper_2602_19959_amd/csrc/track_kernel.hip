@@ -34,9 +34,8 @@ __device__ __forceinline__ float softplus(float x)
     return fmaxf(x, 0.f) + log1pf(expf(-fabsf(x)));
 }
 
-__global__ __launch_bounds__(NT) void track_stage(TrackArgs a)
+__device__ void track_event(const TrackArgs& a, int e, float* smem)
 {
-    extern __shared__ float smem[];
     const int n_bins = a.n_out * a.n_intervals;
     float* H = smem;                                  // [n_bins]
     float* hb = H + n_bins;                           // [NT][HP]
@@ -45,7 +44,6 @@ __global__ __launch_bounds__(NT) void track_stage(TrackArgs a)
     __shared__ int dropped_any;
 
     const int tid = threadIdx.x;
-    const int e = blockIdx.x;
     const int op = a.n_out + 1;
 
     for (int b = tid; b < n_bins; b += NT) H[b] = 0.f;
@@ -158,6 +156,79 @@ __global__ __launch_bounds__(NT) void track_stage(TrackArgs a)
     float* x0 = a.x0 + (int64_t)e * a.r0 + kGuard;
     for (int b = tid; b < n_bins; b += NT) x0[b] = a.s_in * H[b];
     if (tid == 0) a.flags[e] = status | (dropped_any ? PVF_EV_TRACKS_DROPPED : 0);
+    __syncthreads();   // the block's LDS is reused by its next event
+}
+
+// One block per event.
+__global__ __launch_bounds__(NT) void track_stage(TrackArgs a)
+{
+    extern __shared__ float smem[];
+    track_event(a, blockIdx.x, smem);
+}
+
+// Persistent form for uneven track counts: a fixed grid of blocks takes
+// tickets from a device counter; ticket k is the k-th event in descending
+// track count (largest first, so the long events do not end the launch
+// alone).  Every event's result is the same whichever block computes it.
+__global__ __launch_bounds__(NT) void track_stage_queue(TrackArgs a, int n_events)
+{
+    extern __shared__ float smem[];
+    __shared__ int ticket;
+    for (;;) {
+        if (threadIdx.x == 0) ticket = atomicAdd(a.queue_counter, 1);
+        __syncthreads();
+        const int k = ticket;
+        __syncthreads();
+        if (k >= n_events) break;
+        track_event(a, a.order[k], smem);
+    }
+}
+
+// Queue order: a counting sort of the events by descending track count
+// (counts clamped to [0, max_tracks + 1]; malformed offsets count 0), in one
+// block.  Events of equal count may come out in any order: the order only
+// schedules work, it never changes a result.  The kernel also resets the
+// queue counter for the launch that follows, so no memset is needed (safe
+// under graph capture).  hist: max_tracks + 2 ints of scratch.
+constexpr int kOrderThreads = 1024;
+__global__ __launch_bounds__(kOrderThreads) void track_order(TrackArgs a, int n_events, int* hist)
+{
+    __shared__ int part[kOrderThreads];
+    const int tid = threadIdx.x;
+    const int nb = a.max_tracks + 2;
+    auto bucket = [&](int e) {           // descending count -> ascending bucket
+        const int64_t beg = a.offsets[e], end = a.offsets[e + 1];
+        const int64_t t = (beg < 0 || end < beg || end > a.n_tracks_total) ? 0 : end - beg;
+        return nb - 1 - (int)(t > a.max_tracks ? a.max_tracks + 1 : t);
+    };
+    for (int b = tid; b < nb; b += kOrderThreads) hist[b] = 0;
+    __syncthreads();
+    for (int e = tid; e < n_events; e += kOrderThreads) atomicAdd(&hist[bucket(e)], 1);
+    __syncthreads();
+    // exclusive scan of hist: each thread sums a run of buckets, the runs are
+    // scanned in LDS, then each thread rewrites its run
+    const int per = (nb + kOrderThreads - 1) / kOrderThreads;
+    const int b0 = tid * per < nb ? tid * per : nb;
+    const int b1 = b0 + per < nb ? b0 + per : nb;
+    int sum = 0;
+    for (int b = b0; b < b1; ++b) sum += hist[b];
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < kOrderThreads; off <<= 1) {
+        const int v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int run = part[tid] - sum;
+    for (int b = b0; b < b1; ++b) {
+        const int c = hist[b];
+        hist[b] = run;
+        run += c;
+    }
+    if (tid == 0) *a.queue_counter = 0;
+    __syncthreads();
+    for (int e = tid; e < n_events; e += kOrderThreads) a.order[atomicAdd(&hist[bucket(e)], 1)] = e;
 }
 
 }  // namespace
@@ -167,15 +238,27 @@ static size_t track_stage_lds_bytes(int n_out, int n_intervals)
     return sizeof(float) * ((size_t)n_out * n_intervals + NT * HP + SUB * (n_out + 1)) + sizeof(int) * NT;
 }
 
-hipError_t launch_track(const TrackArgs& a, int n_events, hipStream_t s)
+hipError_t launch_track(const TrackArgs& a, int n_events, int persistent_blocks, int* order_scratch,
+                        hipStream_t s)
 {
     const size_t lds = track_stage_lds_bytes(a.n_out, a.n_intervals);
     if (lds > 64 * 1024) {
         hipError_t err = hipFuncSetAttribute((const void*)track_stage,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (err == hipSuccess)
+            err = hipFuncSetAttribute((const void*)track_stage_queue, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds);
         if (err != hipSuccess) return err;
     }
-    hipLaunchKernelGGL(track_stage, dim3(n_events), dim3(NT), lds, s, a);
+    if (persistent_blocks <= 0 || !a.order || !a.queue_counter) {
+        hipLaunchKernelGGL(track_stage, dim3(n_events), dim3(NT), lds, s, a);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(track_order, dim3(1), dim3(kOrderThreads), 0, s, a, n_events, order_scratch);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    const int blocks = persistent_blocks < n_events ? persistent_blocks : n_events;
+    hipLaunchKernelGGL(track_stage_queue, dim3(blocks), dim3(NT), lds, s, a, n_events);
     return hipGetLastError();
 }
 

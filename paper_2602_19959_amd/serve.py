@@ -1,0 +1,299 @@
+"""Continuous-batching request loop over the C ABI.
+
+The trigger framework of the paper (Section 3) runs inference on a fixed
+memory pool with work enqueued on framework streams.  This loop serves
+*requests* -- slices of events arriving over time -- on one GPU:
+
+* a fixed HBM pool budget holds the engines' arenas plus every admitted
+  request's device-resident state (its tracks, and its output buffers until
+  the results are read back); a request is admitted as soon as its state fits
+  in the pool, otherwise it waits;
+* several lanes (one engine = arena + stream each) run steps concurrently, so
+  work of different requests overlaps on the device;
+* continuous batching: whenever a lane is free it packs the next events from
+  the head of the admitted queue -- possibly the tail of one request and the
+  head of the next -- into one step of at most its capacity; a request can
+  span several steps and lanes;
+* a request completes when its last event's results are back on the host;
+  its latency is completion time minus arrival time.
+
+Every kernel is batch-invariant (fixed k order), so an event's results are
+the same bits whether it ran alone or packed with others.  PyTorch only
+provides device memory, streams, events and the copies that gather a step's
+inputs and scatter its outputs.
+"""
+
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from ._binding import Engine, arena_bytes, default_spec
+
+OUT_KEYS = ("n_vertices", "z", "peak_prob", "integral", "status", "bin")
+
+
+@dataclass
+class Request:
+    rid: int
+    batch: object                 # synth.EventBatch (host)
+    arrival: float                # seconds, loop clock
+    feat: object = None           # device float32 [9][T]
+    offsets: object = None        # device int32 [E+1]
+    out: dict = None              # device outputs per key, [E] or [E][max_peaks]
+    state_bytes: int = 0
+    next_event: int = 0           # first event not yet packed into a step
+    done_events: int = 0
+    t_admit: float = 0.0
+    t_done: float = 0.0
+    result: dict = None           # host copy of the outputs
+
+    @property
+    def n_events(self):
+        return self.batch.n_events
+
+
+@dataclass
+class _Step:
+    lane: int
+    pieces: list                  # (request, first event, count, first row in the step)
+    n_events: int
+    done_event: object = None     # torch.cuda.Event recorded after the step
+
+
+@dataclass
+class ServeStats:
+    latencies_s: list = field(default_factory=list)
+    sizes: list = field(default_factory=list)
+    t_first_arrival: float = 0.0
+    t_last_done: float = 0.0
+    steps: int = 0
+    max_pool_used: int = 0
+
+    def summary(self):
+        lat = np.array(self.latencies_s)
+        per_ev = lat / np.array(self.sizes)
+        total = int(np.sum(self.sizes))
+        span = self.t_last_done - self.t_first_arrival
+        return {
+            "requests": len(lat), "events": total, "steps": self.steps,
+            "events_per_s": total / span if span > 0 else float("nan"),
+            "slice_latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
+            "slice_latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
+            "us_per_event_p50": float(np.percentile(per_ev, 50) * 1e6),
+            "us_per_event_p99": float(np.percentile(per_ev, 99) * 1e6),
+            "max_pool_used_gb": self.max_pool_used / 1e9,
+        }
+
+
+class Server:
+    def __init__(self, weights_blob: bytes, pool_bytes: int = 8 << 30, lanes: int = 2,
+                 lane_events: int | None = None, compute_dtype: str = "bf16",
+                 max_tracks_per_event: int = 1500, max_peaks: int = 2000, device: str = "cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.pool_bytes = int(pool_bytes)
+        self.max_peaks = max_peaks
+        per_event_state = self._state_bytes_per_event(max_tracks_per_event=200)
+        if lane_events is None:
+            # half the pool for arenas, the rest for requests in flight
+            probe = default_spec(max_events=1, compute_dtype=compute_dtype, max_peaks_per_event=max_peaks)
+            a1 = arena_bytes(probe)
+            probe.max_events = 101
+            per_ev_arena = (arena_bytes(probe) - a1) / 100
+            lane_events = max(1, int(self.pool_bytes // 2 // lanes // (per_ev_arena + per_event_state)))
+        self.lane_events = lane_events
+        self.lanes = []
+        for _ in range(lanes):
+            spec = default_spec(max_events=lane_events, compute_dtype=compute_dtype,
+                                max_tracks_per_event=max_tracks_per_event, max_peaks_per_event=max_peaks,
+                                max_tracks_total=lane_events * max_tracks_per_event)
+            self.lanes.append(Engine(weights_blob, spec, device=device))
+        # per-lane step buffers, allocated once: gathered inputs and step outputs
+        self.step_out = [e.alloc_outputs(lane_events, with_prob=False) for e in self.lanes]
+        step_bytes = sum(v.numel() * v.element_size() for v in self.step_out[0].__dict__.values() if v is not None)
+        step_bytes += 36 * lane_events * max_tracks_per_event + 4 * (lane_events + 1)
+        self.arena_total = sum(e.arena_bytes for e in self.lanes) + lanes * step_bytes
+        if self.arena_total >= self.pool_bytes:
+            raise ValueError("pool budget too small for the lanes' arenas and step buffers")
+        self.copy_stream = torch.cuda.Stream(device=self.device)
+        self.pool_used = self.arena_total
+        self.busy = [None] * lanes            # _Step or None per lane
+
+    # -- accounting ----------------------------------------------------------
+    def _state_bytes_per_event(self, max_tracks_per_event):
+        return 36 * max_tracks_per_event + 4 + self.max_peaks * (8 + 4 + 8 + 4) + 8
+
+    def request_bytes(self, batch) -> int:
+        return int(batch.feat.nbytes + batch.offsets.nbytes + batch.n_events * (self.max_peaks * 24 + 8))
+
+    # -- request life cycle --------------------------------------------------
+    def _admit(self, r: Request, now: float):
+        t = self.torch
+        with t.cuda.stream(self.copy_stream):
+            r.feat = t.from_numpy(r.batch.feat).pin_memory().to(self.device, non_blocking=True)
+            r.offsets = t.from_numpy(r.batch.offsets).pin_memory().to(self.device, non_blocking=True)
+            E, mp = r.n_events, self.max_peaks
+            r.out = {
+                "n_vertices": t.zeros(E, dtype=t.int32, device=self.device),
+                "z": t.empty(E, mp, dtype=t.float64, device=self.device),
+                "peak_prob": t.empty(E, mp, dtype=t.float32, device=self.device),
+                "integral": t.empty(E, mp, dtype=t.float64, device=self.device),
+                "status": t.zeros(E, dtype=t.int32, device=self.device),
+                "bin": t.empty(E, mp, dtype=t.int32, device=self.device),
+            }
+        r.uploaded = t.cuda.Event()
+        r.uploaded.record(self.copy_stream)
+        r.state_bytes = self.request_bytes(r.batch)
+        r.t_admit = now
+        self.pool_used += r.state_bytes
+
+    def _launch_step(self, lane: int, queue):
+        """Pack up to lane_events events from the head of the queue into one step."""
+        t = self.torch
+        eng = self.lanes[lane]
+        pieces, rows = [], 0
+        for r in queue:
+            if rows >= self.lane_events:
+                break
+            take = min(r.n_events - r.next_event, self.lane_events - rows)
+            if take <= 0:
+                continue
+            pieces.append((r, r.next_event, take, rows))
+            r.next_event += take
+            rows += take
+        if not pieces:
+            return None
+        s = eng.stream
+        for r, _, _, _ in pieces:
+            s.wait_event(r.uploaded)
+        with t.cuda.stream(s):
+            feats, offs, base = [], [t.zeros(1, dtype=t.int32, device=self.device)], 0
+            for r, e0, n, _ in pieces:
+                a, b = int(r.batch.offsets[e0]), int(r.batch.offsets[e0 + n])
+                feats.append(r.feat[:, a:b])
+                offs.append(r.offsets[e0 + 1:e0 + n + 1] - a + base)
+                base += b - a
+            feat = t.cat(feats, dim=1).contiguous() if base > 0 else t.zeros(9, 0, dtype=t.float32, device=self.device)
+            off = t.cat(offs).contiguous()
+            full = self.step_out[lane]
+            out = type(full)(**{k: (None if v is None else v[:rows]) for k, v in full.__dict__.items()})
+            eng.execute(feat, off, out, stream=s)
+            for r, e0, n, row in pieces:
+                for k in OUT_KEYS:
+                    r.out[k][e0:e0 + n].copy_(getattr(out, k)[row:row + n])
+            ev = t.cuda.Event()
+            ev.record(s)
+        step = _Step(lane, pieces, rows, ev)
+        step._keep = (feat, off, out)
+        self.busy[lane] = step
+        return step
+
+    def _finish_step(self, step: _Step, now: float, done: list):
+        for r, e0, n, _ in step.pieces:
+            r.done_events += n
+            if r.done_events == r.n_events:
+                r.out_ready = step.done_event
+                done.append(r)
+
+    def _start_readback(self, r: Request):
+        """Queue the device-to-host copy of a finished request's outputs on the
+        copy stream (pinned host buffers, asynchronous)."""
+        t = self.torch
+        self.copy_stream.wait_event(r.out_ready)
+        r.host = {k: t.empty(v.shape, dtype=v.dtype, pin_memory=True) for k, v in r.out.items()}
+        with t.cuda.stream(self.copy_stream):
+            for k, v in r.out.items():
+                r.host[k].copy_(v, non_blocking=True)
+                v.record_stream(self.copy_stream)
+        r.readback = t.cuda.Event()
+        r.readback.record(self.copy_stream)
+
+    def _complete(self, r: Request):
+        r.result = {k: v.numpy() for k, v in r.host.items()}
+        r.t_done = time.perf_counter() - self.t0
+        r.feat = r.offsets = r.out = r.host = None
+        self.pool_used -= r.state_bytes
+
+    # -- the loop --------------------------------------------------------------
+    def run(self, requests: list, realtime: bool = True) -> ServeStats:
+        """Serve `requests` (arrival times in seconds from the start).  With
+        realtime=False every request counts as arrived at time 0."""
+        t = self.torch
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        waiting = collections.deque()          # arrived, not admitted (pool full)
+        queue = []                             # admitted, with events left to pack
+        reading = []                           # outputs on their way to the host
+        stats = ServeStats()
+        if not realtime:
+            for r in pending:
+                r.arrival = 0.0
+        self.t0 = time.perf_counter()
+        n_left = len(requests)
+        while n_left:
+            now = time.perf_counter() - self.t0
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            while waiting and self.pool_used + self.request_bytes(waiting[0].batch) <= self.pool_bytes:
+                r = waiting.popleft()
+                self._admit(r, now)
+                queue.append(r)
+            stats.max_pool_used = max(stats.max_pool_used, self.pool_used)
+            # retire finished steps; a request whose last event is done starts its readback
+            for lane, step in enumerate(self.busy):
+                if step is not None and step.done_event.query():
+                    self.busy[lane] = None
+                    finished = []
+                    self._finish_step(step, now, finished)
+                    for r in finished:
+                        self._start_readback(r)
+                        reading.append(r)
+            still = []
+            for r in reading:
+                if r.readback.query():
+                    self._complete(r)
+                    stats.latencies_s.append(r.t_done - r.arrival)
+                    stats.sizes.append(r.n_events)
+                    stats.t_last_done = r.t_done
+                    n_left -= 1
+                else:
+                    still.append(r)
+            reading = still
+            queue = [r for r in queue if r.next_event < r.n_events]
+            # fill free lanes
+            for lane in range(len(self.lanes)):
+                if self.busy[lane] is None and queue:
+                    if self._launch_step(lane, queue) is not None:
+                        stats.steps += 1
+                    queue = [r for r in queue if r.next_event < r.n_events]
+            if not queue and not waiting:
+                nxt = pending[0].arrival - (time.perf_counter() - self.t0) if pending else 0.0
+                time.sleep(min(1e-4, max(2e-5, nxt)))
+        t.cuda.synchronize()
+        stats.t_first_arrival = min(r.arrival for r in requests)
+        return stats
+
+    def close(self):
+        for e in self.lanes:
+            e.close()
+
+
+def poisson_requests(rate_hz: float, n: int, seed: int, pool, min_events: int = 100, max_events: int = 2000):
+    """n requests with Poisson arrivals at `rate_hz` (first at t = 0) and sizes
+    uniform in [min_events, max_events]; each slice is a run of consecutive
+    events cut from the pre-drawn batch `pool` (a synth.EventBatch), wrapping
+    around its end."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate_hz, n)
+    sizes = rng.integers(min_events, max_events + 1, n)
+    starts = rng.integers(0, pool.n_events, n)
+    t = np.cumsum(gaps) - gaps[0]
+    reqs = []
+    for i in range(n):
+        idx = [(int(starts[i]) + k) % pool.n_events for k in range(int(sizes[i]))]
+        reqs.append(Request(i, pool.subset(idx), float(t[i])))
+    return reqs

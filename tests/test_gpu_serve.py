@@ -1,0 +1,60 @@
+"""Continuous-batching serving: requests admitted into a fixed HBM pool,
+packed event by event into steps on two lanes whose work overlaps, must give
+every event the same bits as the slice run alone (FP32 and BF16 kernels are
+batch-invariant)."""
+
+import numpy as np
+import pytest
+
+from synth import make_events
+from tests.gpu_util import torch_cuda, blob, make_engine, run
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-serve]", *a, flush=True)
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+@pytest.mark.parametrize("realtime", [False, True])
+def test_results_same_alone_and_in_the_mix(dtype, realtime):
+    torch_cuda()
+    from paper_2602_19959_amd.serve import Server, poisson_requests
+    pool = make_events(400, seed=21, mix="lognormal")
+    reqs = poisson_requests(rate_hz=2000.0, n=12, seed=3, pool=pool, min_events=5, max_events=90)
+    srv = Server(blob(), pool_bytes=3 << 30, lanes=2, lane_events=64, compute_dtype=dtype)
+    stats = srv.run(reqs, realtime=realtime)
+    summ = stats.summary()
+    say(dtype, "realtime" if realtime else "all-at-once", summ)
+    assert summ["requests"] == 12 and stats.steps >= 3
+    assert max(r.n_events for r in reqs) > 64           # some request spans several steps
+    eng = make_engine(100, compute_dtype=dtype)
+    for r in reqs:
+        alone = run(eng, r.batch, with_prob=False)
+        for k in ("n_vertices", "status"):
+            assert np.array_equal(r.result[k], alone[k]), (r.rid, k)
+        for e in range(r.n_events):
+            n = int(alone["n_vertices"][e])
+            for k in ("z", "peak_prob", "integral", "bin"):
+                assert np.array_equal(r.result[k][e, :n], alone[k][e, :n]), (r.rid, e, k)
+    eng.close()
+    srv.close()
+
+
+def test_admission_waits_for_pool_space():
+    """A pool that fits the lanes and about one request at a time still serves
+    everything, never above its budget."""
+    torch_cuda()
+    from paper_2602_19959_amd.serve import Server, poisson_requests
+    pool = make_events(200, seed=22)
+    reqs = poisson_requests(rate_hz=1e6, n=6, seed=4, pool=pool, min_events=40, max_events=60)
+    probe = Server(blob(), pool_bytes=3 << 30, lanes=2, lane_events=32, compute_dtype="bf16")
+    budget = probe.arena_total + int(1.5 * max(probe.request_bytes(r.batch) for r in reqs))
+    probe.close()
+    srv = Server(blob(), pool_bytes=budget, lanes=2, lane_events=32, compute_dtype="bf16")
+    stats = srv.run(reqs, realtime=True)
+    say("budget GB", budget / 1e9, stats.summary())
+    assert stats.summary()["requests"] == 6
+    assert stats.max_pool_used <= budget
+    srv.close()
