@@ -10,10 +10,10 @@ memory pool with work enqueued on framework streams.  This loop serves
   in the pool, otherwise it waits;
 * several lanes (one engine = arena + stream each) run steps concurrently, so
   work of different requests overlaps on the device;
-* continuous batching: whenever a lane is free it packs the next events from
-  the head of the admitted queue -- possibly the tail of one request and the
-  head of the next -- into one step of at most its capacity; a request can
-  span several steps and lanes;
+* continuous batching: whenever a lane is free it packs events of the
+  admitted requests, shortest remaining request first -- possibly the tail of
+  one request and the head of the next -- into one step of at most its
+  capacity; a request can span several steps and lanes;
 * a request completes when its last event's results are back on the host;
   its latency is completion time minus arrival time.
 
@@ -100,12 +100,14 @@ class Server:
         self.max_peaks = max_peaks
         per_event_state = self._state_bytes_per_event(max_tracks_per_event=200)
         if lane_events is None:
-            # half the pool for arenas, the rest for requests in flight
+            # the lanes' arenas take the pool minus room for a few of the
+            # largest slices in flight (their tracks and output buffers)
             probe = default_spec(max_events=1, compute_dtype=compute_dtype, max_peaks_per_event=max_peaks)
             a1 = arena_bytes(probe)
             probe.max_events = 101
             per_ev_arena = (arena_bytes(probe) - a1) / 100
-            lane_events = max(1, int(self.pool_bytes // 2 // lanes // (per_ev_arena + per_event_state)))
+            reserve = min(self.pool_bytes // 4, 4 * 2000 * per_event_state)
+            lane_events = max(1, int((self.pool_bytes - reserve) // lanes // (per_ev_arena + per_event_state)))
         self.lane_events = lane_events
         self.lanes = []
         for _ in range(lanes):
@@ -153,11 +155,13 @@ class Server:
         self.pool_used += r.state_bytes
 
     def _launch_step(self, lane: int, queue):
-        """Pack up to lane_events events from the head of the queue into one step."""
+        """Pack up to lane_events events into one step, shortest remaining
+        request first (small slices do not wait behind large ones; the order
+        never changes a result, the kernels being batch-invariant)."""
         t = self.torch
         eng = self.lanes[lane]
         pieces, rows = [], 0
-        for r in queue:
+        for r in sorted(queue, key=lambda q: (q.n_events - q.next_event, q.arrival)):
             if rows >= self.lane_events:
                 break
             take = min(r.n_events - r.next_event, self.lane_events - rows)
