@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = {"conv_mfma_f32": "conv_kernel.hip", "conv_mfma_lp": "conv_lp_kernel.hip",
                   "track_stage": "track_kernel.hip", "peak_finder": "peaks_kernel.hip",
-                  "first_conv": "aux_kernels.hip"}
+                  "conv_mfma_fp8": "conv_fp8_kernel.hip", "first_conv": "aux_kernels.hip"}
 
 
 def kernel_source_sha(kernel_name):
@@ -132,7 +132,18 @@ def serve_bench(args):
 
     blob = weights_to_blob(make_weights(args.seed))
     pool_events = make_events(8000, seed=args.seed + 1, mix="lognormal")
-    srv = Server(blob, pool_bytes=int(args.pool_gb * (1 << 30)), lanes=args.lanes, compute_dtype=args.dtype)
+    amax = None
+    if args.dtype == "fp8_e4m3":
+        import paper_2602_19959_amd as pv
+        cb = make_events(args.calib_events, seed=args.seed + 5, mix="lognormal")
+        CT = np.diff(cb.offsets)
+        ceng = pv.Engine(blob, pv.default_spec(max_events=cb.n_events, max_tracks_total=int(max(CT.sum(), 1)),
+                                               max_tracks_per_event=max(1500, int(CT.max()))))
+        cf, co = pv.upload_events(cb)
+        amax = ceng.calibrate(cf, co)
+        ceng.close()
+    srv = Server(blob, pool_bytes=int(args.pool_gb * (1 << 30)), lanes=args.lanes, compute_dtype=args.dtype,
+                 fp8_amax=amax)
     print(f"[serve] {args.dtype} pool {args.pool_gb} GB, {args.lanes} lanes x {srv.lane_events} events",
           file=sys.stderr, flush=True)
     warm = poisson_requests(1e9, 4, args.seed + 7, pool_events)
@@ -168,7 +179,9 @@ def main():
     ap.add_argument("--events", type=int, default=1000)
     ap.add_argument("--mix", default="poisson", choices=["poisson", "lognormal"])
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--dtype", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--dtype", default="fp32", choices=["fp32", "bf16", "fp16", "fp8_e4m3"])
+    ap.add_argument("--calib-events", type=int, default=256,
+                    help="FP8: events (seed + 5) of the FP32 calibration run that sets the channel scales")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedule", default="queue", choices=["queue", "block"],
                     help="track stage: persistent work queue (default) or one block per event")
@@ -214,7 +227,22 @@ def main():
     T = np.diff(batch.offsets)
     spec = pv.default_spec(max_events=E, max_tracks_total=int(max(T.sum(), 1)), compute_dtype=args.dtype,
                            max_tracks_per_event=max(1500, int(T.max())))
-    eng = pv.Engine(weights_to_blob(w), spec)
+    amax = None
+    if args.dtype == "fp8_e4m3":
+        # set-up, before and outside the timed region: channel scales from an
+        # FP32 run over other events
+        cb = make_events(args.calib_events, seed=args.seed + 5, mix=args.mix)
+        CT = np.diff(cb.offsets)
+        cspec = pv.default_spec(max_events=cb.n_events, max_tracks_total=int(max(CT.sum(), 1)),
+                                max_tracks_per_event=max(1500, int(CT.max())))
+        ceng = pv.Engine(weights_to_blob(w), cspec)
+        cf, co = pv.upload_events(cb)
+        amax = ceng.calibrate(cf, co)
+        ceng.close()
+        del cf, co
+        print(f"[bench] FP8 calibration over {cb.n_events} events: {amax.size} channel scales",
+              file=sys.stderr, flush=True)
+    eng = pv.Engine(weights_to_blob(w), spec, fp8_amax=amax)
     eng.set_track_schedule(args.schedule == "queue")
     feat, off = pv.upload_events(batch)
     out = eng.alloc_outputs(E, with_prob=False)
@@ -311,7 +339,7 @@ def main():
     dom_name, dom = max(by_kernel.items(), key=lambda kv: kv[1]["ms"])
     avg_dur_s = dom["ms"] / dom["launches"] / 1e3
     flops_per_launch = dom["flops"] / dom["launches"]
-    eb = 4 if args.dtype == "fp32" else 2
+    eb = {"fp32": 4, "fp8_e4m3": 1}.get(args.dtype, 2)
     lbytes = layer_bytes(spec, eb)
     lbytes["track"] = (36.0 * valid_tracks + E * spec.n_bins * 4) / E
     bytes_per_launch = sum(lbytes[n] * E for n in dom["layers"]) / dom["launches"]
@@ -349,7 +377,9 @@ def main():
         "dtype": DTYPE_TAG[args.dtype],
         "data": "synthetic: seeded events (Poisson(5.6) PVs, Poisson(180) tracks) and seeded He-init weights",
         "config": {"workload": f"{E} events per batch, {args.mix} track counts (mean {T.mean():.1f}), "
-                               f"UNet 32/64/128/256 over 4000 bins, {args.dtype.upper()} convolutions (FP32 accumulate), seed {args.seed}",
+                               f"UNet 32/64/128/256 over 4000 bins, {args.dtype.upper()} convolutions (FP32 accumulate)"
+                               + (f", FP8 scales from {args.calib_events} calibration events" if amax is not None else "")
+                               + f", seed {args.seed}",
                    "events_per_batch": E, "tracks_total": int(T.sum()), "max_tracks": int(T.max()),
                    "track_schedule": args.schedule, "hip_graph": bool(args.graph)},
         "p50_us_per_event": p50,

@@ -64,8 +64,10 @@ enum {
                                     non-finite feature were left out          */
 };
 
-/* Arithmetic type of the UNet convolutions.  FP32 is the deployed
- * precision of the paper (Section 2, Fig. 1). */
+/* Arithmetic type of the UNet convolutions (FP32 accumulation throughout).
+ * FP32 is the deployed precision of the paper (Section 2, Fig. 1); BF16 and
+ * FP16 follow its mixed-precision roadmap (Section 5); FP8 (OCP e4m3) needs
+ * calibration scales (pvf_init_fp8). */
 typedef enum { PVF_FP32 = 0, PVF_BF16 = 1, PVF_FP16 = 2, PVF_FP8_E4M3 = 3 } pvf_dtype;
 
 /* The frozen tensor specification ("TensorSpec", Section 3).  Fill it with
@@ -146,6 +148,25 @@ pvf_status pvf_arena_bytes(const pvf_spec *spec, size_t *out_bytes);
  * packed weights and clearing the arena).  On error *out is NULL. */
 pvf_status pvf_init(const pvf_spec *spec, const void *weights_blob, size_t blob_bytes,
                     void *d_arena, size_t arena_bytes, void *stream, pvf_engine **out);
+
+/* FP8 engine (spec.compute_dtype = PVF_FP8_E4M3).  amax: host floats, the
+ * per-channel absolute maxima of every stored activation measured by
+ * pvf_calibrate on a higher-precision engine of the same network, n_amax of
+ * them.  Each stored FP8 tensor then holds x / a_c with a_c = amax_c / 448;
+ * each convolution folds its input scales into its weights and quantises
+ * every output column with its own scale (per-output-channel).  pvf_init
+ * with an FP8 spec returns PVF_ERR_INVALID_ARGUMENT (the scales are needed). */
+pvf_status pvf_init_fp8(const pvf_spec *spec, const void *weights_blob, size_t blob_bytes, const float *amax,
+                        size_t n_amax, void *d_arena, size_t arena_bytes, void *stream, pvf_engine **out);
+
+/* Calibration for FP8 (set-up call, synchronises nothing but clears d_amax
+ * on the stream): runs the batch like pvf_execute on an FP32/BF16/FP16
+ * engine and writes into d_amax (device floats) the per-channel absolute
+ * maxima of every stored activation, in launch order.  n must equal
+ * pvf_calibration_size(eng).  Not for graph capture. */
+int64_t pvf_calibration_size(const pvf_engine *eng);
+pvf_status pvf_calibrate(pvf_engine *eng, const pvf_tracks *tracks, const pvf_vertices *out, float *d_amax,
+                         int64_t n);
 
 /* Enqueue the whole path for one batch on the engine's stream and return
  * at once (Section 3, Execute phase).  No allocation, no synchronisation.

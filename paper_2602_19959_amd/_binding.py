@@ -96,6 +96,13 @@ def load_library() -> C.CDLL:
     lib.pvf_arena_bytes.restype = C.c_int
     lib.pvf_init.argtypes = [C.POINTER(Spec), C.c_char_p, C.c_size_t, vp, C.c_size_t, vp, C.POINTER(vp)]
     lib.pvf_init.restype = C.c_int
+    lib.pvf_init_fp8.argtypes = [C.POINTER(Spec), C.c_char_p, C.c_size_t, C.POINTER(C.c_float), C.c_size_t, vp,
+                                 C.c_size_t, vp, C.POINTER(vp)]
+    lib.pvf_init_fp8.restype = C.c_int
+    lib.pvf_calibration_size.argtypes = [vp]
+    lib.pvf_calibration_size.restype = i64
+    lib.pvf_calibrate.argtypes = [vp, C.POINTER(Tracks), C.POINTER(Vertices), vp, i64]
+    lib.pvf_calibrate.restype = C.c_int
     lib.pvf_execute.argtypes = [vp, C.POINTER(Tracks), C.POINTER(Vertices)]
     lib.pvf_execute.restype = C.c_int
     lib.pvf_execute_on.argtypes = [vp, C.POINTER(Tracks), C.POINTER(Vertices), vp]
@@ -182,7 +189,9 @@ class Engine:
     """One engine = one frozen spec, one arena, one stream (torch.cuda.Stream)."""
 
     def __init__(self, weights_blob: bytes, spec: Spec | None = None, device: str = "cuda:0",
-                 stream=None):
+                 stream=None, fp8_amax=None):
+        """fp8_amax: the calibration table (Engine.calibrate of a
+        higher-precision engine) an FP8 spec needs; None otherwise."""
         import torch
 
         self._torch = torch
@@ -197,10 +206,18 @@ class Engine:
         self._blob = bytes(weights_blob)
         h = C.c_void_p(None)
         with torch.cuda.device(self.device):
-            st = self.lib.pvf_init(C.byref(self.spec), self._blob, len(self._blob),
-                                   C.c_void_p(self.arena.data_ptr()), nbytes,
-                                   C.c_void_p(self.stream.cuda_stream), C.byref(h))
-        _check("pvf_init", st)
+            if fp8_amax is None:
+                st = self.lib.pvf_init(C.byref(self.spec), self._blob, len(self._blob),
+                                       C.c_void_p(self.arena.data_ptr()), nbytes,
+                                       C.c_void_p(self.stream.cuda_stream), C.byref(h))
+            else:
+                import numpy as np
+                am = np.ascontiguousarray(np.asarray(fp8_amax, dtype=np.float32).reshape(-1))
+                st = self.lib.pvf_init_fp8(C.byref(self.spec), self._blob, len(self._blob),
+                                           am.ctypes.data_as(C.POINTER(C.c_float)), am.size,
+                                           C.c_void_p(self.arena.data_ptr()), nbytes,
+                                           C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        _check("pvf_init_fp8" if fp8_amax is not None else "pvf_init", st)
         self.handle = h
         self.arena_bytes = nbytes
 
@@ -306,6 +323,20 @@ class Engine:
         self.stream.wait_stream(t.cuda.current_stream(self.device))
         _check("pvf_autotune", self.lib.pvf_autotune(self.handle, C.byref(tr), C.byref(v), reps))
         return self.variants()
+
+    def calibrate(self, feat, offsets):
+        """Per-channel absolute maxima of every stored activation on this
+        batch (numpy float32), the table an FP8 engine is built from."""
+        t = self._torch
+        n = int(self.lib.pvf_calibration_size(self.handle))
+        out = self.alloc_outputs(offsets.shape[0] - 1)
+        amax = t.empty(n, dtype=t.float32, device=self.device)
+        tr, v = self._views(feat, offsets, out)
+        self.stream.wait_stream(t.cuda.current_stream(self.device))
+        _check("pvf_calibrate", self.lib.pvf_calibrate(self.handle, C.byref(tr), C.byref(v),
+                                                       C.c_void_p(amax.data_ptr()), n))
+        self.stream.synchronize()
+        return amax.cpu().numpy()
 
     def set_track_schedule(self, persistent: bool):
         _check("pvf_set_track_schedule", self.lib.pvf_set_track_schedule(self.handle, 1 if persistent else 0))

@@ -11,6 +11,20 @@ constexpr int kMaxC0 = 64;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// OCP e4m3 helpers (saturated conversion: the hardware conversion maps
+// out-of-range values to NaN)
+__device__ __forceinline__ uint8_t to_e4m3(float x)
+{
+    x = fminf(fmaxf(x, -448.f), 448.f);
+    return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.f, 0, false) & 0xff);
+}
+__device__ __forceinline__ float e4m3_to_f32(uint8_t b)
+{
+    const int e = (b >> 3) & 15, m = b & 7;
+    const float v = e ? ldexpf(1.f + m / 8.f, e - 7) : ldexpf(m / 8.f, -6);
+    return (b & 0x80) ? -v : v;
+}
+
 // enc0.c1: y[c] = LeakyReLU(b[c] + sum_j w[c][j] x[t + j - 2]), one row per
 // thread, all C0 channels written as one contiguous run of float4 stores.
 template <class T>
@@ -37,12 +51,16 @@ __global__ __launch_bounds__(NT) void first_conv(FirstConvArgs a)
             float s = b[c + u];
 #pragma unroll
             for (int j = 0; j < kTaps; ++j) s = fmaf(w[(c + u) * kTaps + j], x[j], s);
-            y[u] = (T)(s >= 0.f ? s : a.slope * s);
+            const float act = s >= 0.f ? s : a.slope * s;
+            if constexpr (sizeof(T) == 1) y[u] = to_e4m3(act * a.out_inv_scale[c + u]);
+            else y[u] = (T)act;
         }
         // 8 channels = 32 B (float) or 16 B (16-bit): whole-vector stores
         if constexpr (sizeof(T) == 4) {
             reinterpret_cast<f32x4*>(o + c)[0] = *reinterpret_cast<const f32x4*>(y);
             reinterpret_cast<f32x4*>(o + c)[1] = *reinterpret_cast<const f32x4*>(y + 4);
+        } else if constexpr (sizeof(T) == 1) {
+            *reinterpret_cast<uint2*>(o + c) = *reinterpret_cast<const uint2*>(y);
         } else {
             *reinterpret_cast<uint4*>(o + c) = *reinterpret_cast<const uint4*>(y);
         }
@@ -59,7 +77,23 @@ __global__ __launch_bounds__(NT) void gather_channels_first(GatherArgs a)
     const int64_t rem = i - e * per_event;
     const int c = (int)(rem / a.L);
     const int t = (int)(rem - (int64_t)c * a.L);
-    a.dst[i] = (float)static_cast<const T*>(a.src)[(e * a.r + a.guard + t) * a.ld + a.ch_off + c];
+    const T v = static_cast<const T*>(a.src)[(e * a.r + a.guard + t) * a.ld + a.ch_off + c];
+    if constexpr (sizeof(T) == 1) a.dst[i] = e4m3_to_f32(v) * a.ch_scale[c];
+    else a.dst[i] = (float)v;
+}
+
+template <class T>
+__global__ __launch_bounds__(NT) void amax_channels(AmaxArgs a)
+{
+    // block: 256 threads = (256 / C) row lanes x C channels, 64 rows each
+    const int per = NT / a.C;
+    const int c = threadIdx.x % a.C, lr = threadIdx.x / a.C;
+    if (lr >= per) return;
+    const int64_t r0 = ((int64_t)blockIdx.x * per + lr) * 64;
+    float m = 0.f;
+    for (int64_t r = r0; r < r0 + 64 && r < a.rows; ++r)
+        m = fmaxf(m, fabsf((float)static_cast<const T*>(a.src)[r * a.ld + a.ch_off + c]));
+    atomicMax(reinterpret_cast<unsigned int*>(a.out + c), __float_as_uint(m));
 }
 
 }  // namespace
@@ -71,6 +105,7 @@ hipError_t launch_first_conv(const FirstConvArgs& a, int dtype, hipStream_t s)
     if (dtype == PVF_FP32) hipLaunchKernelGGL(first_conv<float>, dim3(blocks), dim3(NT), 0, s, a);
     else if (dtype == PVF_BF16) hipLaunchKernelGGL(first_conv<__bf16>, dim3(blocks), dim3(NT), 0, s, a);
     else if (dtype == PVF_FP16) hipLaunchKernelGGL(first_conv<_Float16>, dim3(blocks), dim3(NT), 0, s, a);
+    else if (dtype == PVF_FP8_E4M3 && a.out_inv_scale) hipLaunchKernelGGL(first_conv<uint8_t>, dim3(blocks), dim3(NT), 0, s, a);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
@@ -80,8 +115,24 @@ hipError_t launch_gather(const GatherArgs& a, hipStream_t s)
     if (a.count <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)((a.count + NT - 1) / NT);
     if (a.src_bytes == 4) hipLaunchKernelGGL(gather_channels_first<float>, dim3(blocks), dim3(NT), 0, s, a);
+    else if (a.src_bytes == 1) {
+        if (!a.ch_scale) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(gather_channels_first<uint8_t>, dim3(blocks), dim3(NT), 0, s, a);
+    }
     else if (a.dtype == PVF_BF16) hipLaunchKernelGGL(gather_channels_first<__bf16>, dim3(blocks), dim3(NT), 0, s, a);
     else hipLaunchKernelGGL(gather_channels_first<_Float16>, dim3(blocks), dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_amax(const AmaxArgs& a, hipStream_t s)
+{
+    if (a.C <= 0 || a.C > NT || NT % a.C != 0 || a.rows <= 0) return hipErrorInvalidValue;
+    const int per = NT / a.C;
+    const unsigned blocks = (unsigned)((a.rows + (int64_t)per * 64 - 1) / ((int64_t)per * 64));
+    if (a.elem_bytes == 4) hipLaunchKernelGGL(amax_channels<float>, dim3(blocks), dim3(NT), 0, s, a);
+    else if (a.dtype == PVF_BF16) hipLaunchKernelGGL(amax_channels<__bf16>, dim3(blocks), dim3(NT), 0, s, a);
+    else if (a.dtype == PVF_FP16) hipLaunchKernelGGL(amax_channels<_Float16>, dim3(blocks), dim3(NT), 0, s, a);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -6,24 +6,34 @@ namespace pvf {
 hipError_t launch_conv(int dtype, const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s)
 {
     if (dtype == PVF_FP32) return launch_conv_f32(a, taps, epi, variant, s);
+    if (dtype == PVF_FP8_E4M3) return launch_conv_fp8(a, taps, epi, variant, s);
     return launch_conv_lp(dtype, a, taps, epi, variant, s);
 }
 
-int conv_variant_count(int dtype) { return dtype == PVF_FP32 ? f32_variant_count() : lp_variant_count(); }
+int conv_variant_count(int dtype)
+{
+    return dtype == PVF_FP32 ? f32_variant_count() : dtype == PVF_FP8_E4M3 ? fp8_variant_count() : lp_variant_count();
+}
 
 bool conv_variant_ok(int dtype, int variant, int n, int cin, int taps, Epi epi)
 {
-    return dtype == PVF_FP32 ? f32_variant_ok(variant, n, taps, epi) : lp_variant_ok(variant, n, cin, taps, epi);
+    if (dtype == PVF_FP32) return f32_variant_ok(variant, n, taps, epi);
+    if (dtype == PVF_FP8_E4M3) return fp8_variant_ok(variant, n, taps, epi);
+    return lp_variant_ok(variant, n, cin, taps, epi);
 }
 
 int conv_default_variant(int dtype, int n, int cin, int taps, Epi epi)
 {
-    return dtype == PVF_FP32 ? f32_default_variant(n, taps, epi) : lp_default_variant(n, cin, taps, epi);
+    if (dtype == PVF_FP32) return f32_default_variant(n, taps, epi);
+    if (dtype == PVF_FP8_E4M3) return fp8_default_variant(n, taps, epi);
+    return lp_default_variant(n, cin, taps, epi);
 }
 
 std::string conv_kernel_name(int dtype, int variant, int taps, Epi epi)
 {
-    return dtype == PVF_FP32 ? f32_kernel_name(variant, taps, epi) : lp_kernel_name(dtype, variant, taps, epi);
+    if (dtype == PVF_FP32) return f32_kernel_name(variant, taps, epi);
+    if (dtype == PVF_FP8_E4M3) return fp8_kernel_name(variant, taps, epi);
+    return lp_kernel_name(dtype, variant, taps, epi);
 }
 
 }  // namespace pvf

@@ -16,6 +16,7 @@ namespace pvf {
 namespace {
 
 constexpr int kMaxBins = 16384;
+constexpr size_t kMaxScaleFloats = 1 << 15;   // FP8 column / output / tensor scales
 constexpr int kMaxBinsPerInterval = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -29,7 +30,6 @@ pvf_status validate_spec(const pvf_spec* s)
         s->max_tracks_total < 0 || s->max_tracks_total > INT32_MAX)
         return PVF_ERR_INVALID_ARGUMENT;
     if (s->compute_dtype < PVF_FP32 || s->compute_dtype > PVF_FP8_E4M3) return PVF_ERR_INVALID_ARGUMENT;
-    if (s->compute_dtype == PVF_FP8_E4M3) return PVF_ERR_UNSUPPORTED_DTYPE;
     if (!(std::isfinite(s->z_min_mm) && std::isfinite(s->bin_width_mm) && s->bin_width_mm > 0 &&
           std::isfinite(s->peak_min) && std::isfinite(s->integral_min)))
         return PVF_ERR_INVALID_ARGUMENT;
@@ -78,6 +78,7 @@ void make_plan(const pvf_spec* s, size_t weight_floats, Plan* p)
     p->prob = take(E * p->lv[0].L * sizeof(float));
     p->flags = take(E * sizeof(int32_t));
     p->order = take(E * sizeof(int32_t));
+    p->scales = s->compute_dtype == PVF_FP8_E4M3 ? take(kMaxScaleFloats * sizeof(float)) : 0;
     p->queue = take(((size_t)s->max_tracks_per_event + 3) * sizeof(int32_t));
     p->total = off;
 }
@@ -292,6 +293,35 @@ uint16_t to_f16(float f)
     return u;
 }
 
+// float -> OCP e4m3 (finite range +-448, saturated), round to nearest even:
+// the nearest of the 127 non-negative finite codes, ties to the even code.
+uint8_t to_e4m3_host(float f)
+{
+    static float tab[127];
+    static bool init = false;
+    if (!init) {
+        for (int b = 0; b < 127; ++b) {
+            const int e = b >> 3, m = b & 7;
+            tab[b] = e ? std::ldexp(1.f + m / 8.f, e - 7) : std::ldexp(m / 8.f, -6);
+        }
+        init = true;
+    }
+    const bool neg = std::signbit(f);
+    float a = std::fabs(f);
+    if (!(a < 448.f)) a = 448.f;                     // saturate (NaN never reaches here)
+    int lo = 0, hi = 126;                            // largest code with tab <= a
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (tab[mid] <= a) lo = mid; else hi = mid - 1;
+    }
+    int b = lo;
+    if (lo < 126) {
+        const float d0 = a - tab[lo], d1 = tab[lo + 1] - a;
+        if (d1 < d0 || (d1 == d0 && ((lo + 1) & 1) == 0)) b = lo + 1;
+    }
+    return (uint8_t)(b | (neg ? 0x80 : 0));
+}
+
 // 16-bit copy of every conv weight tensor the matrix-core kernels read
 void pack_weights_lp(const WeightLayout& w, const NetShape& n, const std::vector<float>& f32, int dtype,
                      std::vector<uint16_t>& out)
@@ -338,7 +368,19 @@ struct pvf_engine {
     hipStream_t stream = nullptr;
     std::vector<std::string> names;      // one per launch of pvf_execute
     std::vector<std::string> kernels;    // kernel instance of each launch
-    struct ConvLaunch { int n = 0, cin = 0, taps = 0; Epi epi = EPI_STORE; int variant = -1; };
+    struct ConvLaunch {
+        int n = 0, cin = 0, taps = 0, cout = 0;
+        Epi epi = EPI_STORE;
+        int variant = -1;
+        const WeightLayout::Conv* w = nullptr;
+        std::vector<int> in_src;      // launches whose stored outputs form this input, in channel order
+        size_t col = 0;               // FP8: offsets (floats) into the scales region
+    };
+    std::vector<int> out_channels;       // channels of the tensor launch i stores (0: none)
+    std::vector<size_t> outinv_off, a_off;   // FP8: 1/a and a of launch i's stored tensor
+    std::vector<size_t> calib_off;       // offset of launch i's channels in the calibration table
+    size_t calib_total = 0;
+    float* calib_table = nullptr;        // set only during pvf_calibrate
     std::vector<ConvLaunch> conv;        // per launch; variant -1 = not a conv launch
     std::vector<hipEvent_t> events;      // launch boundaries when profiling
     bool profiling = false;
@@ -357,44 +399,121 @@ void build_names(pvf_engine* e)
 {
     const int n = e->spec.n_levels;
     const int c0 = e->spec.base_channels;
+    const WeightLayout& W = e->wl;
     e->names.clear();
     e->kernels.clear();
     e->conv.clear();
-    auto plain = [&](const std::string& name, const std::string& kernel) {
+    e->out_channels.clear();
+    auto find = [&](const std::string& name) {
+        for (size_t i = 0; i < e->names.size(); ++i)
+            if (e->names[i] == name) return (int)i;
+        return -1;
+    };
+    auto plain = [&](const std::string& name, const std::string& kernel, int stored_channels) {
         e->names.push_back(name);
         e->kernels.push_back(kernel);
         e->conv.push_back({});
+        e->out_channels.push_back(stored_channels);
     };
-    auto conv = [&](const std::string& name, int gemm_n, int cin, int taps, Epi epi) {
+    auto conv = [&](const std::string& name, int gemm_n, int cout, int cin, int taps, Epi epi,
+                    const WeightLayout::Conv* w, std::vector<int> src) {
         pvf_engine::ConvLaunch c;
         c.n = gemm_n;
+        c.cout = cout;
         c.cin = cin;
         c.taps = taps;
         c.epi = epi;
+        c.w = w;
+        c.in_src = std::move(src);
         c.variant = conv_default_variant(e->spec.compute_dtype, gemm_n, cin, taps, epi);
         e->names.push_back(name);
         e->kernels.push_back(conv_kernel_name(e->spec.compute_dtype, c.variant, taps, epi));
         e->conv.push_back(c);
+        e->out_channels.push_back(epi == EPI_HEAD ? 0 : cout);
     };
-    plain("track", e->track_blocks > 0 ? "track_stage_queue" : "track_stage");
+    plain("track", e->track_blocks > 0 ? "track_stage_queue" : "track_stage", 0);
     for (int l = 0; l < n; ++l) {
         const std::string L = std::to_string(l);
         const int C = c0 << l;
-        if (l == 0) plain("enc0.c1", "first_conv");
-        else conv("enc" + L + ".c1", C, C / 2, kTaps, EPI_STORE);
-        conv("enc" + L + ".c2", C, C, kTaps, l < n - 1 ? EPI_POOL : EPI_STORE);
+        if (l == 0) plain("enc0.c1", "first_conv", C);
+        else conv("enc" + L + ".c1", C, C, C / 2, kTaps, EPI_STORE, &W.enc[l][0],
+                  {find("enc" + std::to_string(l - 1) + ".c2")});
+        conv("enc" + L + ".c2", C, C, C, kTaps, l < n - 1 ? EPI_POOL : EPI_STORE, &W.enc[l][1],
+             {find("enc" + L + ".c1")});
     }
     for (int l = n - 2; l >= 0; --l) {
         const std::string L = std::to_string(l);
         const int C = c0 << l;
-        conv("up" + L, 2 * C, 2 * C, 1, EPI_CONVT);
-        conv("dec" + L + ".c1", C, 2 * C, kTaps, EPI_STORE);
-        conv(l == 0 ? "dec0.c2+head" : "dec" + L + ".c2", C, C, kTaps, l == 0 ? EPI_HEAD : EPI_STORE);
+        conv("up" + L, 2 * C, C, 2 * C, 1, EPI_CONVT, &W.up[l],
+             {find(l == n - 2 ? "enc" + std::to_string(n - 1) + ".c2" : "dec" + std::to_string(l + 1) + ".c2")});
+        conv("dec" + L + ".c1", C, C, 2 * C, kTaps, EPI_STORE, &W.dec[l][0], {find("enc" + L + ".c2"), find("up" + L)});
+        conv(l == 0 ? "dec0.c2+head" : "dec" + L + ".c2", C, C, C, kTaps, l == 0 ? EPI_HEAD : EPI_STORE,
+             &W.dec[l][1], {find("dec" + L + ".c1")});
     }
-    plain("peaks", "peak_finder");
+    plain("peaks", "peak_finder", 0);
+    // calibration table: the stored tensors' channels, in launch order
+    e->calib_off.assign(e->names.size(), 0);
+    e->calib_total = 0;
+    for (size_t i = 0; i < e->names.size(); ++i) {
+        e->calib_off[i] = e->calib_total;
+        e->calib_total += e->out_channels[i];
+    }
 }
 
 bool misaligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) != 0; }
+
+// FP8 engine set-up from a calibration table (per-channel absolute maxima of
+// every stored tensor, layout of pvf_calibrate):
+//   a_c   = amax_c / 448 (1 for a channel that never left zero);
+//   W'    = W * a_c of the input channel, s_n = max|W'[n]| / 448 per column,
+//   Wq    = e4m3(W' / s_n);
+// the kernels then compute acc * s_n (+ bias) and store y / a of their output.
+pvf_status setup_fp8(pvf_engine* e, const std::vector<float>& f32, const float* amax, size_t n_amax,
+                     std::vector<uint8_t>& wq, std::vector<float>& sc)
+{
+    if (!amax || n_amax != e->calib_total) return PVF_ERR_INVALID_ARGUMENT;
+    const size_t nl = e->names.size();
+    std::vector<std::vector<float>> a(nl);
+    for (size_t i = 0; i < nl; ++i)
+        for (int c = 0; c < e->out_channels[i]; ++c) {
+            const float m = amax[e->calib_off[i] + c];
+            if (!std::isfinite(m) || m < 0.f) return PVF_ERR_INVALID_ARGUMENT;
+            a[i].push_back(m > 0.f ? m / 448.f : 1.f);
+        }
+    sc.clear();
+    e->outinv_off.assign(nl, 0);
+    e->a_off.assign(nl, 0);
+    for (size_t i = 0; i < nl; ++i) {
+        if (e->out_channels[i] == 0) continue;
+        e->outinv_off[i] = sc.size();
+        for (float x : a[i]) sc.push_back(1.f / x);
+        e->a_off[i] = sc.size();
+        for (float x : a[i]) sc.push_back(x);
+    }
+    wq.assign(e->wl.total, 0);
+    for (size_t i = 0; i < nl; ++i) {
+        auto& c = e->conv[i];
+        if (c.variant < 0) continue;
+        std::vector<float> ain;                 // scale of every input channel
+        for (int src : c.in_src) ain.insert(ain.end(), a[src].begin(), a[src].end());
+        if ((int)ain.size() != c.cin) return PVF_ERR_INVALID_ARGUMENT;
+        c.col = sc.size();
+        const int per_n = c.taps * c.cin;       // packed row: [tap][cin]
+        for (int n = 0; n < c.n; ++n) {
+            const float* row = &f32[c.w->w + (size_t)n * per_n];
+            float m = 0.f;
+            for (int t = 0; t < c.taps; ++t)
+                for (int ch = 0; ch < c.cin; ++ch) m = std::max(m, std::fabs(row[t * c.cin + ch] * ain[ch]));
+            const float sn = m > 0.f ? m / 448.f : 1.f;
+            sc.push_back(sn);
+            for (int t = 0; t < c.taps; ++t)
+                for (int ch = 0; ch < c.cin; ++ch)
+                    wq[c.w->w + (size_t)n * per_n + t * c.cin + ch] = to_e4m3_host(row[t * c.cin + ch] * ain[ch] / sn);
+        }
+    }
+    if (sc.size() > kMaxScaleFloats) return PVF_ERR_SHAPE;
+    return PVF_OK;
+}
 
 ConvArgs conv_args(pvf_engine* eng, const WeightLayout::Conv& c, const void* in, int ld_in, int rows_per_event,
                    int n_events, void* out, int ld_out)
@@ -407,6 +526,7 @@ ConvArgs conv_args(pvf_engine* eng, const WeightLayout::Conv& c, const void* in,
     a.m_rows = n_events * rows_per_event;
     a.r_in = rows_per_event;
     if (eng->spec.compute_dtype == PVF_FP32) a.w = wbase + c.w;
+    else if (eng->spec.compute_dtype == PVF_FP8_E4M3) a.w = at<uint8_t>(eng, eng->plan.weights_lp) + c.w;
     else a.w = at<uint16_t>(eng, eng->plan.weights_lp) + c.w;
     a.bias = wbase + c.b;
     a.n = c.cout;
@@ -463,6 +583,38 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
     ta.queue_counter = at<int32_t>(eng, P.queue);
     check(launch_track(ta, E, eng->track_blocks, at<int32_t>(eng, P.queue) + 1, s));
 
+    // Calibration (pvf_calibrate only): per-channel absolute maximum of the
+    // tensor the launch just enqueued stored.
+    auto calib = [&](const char* base, int ld, int level, int C, int ch_off) {
+        if (!eng->calib_table || err != hipSuccess) return;
+        AmaxArgs m{};
+        m.src = base;
+        m.elem_bytes = (int)eb;
+        m.dtype = dt;
+        m.rows = (int64_t)E * P.lv[level].R;
+        m.ld = ld;
+        m.C = C;
+        m.ch_off = ch_off;
+        m.out = eng->calib_table + eng->calib_off[li - 1];
+        err = launch_amax(m, s);
+    };
+    float* scales = dt == PVF_FP8_E4M3 ? at<float>(eng, P.scales) : nullptr;
+    // one UNet convolution: FP8 scales of this launch, launch, then calibration
+    auto conv = [&](ConvArgs a, int taps, Epi epi, int store_level, int store_ld, int store_ch_off) {
+        if (scales) {
+            a.col_scale = scales + eng->conv[li].col;
+            a.out_inv_scale = epi == EPI_HEAD ? nullptr : scales + eng->outinv_off[li];
+        }
+        const int C = eng->conv[li].cout;
+        check(launch_conv(dt, a, taps, epi, var(), s));
+        if (epi != EPI_HEAD) {
+            // a.out points at the tensor's first channel; the calibration reads
+            // whole rows from the buffer start with the channel offset
+            const char* base = static_cast<const char*>(a.out) - (size_t)store_ch_off * eb;
+            calib(base, store_ld, store_level, C, store_ch_off);
+        }
+    };
+
     // ---- encoder
     FirstConvArgs fa{};
     fa.x0 = at<float>(eng, P.x0);
@@ -473,53 +625,50 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
     fa.c0 = P.lv[0].C;
     fa.slope = eng->leaky;
     fa.out = act(P.a[0]);
+    fa.out_inv_scale = scales ? scales + eng->outinv_off[li] : nullptr;
     check(launch_first_conv(fa, dt, s));
+    calib(act(P.a[0]), P.lv[0].C, 0, P.lv[0].C, 0);
 
     for (int l = 0; l < n; ++l) {
         const Level& lv = P.lv[l];
         if (l > 0) {
             const Level& up = P.lv[l - 1];
-            ConvArgs a = conv_args(eng, W.enc[l][0], act(P.pool[l]), up.C, lv.R, E,
-                                   act(P.a[l]), lv.C);
-            check(launch_conv(dt, a, kTaps, EPI_STORE, var(), s));
+            conv(conv_args(eng, W.enc[l][0], act(P.pool[l]), up.C, lv.R, E, act(P.a[l]), lv.C), kTaps, EPI_STORE,
+                 l, lv.C, 0);
         }
         if (l < n - 1) {
-            ConvArgs a = conv_args(eng, W.enc[l][1], act(P.a[l]), lv.C, lv.R, E,
-                                   act(P.cat[l]), 2 * lv.C);
+            ConvArgs a = conv_args(eng, W.enc[l][1], act(P.a[l]), lv.C, lv.R, E, act(P.cat[l]), 2 * lv.C);
             a.pool_out = act(P.pool[l + 1]);
             a.ld_pool = lv.C;
             a.r_pool = P.lv[l + 1].R;
-            check(launch_conv(dt, a, kTaps, EPI_POOL, var(), s));
+            conv(a, kTaps, EPI_POOL, l, 2 * lv.C, 0);
         } else {
-            ConvArgs a = conv_args(eng, W.enc[l][1], act(P.a[l]), lv.C, lv.R, E,
-                                   act(P.d[l]), lv.C);
-            check(launch_conv(dt, a, kTaps, EPI_STORE, var(), s));
+            conv(conv_args(eng, W.enc[l][1], act(P.a[l]), lv.C, lv.R, E, act(P.d[l]), lv.C), kTaps, EPI_STORE, l,
+                 lv.C, 0);
         }
     }
     // ---- decoder
     for (int l = n - 2; l >= 0; --l) {
         const Level& lv = P.lv[l];
         const Level& lo = P.lv[l + 1];
-        ConvArgs u = conv_args(eng, W.up[l], act(P.d[l + 1]), lo.C, lo.R, E,
-                               act(P.cat[l]) + (size_t)lv.C * eb, 2 * lv.C);
+        ConvArgs u = conv_args(eng, W.up[l], act(P.d[l + 1]), lo.C, lo.R, E, act(P.cat[l]) + (size_t)lv.C * eb,
+                               2 * lv.C);
         u.n = 2 * lv.C;
         u.cout = lv.C;
         u.r_out = lv.R;
-        check(launch_conv(dt, u, 1, EPI_CONVT, var(), s));
-        ConvArgs a = conv_args(eng, W.dec[l][0], act(P.cat[l]), 2 * lv.C, lv.R, E,
-                               act(P.a[l]), lv.C);
-        check(launch_conv(dt, a, kTaps, EPI_STORE, var(), s));
+        conv(u, 1, EPI_CONVT, l, 2 * lv.C, lv.C);
+        conv(conv_args(eng, W.dec[l][0], act(P.cat[l]), 2 * lv.C, lv.R, E, act(P.a[l]), lv.C), kTaps, EPI_STORE, l,
+             lv.C, 0);
         if (l > 0) {
-            ConvArgs b = conv_args(eng, W.dec[l][1], act(P.a[l]), lv.C, lv.R, E,
-                                   act(P.d[l]), lv.C);
-            check(launch_conv(dt, b, kTaps, EPI_STORE, var(), s));
+            conv(conv_args(eng, W.dec[l][1], act(P.a[l]), lv.C, lv.R, E, act(P.d[l]), lv.C), kTaps, EPI_STORE, l,
+                 lv.C, 0);
         } else {
             ConvArgs b = conv_args(eng, W.dec[0][1], act(P.a[0]), lv.C, lv.R, E, nullptr, 0);
             b.head_w = wbase + W.head_w;
             b.head_b = eng->head_b;
             b.prob = prob;
             b.l_out = lv.L;
-            check(launch_conv(dt, b, kTaps, EPI_HEAD, var(), s));
+            conv(b, kTaps, EPI_HEAD, 0, 0, 0);
         }
     }
     // ---- peaks
@@ -579,14 +728,16 @@ pvf_status pvf_arena_bytes(const pvf_spec* spec, size_t* out_bytes)
     return PVF_OK;
 }
 
-pvf_status pvf_init(const pvf_spec* spec, const void* blob, size_t blob_bytes, void* d_arena, size_t arena_bytes,
-                    void* stream, pvf_engine** out)
+static pvf_status init_impl(const pvf_spec* spec, const void* blob, size_t blob_bytes, const float* amax,
+                            size_t n_amax, void* d_arena, size_t arena_bytes, void* stream, pvf_engine** out)
 {
     if (out) *out = nullptr;
     if (!spec || !blob || !d_arena || !stream || !out) return PVF_ERR_INVALID_ARGUMENT;
     if (misaligned(d_arena, kAlign)) return PVF_ERR_ALIGNMENT;
     pvf_status st = validate_spec(spec);
     if (st != PVF_OK) return st;
+    const bool fp8 = spec->compute_dtype == PVF_FP8_E4M3;
+    if (fp8 != (amax != nullptr)) return PVF_ERR_INVALID_ARGUMENT;
     Plan plan;
     make_plan(spec, weight_floats_for(spec), &plan);
     if (arena_bytes < plan.total) return PVF_ERR_ARENA_TOO_SMALL;
@@ -617,10 +768,25 @@ pvf_status pvf_init(const pvf_spec* spec, const void* blob, size_t blob_bytes, v
 
     std::vector<float> packed;
     pack_weights(b, e->wl, packed);
+    std::vector<uint16_t> packed_lp;
+    std::vector<uint8_t> packed_fp8;
+    std::vector<float> fp8_scales;
+    if (fp8) {
+        st = setup_fp8(e, packed, amax, n_amax, packed_fp8, fp8_scales);
+        if (st != PVF_OK) {
+            delete e;
+            return st;
+        }
+    }
     hipError_t err = hipMemcpyAsync(e->arena + plan.weights, packed.data(), packed.size() * sizeof(float),
                                     hipMemcpyHostToDevice, e->stream);
-    std::vector<uint16_t> packed_lp;
-    if (err == hipSuccess && spec->compute_dtype != PVF_FP32) {
+    if (err == hipSuccess && fp8) {
+        err = hipMemcpyAsync(e->arena + plan.weights_lp, packed_fp8.data(), packed_fp8.size(), hipMemcpyHostToDevice,
+                             e->stream);
+        if (err == hipSuccess)
+            err = hipMemcpyAsync(e->arena + plan.scales, fp8_scales.data(), fp8_scales.size() * sizeof(float),
+                                 hipMemcpyHostToDevice, e->stream);
+    } else if (err == hipSuccess && spec->compute_dtype != PVF_FP32) {
         pack_weights_lp(e->wl, b.shape, packed, spec->compute_dtype, packed_lp);
         err = hipMemcpyAsync(e->arena + plan.weights_lp, packed_lp.data(), packed_lp.size() * sizeof(uint16_t),
                              hipMemcpyHostToDevice, e->stream);
@@ -634,6 +800,19 @@ pvf_status pvf_init(const pvf_spec* spec, const void* blob, size_t blob_bytes, v
     }
     *out = e;
     return PVF_OK;
+}
+
+pvf_status pvf_init(const pvf_spec* spec, const void* blob, size_t blob_bytes, void* d_arena, size_t arena_bytes,
+                    void* stream, pvf_engine** out)
+{
+    return init_impl(spec, blob, blob_bytes, nullptr, 0, d_arena, arena_bytes, stream, out);
+}
+
+pvf_status pvf_init_fp8(const pvf_spec* spec, const void* blob, size_t blob_bytes, const float* amax, size_t n_amax,
+                        void* d_arena, size_t arena_bytes, void* stream, pvf_engine** out)
+{
+    if (!amax) return PVF_ERR_INVALID_ARGUMENT;
+    return init_impl(spec, blob, blob_bytes, amax, n_amax, d_arena, arena_bytes, stream, out);
 }
 
 static pvf_status check_call(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* out)
@@ -819,6 +998,22 @@ pvf_status pvf_graph_launch(pvf_engine* eng)
     return hipGraphLaunch(eng->graph_exec, eng->stream) == hipSuccess ? PVF_OK : PVF_ERR_DEVICE;
 }
 
+int64_t pvf_calibration_size(const pvf_engine* eng) { return eng ? (int64_t)eng->calib_total : -1; }
+
+pvf_status pvf_calibrate(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* out, float* d_amax, int64_t n)
+{
+    pvf_status st = check_call(eng, tr, out);
+    if (st != PVF_OK) return st;
+    if (!d_amax || n != (int64_t)eng->calib_total || tr->n_events == 0) return PVF_ERR_INVALID_ARGUMENT;
+    if (eng->spec.compute_dtype == PVF_FP8_E4M3) return PVF_ERR_UNSUPPORTED_DTYPE;
+    if (misaligned(d_amax, 4)) return PVF_ERR_ALIGNMENT;
+    if (hipMemsetAsync(d_amax, 0, (size_t)n * sizeof(float), eng->stream) != hipSuccess) return PVF_ERR_DEVICE;
+    eng->calib_table = d_amax;
+    st = enqueue(eng, tr, out, eng->stream);
+    eng->calib_table = nullptr;
+    return st;
+}
+
 pvf_status pvf_profile_enable(pvf_engine* eng, int on)
 {
     if (!eng) return PVF_ERR_INVALID_ARGUMENT;
@@ -853,6 +1048,12 @@ pvf_status pvf_debug_tensor(pvf_engine* eng, const char* name, int32_t n_events,
     bool found = false;
     const int eb = act_bytes(eng->spec.compute_dtype);
     g.dtype = eng->spec.compute_dtype;
+    auto launch_of = [&](const std::string& nm) {
+        for (size_t i = 0; i < eng->names.size(); ++i)
+            if (eng->names[i] == nm) return (int)i;
+        return -1;
+    };
+    int producer = -1;     // launch whose stored tensor the name refers to
     auto set = [&](size_t off, int ld, int l, int C, int ch_off, int bytes) {
         g.src = eng->arena + off;
         g.src_bytes = bytes;
@@ -865,6 +1066,7 @@ pvf_status pvf_debug_tensor(pvf_engine* eng, const char* name, int32_t n_events,
         found = true;
     };
     const std::string s(name);
+    producer = launch_of(s.rfind("pool", 0) == 0 ? "enc" + s.substr(4) + ".c2" : s);
     if (s == "hist") set(P.x0, 1, 0, 1, 0, 4);
     if (s == "prob") {
         g.src = at<float>(eng, P.prob);
@@ -884,6 +1086,10 @@ pvf_status pvf_debug_tensor(pvf_engine* eng, const char* name, int32_t n_events,
         if (l >= 1 && l < n - 1 && s == "dec" + L + ".c2") set(P.d[l], C, l, C, 0, eb);
     }
     if (!found) return PVF_ERR_INVALID_ARGUMENT;
+    if (g.src_bytes == 1) {
+        if (producer < 0) return PVF_ERR_INVALID_ARGUMENT;
+        g.ch_scale = at<float>(eng, P.scales) + eng->a_off[producer];
+    }
     g.count = (int64_t)n_events * g.C * g.L;
     *out_count = g.count;
     if (!d_dst) return PVF_OK;

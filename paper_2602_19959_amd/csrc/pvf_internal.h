@@ -49,6 +49,7 @@ struct Plan {
     size_t prob = 0;               // [E][L0] float
     size_t flags = 0;              // [E] int32 track-stage status
     size_t order = 0;              // [E] int32 event order of the track work queue
+    size_t scales = 0;             // FP8: per-launch column and output scales
     size_t queue = 0;              // int32 ticket counter + order histogram
     size_t zero_begin = 0, zero_end = 0;   // region cleared at init
     size_t total = 0;
@@ -89,6 +90,8 @@ struct ConvArgs {
     float head_b;
     float* prob;         // EPI_HEAD: [E][L0]
     int l_out;           // positions per event of the output (EPI_HEAD)
+    const float* col_scale;     // FP8: per GEMM column, dequantises the accumulator
+    const float* out_inv_scale; // FP8: per output channel, 1 / scale of the stored tensor
 };
 
 struct TrackArgs {
@@ -122,6 +125,7 @@ struct FirstConvArgs {
     int c0;
     float slope;
     void* out;               // [E][R0][C0], element type = compute dtype
+    const float* out_inv_scale;   // FP8: per channel, 1 / scale of the stored tensor
 };
 
 struct PeakArgs {
@@ -146,7 +150,19 @@ struct GatherArgs {          // debug copy of an internal activation
     int ld, r, guard, L, C, ch_off;
     float* dst;              // [E][C][L]
     int64_t count;
+    const float* ch_scale;   // FP8 source: per channel dequantisation scale
 };
+
+// Per-channel absolute maximum of a channels-last activation (calibration):
+// out[c] = max(out[c], max over rows |src[row][ch_off + c]|).
+struct AmaxArgs {
+    const void* src;
+    int elem_bytes, dtype;
+    int64_t rows;
+    int ld, C, ch_off;
+    float* out;
+};
+hipError_t launch_amax(const AmaxArgs& a, hipStream_t s);
 
 // persistent_blocks > 0: the work-queue form (order kernel + persistent
 // blocks); order_scratch holds max_tracks + 2 ints.  Otherwise one block per event.
@@ -173,7 +189,13 @@ bool lp_variant_ok(int variant, int n, int cin, int taps, Epi epi);
 int lp_default_variant(int n, int cin, int taps, Epi epi);
 std::string lp_kernel_name(int dtype, int variant, int taps, Epi epi);
 
-inline int act_bytes(int dtype) { return dtype == PVF_FP32 ? 4 : 2; }
+hipError_t launch_conv_fp8(const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s);
+int fp8_variant_count();
+bool fp8_variant_ok(int variant, int n, int taps, Epi epi);
+int fp8_default_variant(int n, int taps, Epi epi);
+std::string fp8_kernel_name(int variant, int taps, Epi epi);
+
+inline int act_bytes(int dtype) { return dtype == PVF_FP32 ? 4 : (dtype == PVF_FP8_E4M3 ? 1 : 2); }
 
 hipError_t launch_peaks(const PeakArgs& a, int n_events, hipStream_t s);
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s);

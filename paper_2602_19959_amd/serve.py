@@ -92,7 +92,9 @@ class ServeStats:
 class Server:
     def __init__(self, weights_blob: bytes, pool_bytes: int = 8 << 30, lanes: int = 2,
                  lane_events: int | None = None, compute_dtype: str = "bf16",
-                 max_tracks_per_event: int = 1500, max_peaks: int = 2000, device: str = "cuda:0"):
+                 max_tracks_per_event: int = 1500, max_peaks: int = 2000, device: str = "cuda:0",
+                 fp8_amax=None):
+        """fp8_amax: calibration table (Engine.calibrate) for an FP8 compute_dtype."""
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -114,7 +116,7 @@ class Server:
             spec = default_spec(max_events=lane_events, compute_dtype=compute_dtype,
                                 max_tracks_per_event=max_tracks_per_event, max_peaks_per_event=max_peaks,
                                 max_tracks_total=lane_events * max_tracks_per_event)
-            self.lanes.append(Engine(weights_blob, spec, device=device))
+            self.lanes.append(Engine(weights_blob, spec, device=device, fp8_amax=fp8_amax))
         # per-lane step buffers, allocated once: gathered inputs and step outputs
         self.step_out = [e.alloc_outputs(lane_events, with_prob=False) for e in self.lanes]
         step_bytes = sum(v.numel() * v.element_size() for v in self.step_out[0].__dict__.values() if v is not None)

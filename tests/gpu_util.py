@@ -26,12 +26,25 @@ def blob(seed=0):
     return weights_to_blob(weights(seed))
 
 
-def make_engine(max_events, **spec):
+def make_engine(max_events, fp8_amax=None, **spec):
     import paper_2602_19959_amd as pv
     s = pv.default_spec(max_events=max_events, **spec)
     if "max_tracks_total" not in spec:
         s.max_tracks_total = max_events * 1500
-    return pv.Engine(blob(), s)
+    return pv.Engine(blob(), s, fp8_amax=fp8_amax)
+
+
+@functools.lru_cache(maxsize=None)
+def fp8_calibration(n_events=64, seed=5):
+    """Calibration table of an FP32 engine over `n_events` events of `seed`
+    (events the FP8 tests never score)."""
+    import paper_2602_19959_amd as pv
+    batch = make_events(n_events, seed=seed)
+    eng = make_engine(n_events)
+    feat, off = pv.upload_events(batch)
+    amax = eng.calibrate(feat, off)
+    eng.close()
+    return amax
 
 
 def run(engine, batch, with_prob=True):

@@ -71,7 +71,7 @@ def test_arena_bytes_scales_with_events():
 @pytest.mark.parametrize("field,value,status", [
     ("abi_version", 7, 1), ("max_events", 0, 1), ("max_peaks_per_event", 0, 1),
     ("max_tracks_total", -1, 1), ("compute_dtype", 9, 1),
-    ("compute_dtype", 3, 6), ("n_levels", 1, 2), ("base_channels", 48, 2), ("n_bins", 4001, 2),
+    ("compute_dtype", -1, 1), ("n_levels", 1, 2), ("base_channels", 48, 2), ("n_bins", 4001, 2),
     ("bins_per_interval", 300, 2), ("bin_width_mm", 0.0, 1), ("half_window", -1, 1),
     ("max_peaks_per_event", 5000, 2),
 ])
@@ -110,6 +110,28 @@ def test_init_host_checks_before_device_work():
     assert _init(spec, weights_to_blob(w))[0] == 5                # non-finite weight
     st, h = _init(spec, good, stream=0)
     assert h.value is None
+
+
+def test_fp8_needs_calibration_table():
+    """An FP8 engine is built only from a calibration table of the right size;
+    pvf_init refuses the FP8 spec, pvf_init_fp8 refuses the other dtypes, and
+    both answer before any device work."""
+    lib = pv.load_library()
+    spec = pv.default_spec(max_events=4, compute_dtype=3)
+    blob = weights_to_blob(make_weights(0))
+    n = C.c_size_t(0)
+    assert lib.pvf_arena_bytes(C.byref(spec), C.byref(n)) == 0
+    assert _init(spec, blob)[0] == 1
+    h = C.c_void_p(None)
+    amax = (C.c_float * 4)(1, 1, 1, 1)
+    st = lib.pvf_init_fp8(C.byref(spec), blob, len(blob), None, 0, C.c_void_p(256), n.value, C.c_void_p(8),
+                          C.byref(h))
+    assert st == 1 and h.value is None
+    st = lib.pvf_init_fp8(C.byref(pv.default_spec(max_events=4)), blob, len(blob), amax, 4, C.c_void_p(256),
+                          n.value, C.c_void_p(8), C.byref(h))
+    assert st == 1
+    assert lib.pvf_calibration_size(None) == -1
+    assert lib.pvf_calibrate(None, None, None, None, 0) == 1
 
 
 def test_execute_rejects_null_engine():

@@ -1,0 +1,162 @@
+"""FP8 (OCP e4m3) UNet on the matrix cores against the FP64 oracle, through
+the C ABI.  Activations carry one scale per channel from a calibration batch
+of other events; each convolution folds its input scales into its weights and
+quantises every output column with its own scale (per-output-channel).  This
+takes the paper's low-precision roadmap (Section 5) one format below FP16; the
+bounds and their derivation are in tests/parity.py."""
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import make_events
+from tests import parity
+from tests.gpu_util import torch_cuda, make_engine, run, weights, fp8_calibration
+
+pytestmark = pytest.mark.gpu
+DT = "fp8_e4m3"
+
+
+def say(*a):
+    print("[gpu-fp8]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def batch16():
+    return make_events(16, seed=0)
+
+
+@pytest.fixture(scope="module")
+def ref16(batch16):
+    return oracle.run_batch(batch16, weights())
+
+
+@pytest.fixture(scope="module")
+def amax():
+    torch_cuda()
+    say("calibration: FP32 engine, 64 events of seed 5")
+    return fp8_calibration()
+
+
+@pytest.fixture(scope="module")
+def fp8(batch16, amax):
+    say("engine fp8")
+    eng = make_engine(16, fp8_amax=amax, compute_dtype=DT)
+    out = run(eng, batch16)
+    yield eng, out
+    eng.close()
+
+
+def test_calibration_table_matches_oracle_taps():
+    """The table holds, per stored tensor and channel, the absolute maximum
+    over the calibration batch: check two tensors against the oracle's
+    per-layer activations of the same events."""
+    torch_cuda()
+    w = weights()
+    batch = make_events(8, seed=5)
+    amax = fp8_calibration(n_events=8, seed=5)
+    eng = make_engine(8)
+    names = eng.launch_names()
+    eng.close()
+    # stored tensors in launch order, with their channel counts
+    stored = [n for n in names if n not in ("track", "peaks", "dec0.c2+head")]
+    chans = {n: (32 << int(n[3])) if n.startswith(("enc", "dec")) else (32 << int(n[2])) for n in stored}
+    assert len(amax) == sum(chans.values())
+    off = {}
+    k = 0
+    for n in stored:
+        off[n] = k
+        k += chans[n]
+    want = {n: np.zeros(chans[n]) for n in ("enc0.c1", "dec1.c2")}
+    for e in range(batch.n_events):
+        taps = oracle.unet_taps(w.s_in * oracle.histogram(batch.tracks_of(e), w)[0], w)
+        for n in want:
+            want[n] = np.maximum(want[n], np.abs(taps[n]).max(axis=1))
+    for n, v in want.items():
+        got = amax[off[n]:off[n] + chans[n]]
+        err = float(np.max(np.abs(got - v) / np.maximum(v, 1e-30)))
+        say(n, "calibration max rel err %.2e" % err)
+        assert err <= 1e-4, n
+
+
+def test_probability_within_stated_bound(fp8, ref16):
+    eng, out = fp8
+    dp = max(float(np.max(np.abs(out["prob"][e] - ref16[e]["p"]))) for e in range(16))
+    say("max |dp| %.3e (bound %.2f)" % (dp, parity.P_ABS[DT]))
+    assert dp <= parity.P_ABS[DT]
+
+
+def test_vertices_agree(fp8, ref16):
+    eng, out = fp8
+    matched = extra = total = 0
+    for e in range(16):
+        n = int(out["n_vertices"][e])
+        m = parity.match_vertices(out["z"][e, :n], ref16[e]["z"])
+        matched += m
+        extra += n - m
+        total += len(ref16[e]["z"])
+    say(f"vertices matched {matched}/{total}, extra {extra}")
+    assert matched >= parity.MATCH_MIN[DT] * total
+    assert extra <= parity.EXTRA_MAX[DT] * total
+
+
+def test_deterministic_and_batch_invariant(fp8, batch16):
+    eng, out = fp8
+    again = run(eng, batch16)
+    assert np.array_equal(again["prob"], out["prob"])
+    alone = run(eng, batch16.subset([7]))
+    assert np.array_equal(alone["prob"][0], out["prob"][7])
+
+
+def test_variants_identical(fp8, batch16):
+    eng, out = fp8
+    base = eng.variants()
+    tried = 0
+    for v in range(eng.variant_count(2)):
+        changed = [i for i in range(len(base)) if base[i] >= 0 and eng.set_variant(i, v)]
+        if not changed:
+            continue
+        tried += 1
+        got = run(eng, batch16)
+        assert np.array_equal(got["prob"], out["prob"]), v
+        for i in range(len(base)):
+            if base[i] >= 0:
+                eng.set_variant(i, base[i])
+    assert tried >= 3
+
+
+def test_layer_taps_close_to_fp32(fp8, batch16):
+    """Per-layer activations (dequantised with their channel scales) stay
+    within FP8 rounding of the oracle's, normwise: 3 mantissa bits give a
+    unit roundoff of 2^-4 per stored value, and each layer compounds the
+    rounding of its inputs, weights and output."""
+    eng, out = fp8
+    w = weights()
+    taps = oracle.unet_taps(w.s_in * oracle.histogram(batch16.tracks_of(0), w)[0], w)
+    run(eng, batch16.subset([0]))
+    for name, bound in (("enc0.c2", 0.08), ("pool1", 0.1), ("enc3.c2", 0.2),
+                        ("up2", 0.2), ("dec1.c1", 0.2), ("dec0.c1", 0.25)):
+        got = eng.debug_tensor(name, 1).cpu().numpy().reshape(taps[name].shape)
+        err = parity.tap_err(got, taps[name])
+        say(name, "normwise %.3e (bound %.2f)" % (err, bound))
+        assert err <= bound, name
+
+
+def test_full_batch_sampled(amax):
+    """1000 events in one call, sampled against the oracle."""
+    batch = make_events(1000, seed=0)
+    eng = make_engine(1000, fp8_amax=amax, compute_dtype=DT)
+    out = run(eng, batch)
+    sample = [0, 333, 999]
+    ref = oracle.run_batch(batch.subset(sample), weights())
+    for k, e in enumerate(sample):
+        dp = float(np.max(np.abs(out["prob"][e] - ref[k]["p"])))
+        say(f"event {e} max |dp| {dp:.3e}")
+        assert dp <= parity.P_ABS[DT]
+    eng.close()
+
+
+def test_wrong_table_size_rejected(amax):
+    import paper_2602_19959_amd as pv
+    with pytest.raises(pv.PvfError):
+        make_engine(4, fp8_amax=amax[:-1], compute_dtype=DT)
