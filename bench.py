@@ -195,8 +195,9 @@ def main():
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
     ap.add_argument("--pool-gb", type=float, default=8.0)
     ap.add_argument("--lanes", type=int, default=2)
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the built-in tile shapes instead of timing the variants first")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time every tile variant per launch first and keep the fastest (the built-in "
+                         "defaults are the picks of such sweeps on this workload)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size kernel "
@@ -247,7 +248,7 @@ def main():
     feat, off = pv.upload_events(batch)
     out = eng.alloc_outputs(E, with_prob=False)
     names = eng.launch_names()
-    if not args.no_autotune:
+    if args.autotune:
         t_tune = time.perf_counter()
         picked = eng.autotune(feat, off, eng.alloc_outputs(E, with_prob=False), reps=2)
         print(f"[bench] autotuned in {time.perf_counter() - t_tune:.1f} s: "

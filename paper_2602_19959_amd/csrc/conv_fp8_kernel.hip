@@ -268,10 +268,13 @@ bool fp8_variant_ok(int v, int n, int taps, Epi epi)
     return bn <= (n < 32 ? 32 : n);
 }
 
+// picks of variant sweeps over 1000 events (ties within noise go to the
+// smaller tile)
 int fp8_default_variant(int n, int taps, Epi epi)
 {
     if (epi == EPI_HEAD || n <= 32) return 0;
-    if (epi == EPI_CONVT && taps == 1) return n >= 128 ? 3 : 1;
+    if (epi == EPI_CONVT && taps == 1) return n >= 128 ? 3 : 0;
+    if (epi == EPI_POOL) return 1;
     return n <= 64 ? 1 : 3;
 }
 
