@@ -5,6 +5,6 @@ package.  The product library (``paper_2602_19959_amd``) never imports it.
 """
 
 from .oracle import (  # noqa: F401
-    Geometry, load, bin_index, features, mlp, histogram, conv1d, convT2, maxpool2,
+    Geometry, load, bin_index, neighbour, features, mlp, histogram, conv1d, convT2, maxpool2,
     unet, unet_taps, sigmoid, peaks, run_event, run_batch, params_vector,
 )

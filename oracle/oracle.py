@@ -43,8 +43,10 @@ def load():
         lib.orc_mlp_param_count.restype = _i64
         lib.orc_mlp.argtypes = [_pd, _pf, _i, _i, _i, _i, _d, _pd]
         lib.orc_mlp.restype = None
+        lib.orc_neighbour.argtypes = [C.c_float, _i, _d, _d, _i, _d]
+        lib.orc_neighbour.restype = _i
         lib.orc_histogram.argtypes = [_pf, _i64, _i, _pf, _i, _i, _i, _i, _d, _d, _i,
-                                      _pf, _pf, _d, _pd]
+                                      _pf, _pf, _d, _d, _pd]
         lib.orc_histogram.restype = _i
         lib.orc_conv1d.argtypes = [_pd, _i, _i, _pf, _pf, _i, _i, _pd]
         lib.orc_conv1d.restype = None
@@ -63,7 +65,7 @@ def load():
         lib.orc_peaks.argtypes = [_pd, _i, _d, _d, _d, _d, _i, _i, _pi, _pd, _pd, _pd]
         lib.orc_peaks.restype = _i
         lib.orc_event.argtypes = [_pf, _i64, _i, _pf, _i, _i, _i, _i, _i, _i, _i, _d, _d,
-                                  _pf, _pf, _d, _d, _i, _d, _d, _i, _i,
+                                  _pf, _pf, _d, _d, _i, _d, _i, _d, _d, _i, _i,
                                   _pd, _pd, _pd, _pi, _pi, _pd, _pd, _pd]
         lib.orc_event.restype = _i
         _LIB = lib
@@ -82,7 +84,9 @@ def _dp(a):
 @dataclass(frozen=True)
 class Geometry:
     """Histogram geometry and peak thresholds (Section 2: 40 intervals x 100
-    bins over 400 mm; thresholds as configured)."""
+    bins over 400 mm; thresholds as configured).  boundary_mm > 0 lets
+    boundary tracks feed the neighbouring interval too; layout "interval"
+    runs the UNet on every interval on its own (Section 3 variants)."""
     z_min: float = -100.0
     bin_width: float = 0.1
     n_intervals: int = 40
@@ -91,6 +95,8 @@ class Geometry:
     s_min: float = 0.2
     half_window: int = 5
     max_peaks: int = 2000
+    boundary_mm: float = 0.0
+    layout: str = "event"
 
     @property
     def n_bins(self) -> int:
@@ -112,6 +118,15 @@ def _mlp_params(w) -> np.ndarray:
     names = [n for n, _, _ in w.shape.tensor_list() if n.startswith("mlp")]
     return np.ascontiguousarray(np.concatenate([w.tensors[n].ravel() for n in names]),
                                 dtype=np.float32)
+
+
+_LAYOUTS = {"event": 0, "interval": 1}
+
+
+def neighbour(z: float, interval: int, geo: Geometry) -> int:
+    """Interval a boundary track also feeds, or -1."""
+    return load().orc_neighbour(float(np.float32(z)), interval, geo.z_min, geo.interval_mm,
+                                geo.n_intervals, geo.boundary_mm)
 
 
 def bin_index(z: float, geo: Geometry = Geometry()) -> int:
@@ -146,7 +161,8 @@ def histogram(tracks, w, geo: Geometry = Geometry()):
     H = np.zeros(geo.n_bins, np.float64)
     T = tr.shape[1] if tr.ndim == 2 else 0
     d = load().orc_histogram(trp, max(T, 1), T, pvp, s.n_feat, s.hidden, s.n_hidden, s.n_out,
-                             geo.z_min, geo.interval_mm, geo.n_intervals, shp, scp, w.leaky, _dp(H))
+                             geo.z_min, geo.interval_mm, geo.n_intervals, shp, scp, w.leaky,
+                             geo.boundary_mm, _dp(H))
     return H, d
 
 
@@ -276,7 +292,8 @@ def run_event(tracks, w, geo: Geometry = Geometry(), _pv=None) -> dict:
     dropped = C.c_int(0)
     n = load().orc_event(trp, max(T, 1), T, pvp, s.n_feat, s.hidden, s.n_hidden, s.n_out,
                          s.n_levels, s.base_channels, s.ksize, w.leaky, w.s_in, shp, scp,
-                         geo.z_min, geo.bin_width, geo.n_intervals, geo.p_min, geo.s_min,
+                         geo.z_min, geo.bin_width, geo.n_intervals, geo.boundary_mm,
+                         _LAYOUTS[geo.layout], geo.p_min, geo.s_min,
                          geo.half_window, m, _dp(H), _dp(logit), _dp(p), C.byref(dropped),
                          t.ctypes.data_as(_pi), _dp(z), _dp(pr), _dp(S))
     if n < 0:

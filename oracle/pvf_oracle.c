@@ -12,8 +12,10 @@
  *              of 100 bins; an FC network per track whose outputs are combined
  *              into the histogram; a UNet CNN; heuristic local-maximum peak
  *              finding with thresholds.
- *   Section 3: one track feeds the interval that holds it (the one-interval
- *              case of the boundary-track rule).
+ *   Section 3: a track feeds the interval that holds it and, as a variant,
+ *              a boundary track also feeds the neighbouring interval; the
+ *              CNN input can also be batched by interval ([intervals, C,
+ *              bins]) instead of one sequence per event.
  * Where the paper is silent the reading used is stated at the function.
  * Arithmetic is double precision throughout, starting from the float32
  * input values and float32 parameters.  Loops are direct: no blocking, no
@@ -130,10 +132,33 @@ void orc_mlp(const double *g, const float *params, int n_feat, int hidden,
  * interval i of their output j, in track order; bins of intervals with no
  * track are exactly 0.  `f` points at the event's first track in plane 0 and
  * `stride` is the plane stride.  Returns the number of dropped tracks. */
+/* Boundary tracks (Section 3 lets a track feed one or two intervals; the
+ * paper gives no rule, this is the reading taken): a track closer than
+ * boundary_mm to an edge of its interval that is shared with another
+ * interval also feeds that neighbour.  Returns the neighbour's index, or -1
+ * (boundary_mm <= 0, far from both edges, or the edge ends the histogram).
+ * The distances are taken in double, like the binning. */
+int orc_neighbour(float z, int i, double z_min, double interval_mm, int n_intervals, double boundary_mm)
+{
+    if (!(boundary_mm > 0.0) || i < 0) return -1;
+    double zd = (double)z;
+    double lo = z_min + interval_mm * i;
+    double hi = z_min + interval_mm * (i + 1);
+    if (zd - lo < boundary_mm && i > 0) return i - 1;
+    if (hi - zd < boundary_mm && i < n_intervals - 1) return i + 1;
+    return -1;
+}
+
+/* Histogram of one event: H [n_intervals][n_out] (zeroed here).  Each kept
+ * track adds its network outputs to the bins of its interval; with
+ * boundary_mm > 0 a boundary track also adds the network's outputs for the
+ * neighbouring interval, its features taken in that interval's frame (the z
+ * feature then lies just outside [-1, 1)).  Returns the number of dropped
+ * tracks. */
 int orc_histogram(const float *f, int64_t stride, int n_tracks, const float *params,
                   int n_feat, int hidden, int n_hidden, int n_out,
                   double z_min, double interval_mm, int n_intervals,
-                  const float *shift, const float *scale, double slope, double *H)
+                  const float *shift, const float *scale, double slope, double boundary_mm, double *H)
 {
     double g[64], o[1024];
     int dropped = 0;
@@ -146,6 +171,11 @@ int orc_histogram(const float *f, int64_t stride, int n_tracks, const float *par
         orc_features(ft, stride, n_feat, i, z_min, interval_mm, shift, scale, g);
         orc_mlp(g, params, n_feat, hidden, n_hidden, n_out, slope, o);
         for (int j = 0; j < n_out; ++j) H[(int64_t)n_out * i + j] += o[j];
+        int nb = orc_neighbour(ft[0], i, z_min, interval_mm, n_intervals, boundary_mm);
+        if (nb < 0) continue;
+        orc_features(ft, stride, n_feat, nb, z_min, interval_mm, shift, scale, g);
+        orc_mlp(g, params, n_feat, hidden, n_hidden, n_out, slope, o);
+        for (int j = 0; j < n_out; ++j) H[(int64_t)n_out * nb + j] += o[j];
     }
     return dropped;
 }
@@ -358,14 +388,18 @@ int orc_peaks(const double *p, int L, double z_min, double bw, double p_min,
 
 /* The whole path for one event: histogram -> input scale -> UNet -> sigmoid
  * -> peaks.  Geometry: n_intervals intervals of n_out bins of width bw
- * starting at z_min (L = n_intervals * n_out bins).  Outputs H [L], logit [L],
- * p [L] and up to max_out vertices; returns the vertex count, or -1 on an
- * allocation failure.  *dropped receives the number of dropped tracks. */
+ * starting at z_min (L = n_intervals * n_out bins).  layout 0 runs the UNet
+ * once over all L bins; layout 1 (the interval-batched [intervals, C, bins]
+ * form of Section 3) runs it on every interval's n_out bins on their own,
+ * with zero padding at the interval edges, and concatenates the logits.
+ * Outputs H [L], logit [L], p [L] and up to max_out vertices; returns the
+ * vertex count, or -1 on an allocation failure.  *dropped receives the
+ * number of dropped tracks. */
 int orc_event(const float *f, int64_t stride, int n_tracks, const float *params,
               int n_feat, int hidden, int n_hidden, int n_out,
               int n_levels, int c0, int k, double slope, double s_in,
               const float *shift, const float *scale,
-              double z_min, double bw, int n_intervals,
+              double z_min, double bw, int n_intervals, double boundary_mm, int layout,
               double p_min, double s_min, int hw, int max_out,
               double *H, double *logit, double *p, int *dropped,
               int *t_out, double *z_out, double *prob_out, double *integral_out)
@@ -373,13 +407,20 @@ int orc_event(const float *f, int64_t stride, int n_tracks, const float *params,
     int L = n_intervals * n_out;
     double interval_mm = bw * n_out;
     int d = orc_histogram(f, stride, n_tracks, params, n_feat, hidden, n_hidden, n_out,
-                          z_min, interval_mm, n_intervals, shift, scale, slope, H);
+                          z_min, interval_mm, n_intervals, shift, scale, slope, boundary_mm, H);
     if (dropped) *dropped = d;
     double *x0 = (double *)malloc(sizeof(double) * L);
     if (!x0) return -1;
     for (int t = 0; t < L; ++t) x0[t] = s_in * H[t];
     const float *unet = params + orc_mlp_param_count(n_feat, hidden, n_hidden, n_out);
-    int rc = orc_unet(x0, L, unet, n_levels, c0, k, slope, logit, NULL);
+    int rc = 0;
+    if (layout == 1) {
+        for (int i = 0; i < n_intervals && rc == 0; ++i)
+            rc = orc_unet(x0 + (int64_t)i * n_out, n_out, unet, n_levels, c0, k, slope,
+                          logit + (int64_t)i * n_out, NULL);
+    } else {
+        rc = orc_unet(x0, L, unet, n_levels, c0, k, slope, logit, NULL);
+    }
     free(x0);
     if (rc != 0) return -1;
     for (int t = 0; t < L; ++t) p[t] = orc_sigmoid(logit[t]);

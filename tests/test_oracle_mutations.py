@@ -52,6 +52,15 @@ MUTATIONS = [
      "((double)f[k * stride] + (double)shift[k])", ["test_oracle_hist.py"]),
     ("height threshold not strict", "if (!(p[t] > p_min)) continue;", "if (!(p[t] >= p_min)) continue;",
      ["test_oracle_peaks.py"]),
+    ("boundary neighbour on the wrong side", "if (zd - lo < boundary_mm && i > 0) return i - 1;",
+     "if (zd - lo < boundary_mm && i > 0 && i < n_intervals - 1) return i + 1;", ["test_oracle_variants.py"]),
+    ("boundary distance not strict", "if (zd - lo < boundary_mm && i > 0)", "if (zd - lo <= boundary_mm && i > 0)",
+     ["test_oracle_variants.py"]),
+    ("upper distance sign", "if (hi - zd < boundary_mm", "if (zd - hi < boundary_mm", ["test_oracle_variants.py"]),
+    ("neighbour in the track's own frame", "orc_features(ft, stride, n_feat, nb,", "orc_features(ft, stride, n_feat, i,",
+     ["test_oracle_variants.py"]),
+    ("interval layout reads interval 0", "rc = orc_unet(x0 + (int64_t)i * n_out, n_out,",
+     "rc = orc_unet(x0, n_out,", ["test_oracle_variants.py"]),
 ]
 
 
