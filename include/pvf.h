@@ -80,7 +80,8 @@ typedef struct pvf_spec {
     int64_t  max_tracks_total;     /* tracks per call, <= INT32_MAX             */
     int32_t  compute_dtype;        /* pvf_dtype                                 */
     int32_t  n_levels;             /* UNet levels (4)                           */
-    int32_t  base_channels;        /* channels of level 0 (32); level l has
+    int32_t  base_channels;        /* channels of level 0: 32, or 64 (the paper's
+                                      deployed width); level l has
                                       base_channels << l                        */
     int32_t  n_bins;               /* histogram bins per event (4000)           */
     int32_t  bins_per_interval;    /* bins per spatial interval (100)           */
@@ -89,7 +90,22 @@ typedef struct pvf_spec {
     double   bin_width_mm;         /* bin width (0.1 mm)                        */
     double   peak_min;             /* a vertex needs p > peak_min (0.01)        */
     double   integral_min;         /* and a window sum > integral_min (0.2)     */
+    double   boundary_mm;          /* Section 3 variant: a track closer than this
+                                      to an edge shared with another interval also
+                                      feeds that interval, in its frame (0 = one
+                                      interval per track); at most half an interval */
+    int32_t  unet_layout;          /* pvf_layout: one UNet sequence per event (0),
+                                      or per interval (1, the [intervals, C, bins]
+                                      batching of Section 3)                    */
+    int32_t  reserved;             /* 0                                         */
 } pvf_spec;
+
+/* UNet input layout (Section 3 reads the FC output as [B, C, L] with B the
+ * spatial intervals).  PVF_LAYOUT_EVENT runs the UNet over all n_bins of an
+ * event; PVF_LAYOUT_INTERVAL runs it on each interval's bins_per_interval
+ * bins alone (zero padding at interval edges), which needs bins_per_interval
+ * divisible by 2^(n_levels-1), e.g. 3 levels for 100 bins. */
+typedef enum pvf_layout { PVF_LAYOUT_EVENT = 0, PVF_LAYOUT_INTERVAL = 1 } pvf_layout;
 
 /* Input view: one batch of events in structure-of-arrays form (Section 3:
  * the trigger's SoA buffers, reinterpreted without copies).

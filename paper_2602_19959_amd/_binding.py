@@ -24,6 +24,7 @@ STATUS_NAMES = {0: "PVF_OK", 1: "PVF_ERR_INVALID_ARGUMENT", 2: "PVF_ERR_SHAPE", 
                 7: "PVF_ERR_DEVICE", 8: "PVF_ERR_ALIGNMENT"}
 EV_TOO_MANY_TRACKS, EV_BAD_INPUT, EV_PEAKS_TRUNCATED, EV_TRACKS_DROPPED = 1, 2, 4, 8
 DTYPES = {"fp32": 0, "bf16": 1, "fp16": 2, "fp8_e4m3": 3}
+LAYOUTS = {"event": 0, "interval": 1}
 
 
 class Spec(C.Structure):
@@ -43,6 +44,9 @@ class Spec(C.Structure):
         ("bin_width_mm", C.c_double),
         ("peak_min", C.c_double),
         ("integral_min", C.c_double),
+        ("boundary_mm", C.c_double),
+        ("unet_layout", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 
@@ -154,6 +158,8 @@ def default_spec(**overrides) -> Spec:
     for k, v in overrides.items():
         if k == "compute_dtype" and isinstance(v, str):
             v = DTYPES[v]
+        if k == "unet_layout" and isinstance(v, str):
+            v = LAYOUTS[v]
         setattr(s, k, v)
     return s
 

@@ -85,15 +85,19 @@ __global__ __launch_bounds__(NT) void gather_channels_first(GatherArgs a)
 template <class T>
 __global__ __launch_bounds__(NT) void amax_channels(AmaxArgs a)
 {
-    // block: 256 threads = (256 / C) row lanes x C channels, 64 rows each
-    const int per = NT / a.C;
-    const int c = threadIdx.x % a.C, lr = threadIdx.x / a.C;
-    if (lr >= per) return;
+    // block: 256 threads = row lanes x channel lanes, 64 rows per row lane;
+    // C <= 256: 256 / C row lanes of C channels; C > 256: one row lane and
+    // C / 256 channels per thread
+    const int cl = a.C < NT ? a.C : NT;
+    const int per = NT / cl;
+    const int c0 = threadIdx.x % cl, lr = threadIdx.x / cl;
     const int64_t r0 = ((int64_t)blockIdx.x * per + lr) * 64;
-    float m = 0.f;
-    for (int64_t r = r0; r < r0 + 64 && r < a.rows; ++r)
-        m = fmaxf(m, fabsf((float)static_cast<const T*>(a.src)[r * a.ld + a.ch_off + c]));
-    atomicMax(reinterpret_cast<unsigned int*>(a.out + c), __float_as_uint(m));
+    for (int c = c0; c < a.C; c += NT) {
+        float m = 0.f;
+        for (int64_t r = r0; r < r0 + 64 && r < a.rows; ++r)
+            m = fmaxf(m, fabsf((float)static_cast<const T*>(a.src)[r * a.ld + a.ch_off + c]));
+        atomicMax(reinterpret_cast<unsigned int*>(a.out + c), __float_as_uint(m));
+    }
 }
 
 }  // namespace
@@ -126,8 +130,8 @@ hipError_t launch_gather(const GatherArgs& a, hipStream_t s)
 
 hipError_t launch_amax(const AmaxArgs& a, hipStream_t s)
 {
-    if (a.C <= 0 || a.C > NT || NT % a.C != 0 || a.rows <= 0) return hipErrorInvalidValue;
-    const int per = NT / a.C;
+    if (a.C <= 0 || a.rows <= 0 || (a.C <= NT ? NT % a.C : a.C % NT) != 0) return hipErrorInvalidValue;
+    const int per = a.C < NT ? NT / a.C : 1;
     const unsigned blocks = (unsigned)((a.rows + (int64_t)per * 64 - 1) / ((int64_t)per * 64));
     if (a.elem_bytes == 4) hipLaunchKernelGGL(amax_channels<float>, dim3(blocks), dim3(NT), 0, s, a);
     else if (a.dtype == PVF_BF16) hipLaunchKernelGGL(amax_channels<__bf16>, dim3(blocks), dim3(NT), 0, s, a);

@@ -242,6 +242,7 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
     if constexpr (EPI == EPI_HEAD) {
         switch (v) {
             PVF_FP8_CASE(0)
+            PVF_FP8_CASE(1)
         default: return hipErrorInvalidValue;
         }
     } else {
@@ -264,7 +265,7 @@ bool fp8_variant_ok(int v, int n, int taps, Epi epi)
     if (v < 0 || v >= kNumVariants) return false;
     (void)taps;
     const int bn = kVariants[v].wn * kVariants[v].tnw * 16;
-    if (epi == EPI_HEAD) return v == 0 && bn == n;
+    if (epi == EPI_HEAD) return (v == 0 || v == 1) && bn == n;
     return bn <= (n < 32 ? 32 : n);
 }
 
@@ -272,7 +273,8 @@ bool fp8_variant_ok(int v, int n, int taps, Epi epi)
 // smaller tile)
 int fp8_default_variant(int n, int taps, Epi epi)
 {
-    if (epi == EPI_HEAD || n <= 32) return 0;
+    if (epi == EPI_HEAD) return n == 64 ? 1 : 0;
+    if (n <= 32) return 0;
     if (epi == EPI_CONVT && taps == 1) return n >= 128 ? 3 : 0;
     if (epi == EPI_POOL) return 1;
     return n <= 64 ? 1 : 3;

@@ -297,6 +297,8 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_VARIANT_CASE(0, TAPS, EPI)
             PVF_VARIANT_CASE(1, TAPS, EPI)
             PVF_VARIANT_CASE(2, TAPS, EPI)
+            PVF_VARIANT_CASE(3, TAPS, EPI)
+            PVF_VARIANT_CASE(5, TAPS, EPI)
         default: return hipErrorInvalidValue;
         }
     } else {
@@ -326,7 +328,8 @@ bool f32_variant_ok(int v, int n, int taps, Epi epi)
     if (v < 0 || v >= kNumVariants) return false;
     const Variant& x = kVariants[v];
     const int bn = x.wn * x.tnw * 16;
-    if (epi == EPI_HEAD) return v <= 2 && bn == n && x.wn == 1;
+    // the head reduces over all channels inside one wave's columns
+    if (epi == EPI_HEAD) return (v <= 3 || v == 5) && bn == n && x.wn == 1;
     (void)taps;
     return bn <= (n < 32 ? 32 : n);
 }
@@ -337,6 +340,7 @@ bool f32_variant_ok(int v, int n, int taps, Epi epi)
 int f32_default_variant(int n, int taps, Epi epi)
 {
     if (epi == EPI_CONVT && taps == 1) return n >= 128 ? 9 : (n >= 64 ? 5 : 0);
+    if (epi == EPI_HEAD) return n == 64 ? 3 : 0;
     return 0;
 }
 

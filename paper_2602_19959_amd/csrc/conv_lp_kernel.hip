@@ -328,6 +328,8 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
     if constexpr (EPI == EPI_HEAD) {
         switch (v) {
             PVF_LP_CASE(0)
+            PVF_LP_CASE(1)
+            PVF_LP_CASE(4)
             PVF_LP_CASE(5)
             PVF_LP_CASE(11)
         default: return hipErrorInvalidValue;
@@ -377,14 +379,14 @@ bool lp_variant_ok(int v, int n, int cin, int taps, Epi epi)
     const Variant& x = kVariants[v];
     const int bn = x.wn * x.tnw * 16;
     if (cin % x.kc != 0) return false;
-    if (epi == EPI_HEAD) return (v == 0 || v == 5 || v == 11) && bn == n;
+    if (epi == EPI_HEAD) return (v == 0 || v == 1 || v == 4 || v == 5 || v == 11) && bn == n && x.wn == 1;
     return bn <= (n < 32 ? 32 : n);
 }
 
 // Defaults from a BF16 sweep on MI355X at 1000 events.
 int lp_default_variant(int n, int cin, int taps, Epi epi)
 {
-    if (epi == EPI_HEAD) return 0;
+    if (epi == EPI_HEAD) return n == 64 ? 1 : 0;
     if (epi == EPI_CONVT && taps == 1) return n >= 128 ? 6 : 4;
     if (n <= 32) return 11;
     if (n <= 64) return cin <= 32 ? 4 : 11;

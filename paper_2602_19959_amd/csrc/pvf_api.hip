@@ -34,14 +34,20 @@ pvf_status validate_spec(const pvf_spec* s)
           std::isfinite(s->peak_min) && std::isfinite(s->integral_min)))
         return PVF_ERR_INVALID_ARGUMENT;
     if (s->half_window < 0) return PVF_ERR_INVALID_ARGUMENT;
+    if (s->unet_layout != PVF_LAYOUT_EVENT && s->unet_layout != PVF_LAYOUT_INTERVAL) return PVF_ERR_INVALID_ARGUMENT;
+    if (s->reserved != 0) return PVF_ERR_INVALID_ARGUMENT;
     if (s->n_levels < 2 || s->n_levels > kMaxLevels) return PVF_ERR_SHAPE;
-    // the head epilogue holds all level-0 channels in one 32-wide tile
-    if (s->base_channels != 32) return PVF_ERR_SHAPE;
+    // the head epilogue holds all level-0 channels in one 32- or 64-wide tile
+    if (s->base_channels != 32 && s->base_channels != 64) return PVF_ERR_SHAPE;
     if (s->n_bins < 4 || s->n_bins > kMaxBins) return PVF_ERR_SHAPE;
     if (s->bins_per_interval < 1 || s->bins_per_interval > kMaxBinsPerInterval ||
         s->n_bins % s->bins_per_interval != 0)
         return PVF_ERR_SHAPE;
-    if (s->n_bins % (1 << (s->n_levels - 1)) != 0) return PVF_ERR_SHAPE;
+    const int seq = s->unet_layout == PVF_LAYOUT_INTERVAL ? s->bins_per_interval : s->n_bins;
+    if (seq < 4 || seq % (1 << (s->n_levels - 1)) != 0) return PVF_ERR_SHAPE;
+    const double interval_mm = s->bin_width_mm * s->bins_per_interval;
+    if (!std::isfinite(s->boundary_mm) || s->boundary_mm < 0 || s->boundary_mm > 0.5 * interval_mm)
+        return PVF_ERR_INVALID_ARGUMENT;
     if (s->max_peaks_per_event > s->n_bins) return PVF_ERR_SHAPE;
     return PVF_OK;
 }
@@ -52,12 +58,15 @@ void make_plan(const pvf_spec* s, size_t weight_floats, Plan* p)
     p->n_levels = s->n_levels;
     p->c0 = s->base_channels;
     p->max_events = s->max_events;
+    // UNet sequences: one per event, or one per interval
+    p->units = s->unet_layout == PVF_LAYOUT_INTERVAL ? s->n_bins / s->bins_per_interval : 1;
+    const int seq = s->n_bins / p->units;
     for (int l = 0; l < s->n_levels; ++l) {
-        p->lv[l].L = s->n_bins >> l;
+        p->lv[l].L = seq >> l;
         p->lv[l].R = p->lv[l].L + 2 * kGuard;
         p->lv[l].C = s->base_channels << l;
     }
-    const size_t E = (size_t)s->max_events;
+    const size_t E = (size_t)s->max_events * p->units;     // UNet sequences
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     p->weights_bytes = weight_floats * sizeof(float);
@@ -75,9 +84,9 @@ void make_plan(const pvf_spec* s, size_t weight_floats, Plan* p)
         if (l >= 1) p->d[l] = take(rows * p->lv[l].C * eb);
     }
     p->zero_end = off;
-    p->prob = take(E * p->lv[0].L * sizeof(float));
-    p->flags = take(E * sizeof(int32_t));
-    p->order = take(E * sizeof(int32_t));
+    p->prob = take((size_t)s->max_events * s->n_bins * sizeof(float));
+    p->flags = take((size_t)s->max_events * sizeof(int32_t));
+    p->order = take((size_t)s->max_events * sizeof(int32_t));
     p->scales = s->compute_dtype == PVF_FP8_E4M3 ? take(kMaxScaleFloats * sizeof(float)) : 0;
     p->queue = take(((size_t)s->max_tracks_per_event + 3) * sizeof(int32_t));
     p->total = off;
@@ -541,6 +550,7 @@ ConvArgs conv_args(pvf_engine* eng, const WeightLayout::Conv& c, const void* in,
 pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* out, hipStream_t s)
 {
     const int E = tr->n_events;
+    const int EU = E * eng->plan.units;          // UNet sequences
     const int dt = eng->spec.compute_dtype;
     const size_t eb = (size_t)act_bytes(dt);
     const Plan& P = eng->plan;
@@ -578,6 +588,8 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
     ta.s_in = eng->s_in;
     ta.x0 = at<float>(eng, P.x0);
     ta.r0 = P.lv[0].R;
+    ta.unit_bins = P.lv[0].L;
+    ta.boundary_mm = eng->spec.boundary_mm;
     ta.flags = flags;
     ta.order = at<int32_t>(eng, P.order);
     ta.queue_counter = at<int32_t>(eng, P.queue);
@@ -591,7 +603,7 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
         m.src = base;
         m.elem_bytes = (int)eb;
         m.dtype = dt;
-        m.rows = (int64_t)E * P.lv[level].R;
+        m.rows = (int64_t)EU * P.lv[level].R;
         m.ld = ld;
         m.C = C;
         m.ch_off = ch_off;
@@ -618,7 +630,7 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
     // ---- encoder
     FirstConvArgs fa{};
     fa.x0 = at<float>(eng, P.x0);
-    fa.m_rows = E * P.lv[0].R;
+    fa.m_rows = EU * P.lv[0].R;
     fa.r0 = P.lv[0].R;
     fa.w = wbase + W.first_w;
     fa.b = wbase + W.first_b;
@@ -633,17 +645,17 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
         const Level& lv = P.lv[l];
         if (l > 0) {
             const Level& up = P.lv[l - 1];
-            conv(conv_args(eng, W.enc[l][0], act(P.pool[l]), up.C, lv.R, E, act(P.a[l]), lv.C), kTaps, EPI_STORE,
+            conv(conv_args(eng, W.enc[l][0], act(P.pool[l]), up.C, lv.R, EU, act(P.a[l]), lv.C), kTaps, EPI_STORE,
                  l, lv.C, 0);
         }
         if (l < n - 1) {
-            ConvArgs a = conv_args(eng, W.enc[l][1], act(P.a[l]), lv.C, lv.R, E, act(P.cat[l]), 2 * lv.C);
+            ConvArgs a = conv_args(eng, W.enc[l][1], act(P.a[l]), lv.C, lv.R, EU, act(P.cat[l]), 2 * lv.C);
             a.pool_out = act(P.pool[l + 1]);
             a.ld_pool = lv.C;
             a.r_pool = P.lv[l + 1].R;
             conv(a, kTaps, EPI_POOL, l, 2 * lv.C, 0);
         } else {
-            conv(conv_args(eng, W.enc[l][1], act(P.a[l]), lv.C, lv.R, E, act(P.d[l]), lv.C), kTaps, EPI_STORE, l,
+            conv(conv_args(eng, W.enc[l][1], act(P.a[l]), lv.C, lv.R, EU, act(P.d[l]), lv.C), kTaps, EPI_STORE, l,
                  lv.C, 0);
         }
     }
@@ -651,19 +663,19 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
     for (int l = n - 2; l >= 0; --l) {
         const Level& lv = P.lv[l];
         const Level& lo = P.lv[l + 1];
-        ConvArgs u = conv_args(eng, W.up[l], act(P.d[l + 1]), lo.C, lo.R, E, act(P.cat[l]) + (size_t)lv.C * eb,
+        ConvArgs u = conv_args(eng, W.up[l], act(P.d[l + 1]), lo.C, lo.R, EU, act(P.cat[l]) + (size_t)lv.C * eb,
                                2 * lv.C);
         u.n = 2 * lv.C;
         u.cout = lv.C;
         u.r_out = lv.R;
         conv(u, 1, EPI_CONVT, l, 2 * lv.C, lv.C);
-        conv(conv_args(eng, W.dec[l][0], act(P.cat[l]), 2 * lv.C, lv.R, E, act(P.a[l]), lv.C), kTaps, EPI_STORE, l,
+        conv(conv_args(eng, W.dec[l][0], act(P.cat[l]), 2 * lv.C, lv.R, EU, act(P.a[l]), lv.C), kTaps, EPI_STORE, l,
              lv.C, 0);
         if (l > 0) {
-            conv(conv_args(eng, W.dec[l][1], act(P.a[l]), lv.C, lv.R, E, act(P.d[l]), lv.C), kTaps, EPI_STORE, l,
+            conv(conv_args(eng, W.dec[l][1], act(P.a[l]), lv.C, lv.R, EU, act(P.d[l]), lv.C), kTaps, EPI_STORE, l,
                  lv.C, 0);
         } else {
-            ConvArgs b = conv_args(eng, W.dec[0][1], act(P.a[0]), lv.C, lv.R, E, nullptr, 0);
+            ConvArgs b = conv_args(eng, W.dec[0][1], act(P.a[0]), lv.C, lv.R, EU, nullptr, 0);
             b.head_w = wbase + W.head_w;
             b.head_b = eng->head_b;
             b.prob = prob;
@@ -674,7 +686,7 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
     // ---- peaks
     PeakArgs pa{};
     pa.prob = prob;
-    pa.L = P.lv[0].L;
+    pa.L = eng->spec.n_bins;
     pa.flags = flags;
     pa.z_min = eng->spec.z_min_mm;
     pa.bw = eng->spec.bin_width_mm;
@@ -1090,7 +1102,7 @@ pvf_status pvf_debug_tensor(pvf_engine* eng, const char* name, int32_t n_events,
         if (producer < 0) return PVF_ERR_INVALID_ARGUMENT;
         g.ch_scale = at<float>(eng, P.scales) + eng->a_off[producer];
     }
-    g.count = (int64_t)n_events * g.C * g.L;
+    g.count = (int64_t)n_events * P.units * g.C * g.L;
     *out_count = g.count;
     if (!d_dst) return PVF_OK;
     g.dst = d_dst;

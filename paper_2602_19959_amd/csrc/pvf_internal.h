@@ -38,15 +38,17 @@ struct Plan {
     int n_levels = 0;
     int c0 = 0;
     int max_events = 0;
+    int units = 1;                 // UNet sequences per event (1, or the interval count)
     Level lv[kMaxLevels];
     size_t weights = 0, weights_bytes = 0;
     size_t weights_lp = 0;         // 16-bit conv weights (BF16/FP16 engines)
+    // E below is the number of UNet sequences (events x units)
     size_t x0 = 0;                 // [E][R0][1]      scaled histogram (always FP32)
     size_t a[kMaxLevels] = {};     // [E][Rl][Cl]     conv1 outputs (enc, then dec)
     size_t cat[kMaxLevels] = {};   // [E][Rl][2Cl]    skip | upsampled  (l < n-1)
     size_t pool[kMaxLevels] = {};  // [E][Rl][C(l-1)] pooled input of level l (l >= 1)
     size_t d[kMaxLevels] = {};     // [E][Rl][Cl]     decoder conv2 out (1 <= l <= n-2), deepest conv2 (l = n-1)
-    size_t prob = 0;               // [E][L0] float
+    size_t prob = 0;               // [events][n_bins] float
     size_t flags = 0;              // [E] int32 track-stage status
     size_t order = 0;              // [E] int32 event order of the track work queue
     size_t scales = 0;             // FP8: per-launch column and output scales
@@ -109,8 +111,10 @@ struct TrackArgs {
     float scale[kFeat];
     float slope;
     float s_in;
-    float* x0;               // [E][R0]
+    double boundary_mm;      // > 0: boundary tracks also feed the neighbouring interval
+    float* x0;               // [E * units][R0]
     int r0;
+    int unit_bins;           // bins per UNet sequence (n_bins, or bins per interval)
     int32_t* flags;          // [E]
     int32_t* order;          // [E] queue order (persistent form), or null
     int32_t* queue_counter;  // ticket counter (persistent form), or null

@@ -5,6 +5,12 @@
 // over 40 intervals of 100 bins; Section 3: a track feeds the interval that
 // holds it, and an event is processed by one block reading SoA buffers.
 //
+// Boundary tracks (Section 3 variant): a track closer than boundary_mm to an
+// edge its interval shares with another one also feeds that neighbour, its
+// features taken in the neighbour's frame.  After a chunk's own items are
+// accumulated, its boundary tracks are compacted into a staging list (track
+// order) and go through the network and the accumulation once more.
+//
 // Per chunk of 256 tracks (one per thread, coalesced SoA loads):
 //   A  bin the track (exact comparison with the interval edges in double),
 //      build its features and run the hidden layers in registers; the
@@ -34,16 +40,62 @@ __device__ __forceinline__ float softplus(float x)
     return fmaxf(x, 0.f) + log1pf(expf(-fabsf(x)));
 }
 
+// Exact (uncontracted) lower edge of interval i, as the binning takes it.
+__device__ __forceinline__ double edge(const TrackArgs& a, int i)
+{
+    return __dadd_rn(a.z_min, __dmul_rn(a.interval_mm, (double)i));
+}
+
+// Hidden layers of one track with its features taken in the frame of
+// interval itv (z offset mapped to [-1, 1) inside that interval).
+__device__ __forceinline__ void hidden_layers(const TrackArgs& a, const float* f, double zd, int itv, float* h)
+{
+    const float* W1 = a.mlp;                               // [kHidden][kFeat]
+    const float* b1 = W1 + kHidden * kFeat;
+    const float* Wh = b1 + kHidden;                        // hidden layers 2.. : [W 20x20, b 20]
+    float g[kFeat];
+    g[0] = (float)((zd - edge(a, itv)) / (a.interval_mm * 0.5) - 1.0);
+#pragma unroll
+    for (int k = 1; k < kFeat; ++k) g[k] = (f[k] - a.shift[k]) * a.scale[k];
+#pragma unroll
+    for (int j = 0; j < kHidden; ++j) {
+        float s = b1[j];
+#pragma unroll
+        for (int k = 0; k < kFeat; ++k) s = fmaf(W1[j * kFeat + k], g[k], s);
+        h[j] = lrelu(s, a.slope);
+    }
+    for (int l = 1; l < a.n_hidden; ++l) {
+        const float* W = Wh + (size_t)(l - 1) * (kHidden * kHidden + kHidden);
+        const float* bb = W + kHidden * kHidden;
+        float hn[kHidden];
+#pragma unroll
+        for (int j = 0; j < kHidden; ++j) {
+            float s = bb[j];
+#pragma unroll
+            for (int k = 0; k < kHidden; ++k) s = fmaf(W[j * kHidden + k], h[k], s);
+            hn[j] = lrelu(s, a.slope);
+        }
+#pragma unroll
+        for (int j = 0; j < kHidden; ++j) h[j] = hn[j];
+    }
+}
+
 __device__ void track_event(const TrackArgs& a, int e, float* smem)
 {
     const int n_bins = a.n_out * a.n_intervals;
     float* H = smem;                                  // [n_bins]
     float* hb = H + n_bins;                           // [NT][HP]
     float* ob = hb + NT * HP;                         // [SUB][n_out + 1]
-    int* iv = reinterpret_cast<int*>(ob + SUB * (a.n_out + 1));   // [NT]
+    int* iv = reinterpret_cast<int*>(ob + SUB * (a.n_out + 1));   // [NT] interval of each item
+    int* nbv = iv + NT;                               // [NT] neighbour interval of each track, or -1
+    // staging list of the chunk's boundary tracks; it shares ob's space: it is
+    // written after the own items' last use of ob and read before ob's next
+    int* st = reinterpret_cast<int*>(ob);
     __shared__ int dropped_any;
+    __shared__ int wave_count[NT / 64];
 
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int op = a.n_out + 1;
 
     for (int b = tid; b < n_bins; b += NT) H[b] = 0.f;
@@ -56,105 +108,134 @@ __device__ void track_event(const TrackArgs& a, int e, float* smem)
     else if (end - beg > a.max_tracks) status = PVF_EV_TOO_MANY_TRACKS;
     __syncthreads();
 
-    const float* W1 = a.mlp;                               // [kHidden][kFeat]
-    const float* b1 = W1 + kHidden * kFeat;
-    const float* Wh = b1 + kHidden;                        // hidden layers 2.. : [W 20x20, b 20]
-    const float* Wo = Wh + (size_t)(a.n_hidden - 1) * (kHidden * kHidden + kHidden);  // [n_out][kHidden]
+    const float* Wo = a.mlp + kHidden * kFeat + kHidden +
+                      (size_t)(a.n_hidden - 1) * (kHidden * kHidden + kHidden);   // [n_out][kHidden]
     const float* bo = Wo + (size_t)a.n_out * kHidden;
-    const double z_max = a.z_min + a.interval_mm * a.n_intervals;
+    const double z_max = edge(a, a.n_intervals);
+    const bool two = a.boundary_mm > 0.0;
+
+    // B + C over the first n items of hb / iv: outputs, then the ordered
+    // accumulation (thread j owns column j, items in list order)
+    auto outputs_and_accumulate = [&](int n) {
+        for (int sub = 0; sub < n; sub += SUB) {
+            // ---- B: wave q computes outputs q, q+4, ... for 64 items
+            const int tt = sub + lane;
+            if (tt < n && iv[tt] >= 0) {
+                float hl[kHidden];
+#pragma unroll
+                for (int k = 0; k < kHidden; ++k) hl[k] = hb[tt * HP + k];
+                for (int j = wave; j < a.n_out; j += NT / 64) {
+                    float s = bo[j];
+#pragma unroll
+                    for (int k = 0; k < kHidden; ++k) s = fmaf(Wo[j * kHidden + k], hl[k], s);
+                    ob[lane * op + j] = softplus(s);
+                }
+            }
+            __syncthreads();
+            // ---- C: ordered accumulation
+            if (tid < a.n_out) {
+                const int lim = (n - sub) < SUB ? (n - sub) : SUB;
+                for (int l = 0; l < lim; ++l) {
+                    const int i = iv[sub + l];
+                    if (i >= 0) H[i * a.n_out + tid] += ob[l * op + tid];
+                }
+            }
+            __syncthreads();
+        }
+    };
 
     if (status == 0) {
         for (int64_t base = beg; base < end; base += NT) {
-            // ---- A: bin, features, hidden layers
+            // ---- A: bin, features, hidden layers (own interval)
             const int64_t t = base + tid;
-            int itv = -1;
+            int itv = -1, nb = -1;
+            float f[kFeat];
+            double zd = 0.0;
             float h[kHidden];
 #pragma unroll
             for (int j = 0; j < kHidden; ++j) h[j] = 0.f;
             if (t < end) {
-                float f[kFeat];
                 bool finite = true;
 #pragma unroll
                 for (int k = 0; k < kFeat; ++k) {
                     f[k] = a.feat[k][t];
                     finite = finite && isfinite(f[k]);
                 }
-                const double zd = (double)f[0];
+                zd = (double)f[0];
                 if (finite && zd >= a.z_min && zd < z_max) {
                     int i = (int)floor((zd - a.z_min) / a.interval_mm);
                     i = i < 0 ? 0 : (i >= a.n_intervals ? a.n_intervals - 1 : i);
-                    if (zd < a.z_min + a.interval_mm * i) --i;
-                    else if (zd >= a.z_min + a.interval_mm * (i + 1)) ++i;
+                    if (zd < edge(a, i)) --i;
+                    else if (zd >= edge(a, i + 1)) ++i;
                     if (i >= 0 && i < a.n_intervals) itv = i;
                 }
                 if (itv < 0) {
                     dropped_any = 1;   // benign race: every writer stores 1
                 } else {
-                    float g[kFeat];
-                    const double lo = a.z_min + a.interval_mm * itv;
-                    g[0] = (float)((zd - lo) / (a.interval_mm * 0.5) - 1.0);
-#pragma unroll
-                    for (int k = 1; k < kFeat; ++k) g[k] = (f[k] - a.shift[k]) * a.scale[k];
-#pragma unroll
-                    for (int j = 0; j < kHidden; ++j) {
-                        float s = b1[j];
-#pragma unroll
-                        for (int k = 0; k < kFeat; ++k) s = fmaf(W1[j * kFeat + k], g[k], s);
-                        h[j] = lrelu(s, a.slope);
-                    }
-                    for (int l = 1; l < a.n_hidden; ++l) {
-                        const float* W = Wh + (size_t)(l - 1) * (kHidden * kHidden + kHidden);
-                        const float* bb = W + kHidden * kHidden;
-                        float hn[kHidden];
-#pragma unroll
-                        for (int j = 0; j < kHidden; ++j) {
-                            float s = bb[j];
-#pragma unroll
-                            for (int k = 0; k < kHidden; ++k) s = fmaf(W[j * kHidden + k], h[k], s);
-                            hn[j] = lrelu(s, a.slope);
-                        }
-#pragma unroll
-                        for (int j = 0; j < kHidden; ++j) h[j] = hn[j];
+                    hidden_layers(a, f, zd, itv, h);
+                    // boundary track: closer than boundary_mm to an edge shared
+                    // with another interval (distances in double, exact edges)
+                    if (two) {
+                        if (zd - edge(a, itv) < a.boundary_mm && itv > 0) nb = itv - 1;
+                        else if (edge(a, itv + 1) - zd < a.boundary_mm && itv < a.n_intervals - 1) nb = itv + 1;
                     }
                 }
             }
 #pragma unroll
             for (int j = 0; j < kHidden; ++j) hb[tid * HP + j] = h[j];
             iv[tid] = itv;
+            nbv[tid] = nb;
             __syncthreads();
 
             const int n_chunk = (int)((end - base) < NT ? (end - base) : NT);
-            for (int sub = 0; sub < n_chunk; sub += SUB) {
-                // ---- B: wave q computes outputs q, q+4, ... for the 64 tracks
-                const int lane = tid & 63, q = tid >> 6;
-                const int tt = sub + lane;
-                if (tt < n_chunk && iv[tt] >= 0) {
-                    float hl[kHidden];
-#pragma unroll
-                    for (int k = 0; k < kHidden; ++k) hl[k] = hb[tt * HP + k];
-                    for (int j = q; j < a.n_out; j += NT / 64) {
-                        float s = bo[j];
-#pragma unroll
-                        for (int k = 0; k < kHidden; ++k) s = fmaf(Wo[j * kHidden + k], hl[k], s);
-                        ob[lane * op + j] = softplus(s);
-                    }
-                }
+            outputs_and_accumulate(n_chunk);
+
+            if (two) {
+                // ---- staging: the chunk's boundary tracks, in track order
+                const bool is_b = nbv[tid] >= 0;
+                const uint64_t m = __ballot(is_b);
+                if (lane == 0) wave_count[wave] = __popcll(m);
                 __syncthreads();
-                // ---- C: ordered accumulation, thread j owns column j
-                if (tid < a.n_out) {
-                    const int lim = (n_chunk - sub) < SUB ? (n_chunk - sub) : SUB;
-                    for (int l = 0; l < lim; ++l) {
-                        const int i = iv[sub + l];
-                        if (i >= 0) H[i * a.n_out + tid] += ob[l * op + tid];
-                    }
+                int off = 0, n_st = 0;
+#pragma unroll
+                for (int w = 0; w < NT / 64; ++w) {
+                    off += w < wave ? wave_count[w] : 0;
+                    n_st += wave_count[w];
                 }
+                if (is_b) st[off + __popcll(m & ((1ull << lane) - 1ull))] = tid;
                 __syncthreads();
+                if (n_st > 0) {
+                    // ---- A again for the staged items, in the neighbour's frame
+                    int inb = -1;
+#pragma unroll
+                    for (int j = 0; j < kHidden; ++j) h[j] = 0.f;
+                    if (tid < n_st) {
+                        const int src = st[tid];
+                        inb = nbv[src];
+                        float g[kFeat];
+#pragma unroll
+                        for (int k = 0; k < kFeat; ++k) g[k] = a.feat[k][base + src];
+                        hidden_layers(a, g, (double)g[0], inb, h);
+                    }
+                    __syncthreads();    // every read of nbv / st above is done
+#pragma unroll
+                    for (int j = 0; j < kHidden; ++j) hb[tid * HP + j] = h[j];
+                    iv[tid] = inb;
+                    __syncthreads();
+                    outputs_and_accumulate(n_st);
+                }
             }
         }
     }
     __syncthreads();
-    float* x0 = a.x0 + (int64_t)e * a.r0 + kGuard;
-    for (int b = tid; b < n_bins; b += NT) x0[b] = a.s_in * H[b];
+    // scaled histogram into the UNet's input rows: one sequence per event, or
+    // one per interval (unit_bins bins each), two guard rows on each side
+    const int U = n_bins / a.unit_bins;
+    float* x0 = a.x0 + (int64_t)e * U * a.r0 + kGuard;
+    for (int b = tid; b < n_bins; b += NT) {
+        const int u = b / a.unit_bins;
+        x0[(int64_t)u * a.r0 + (b - u * a.unit_bins)] = a.s_in * H[b];
+    }
     if (tid == 0) a.flags[e] = status | (dropped_any ? PVF_EV_TRACKS_DROPPED : 0);
     __syncthreads();   // the block's LDS is reused by its next event
 }
@@ -235,7 +316,7 @@ __global__ __launch_bounds__(kOrderThreads) void track_order(TrackArgs a, int n_
 
 static size_t track_stage_lds_bytes(int n_out, int n_intervals)
 {
-    return sizeof(float) * ((size_t)n_out * n_intervals + NT * HP + SUB * (n_out + 1)) + sizeof(int) * NT;
+    return sizeof(float) * ((size_t)n_out * n_intervals + NT * HP + SUB * (n_out + 1)) + sizeof(int) * 2 * NT;
 }
 
 hipError_t launch_track(const TrackArgs& a, int n_events, int persistent_blocks, int* order_scratch,

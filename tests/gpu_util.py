@@ -17,30 +17,35 @@ def torch_cuda():
 
 
 @functools.lru_cache(maxsize=None)
-def weights(seed=0):
-    return make_weights(seed)
+def weights(seed=0, shape=None):
+    return make_weights(seed) if shape is None else make_weights(seed, shape=shape)
 
 
 @functools.lru_cache(maxsize=None)
-def blob(seed=0):
-    return weights_to_blob(weights(seed))
+def blob(seed=0, shape=None):
+    return weights_to_blob(weights(seed, shape))
 
 
-def make_engine(max_events, fp8_amax=None, **spec):
+def make_engine(max_events, fp8_amax=None, shape=None, **spec):
+    """Engine for `max_events`; `shape` (a synth NetShape) selects the
+    network (its levels and width go into the spec too)."""
     import paper_2602_19959_amd as pv
+    if shape is not None:
+        spec.setdefault("n_levels", shape.n_levels)
+        spec.setdefault("base_channels", shape.base_channels)
     s = pv.default_spec(max_events=max_events, **spec)
     if "max_tracks_total" not in spec:
         s.max_tracks_total = max_events * 1500
-    return pv.Engine(blob(), s, fp8_amax=fp8_amax)
+    return pv.Engine(blob(0, shape), s, fp8_amax=fp8_amax)
 
 
 @functools.lru_cache(maxsize=None)
-def fp8_calibration(n_events=64, seed=5):
+def fp8_calibration(n_events=64, seed=5, shape=None):
     """Calibration table of an FP32 engine over `n_events` events of `seed`
     (events the FP8 tests never score)."""
     import paper_2602_19959_amd as pv
     batch = make_events(n_events, seed=seed)
-    eng = make_engine(n_events)
+    eng = make_engine(n_events, shape=shape)
     feat, off = pv.upload_events(batch)
     amax = eng.calibrate(feat, off)
     eng.close()
@@ -63,7 +68,8 @@ def geometry(engine):
                            n_intervals=s.n_bins // s.bins_per_interval,
                            bins_per_interval=s.bins_per_interval, p_min=s.peak_min,
                            s_min=s.integral_min, half_window=s.half_window,
-                           max_peaks=s.max_peaks_per_event)
+                           max_peaks=s.max_peaks_per_event, boundary_mm=s.boundary_mm,
+                           layout=("event", "interval")[s.unet_layout])
 
 
 def event_vertices(host, e):

@@ -105,6 +105,13 @@ MATCH_MIN = {"bf16": 0.995, "fp16": 0.999, "fp8_e4m3": 0.95}
 EXTRA_MAX = {"bf16": 0.005, "fp16": 0.001, "fp8_e4m3": 0.05}
 DZ_MATCH = 0.05
 
+# The 64-channel network (the paper's deployed width) sums twice as many
+# rounded products per output and has larger activations; the same
+# emulations on 6 seed-1 events give max|dp| 3.4e-2 (BF16), 4.5e-3 (FP16) and
+# 0.38 (FP8, per-channel scales), with 99.8-100% of vertices matched.
+P_ABS_WIDE = {"bf16": 5e-2, "fp16": 7e-3, "fp8_e4m3": 0.5}
+MATCH_MIN_WIDE = {"bf16": 0.995, "fp16": 0.999, "fp8_e4m3": 0.97}
+
 
 def match_vertices(z_gpu, z_ref, tol=DZ_MATCH):
     """One-to-one matching of two sorted vertex lists by |dz| <= tol

@@ -32,8 +32,9 @@ def test_struct_layout_matches_header(tmp_path):
         #include <stddef.h>
         #include "pvf.h"
         int main(void) {
-          printf("%zu %zu %zu %zu %zu\\n", sizeof(pvf_spec), offsetof(pvf_spec, max_tracks_total),
-                 offsetof(pvf_spec, z_min_mm), offsetof(pvf_spec, integral_min), offsetof(pvf_spec, half_window));
+          printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(pvf_spec), offsetof(pvf_spec, max_tracks_total),
+                 offsetof(pvf_spec, z_min_mm), offsetof(pvf_spec, integral_min), offsetof(pvf_spec, half_window),
+                 offsetof(pvf_spec, boundary_mm), offsetof(pvf_spec, unet_layout));
           printf("%zu %zu %zu\\n", sizeof(pvf_tracks), offsetof(pvf_tracks, d_event_offsets),
                  offsetof(pvf_tracks, d_feat));
           printf("%zu %zu\\n", sizeof(pvf_vertices), offsetof(pvf_vertices, d_bin));
@@ -44,7 +45,8 @@ def test_struct_layout_matches_header(tmp_path):
     lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
     a = [int(x) for x in lines[0].split()]
     assert a == [C.sizeof(B.Spec), B.Spec.max_tracks_total.offset, B.Spec.z_min_mm.offset,
-                 B.Spec.integral_min.offset, B.Spec.half_window.offset]
+                 B.Spec.integral_min.offset, B.Spec.half_window.offset, B.Spec.boundary_mm.offset,
+                 B.Spec.unet_layout.offset]
     b = [int(x) for x in lines[1].split()]
     assert b == [C.sizeof(B.Tracks), B.Tracks.d_event_offsets.offset, B.Tracks.d_feat.offset]
     c = [int(x) for x in lines[2].split()]
@@ -57,6 +59,18 @@ def test_default_spec():
     assert s.z_min_mm == -100.0 and s.bin_width_mm == 0.1
     assert (s.peak_min, s.integral_min, s.half_window) == (0.01, 0.2, 5)
     assert s.compute_dtype == 0 and s.abi_version == 1
+    assert s.boundary_mm == 0.0 and s.unet_layout == 0
+
+
+def test_interval_layout_shapes():
+    """One UNet sequence per interval: 100 bins need 3 levels (100/50/25);
+    the arena grows by the extra guard rows of 40 sequences."""
+    ok = pv.default_spec(max_events=1, unet_layout=1, n_levels=3)
+    ev = pv.default_spec(max_events=1, n_levels=3)
+    assert pv.arena_bytes(ok) > pv.arena_bytes(ev)
+    bad = pv.default_spec(max_events=1, unet_layout=1, bins_per_interval=50)   # 50 % 8 != 0
+    n = C.c_size_t(0)
+    assert pv.load_library().pvf_arena_bytes(C.byref(bad), C.byref(n)) == 2
 
 
 def test_arena_bytes_scales_with_events():
@@ -73,7 +87,9 @@ def test_arena_bytes_scales_with_events():
     ("max_tracks_total", -1, 1), ("compute_dtype", 9, 1),
     ("compute_dtype", -1, 1), ("n_levels", 1, 2), ("base_channels", 48, 2), ("n_bins", 4001, 2),
     ("bins_per_interval", 300, 2), ("bin_width_mm", 0.0, 1), ("half_window", -1, 1),
-    ("max_peaks_per_event", 5000, 2),
+    ("max_peaks_per_event", 5000, 2), ("base_channels", 16, 2), ("base_channels", 64, 0),
+    ("boundary_mm", -0.5, 1), ("boundary_mm", 5.01, 1), ("boundary_mm", 5.0, 0), ("boundary_mm", float("nan"), 1),
+    ("unet_layout", 2, 1), ("unet_layout", 1, 2), ("reserved", 3, 1),
 ])
 def test_spec_validation(field, value, status):
     s = pv.default_spec()
