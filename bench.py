@@ -49,10 +49,16 @@ def kernel_source_sha(kernel_name):
     return None
 
 
+def units(spec):
+    """UNet sequences per event: 1, or the interval count (interval layout)."""
+    return spec.n_bins // spec.bins_per_interval if spec.unet_layout == 1 else 1
+
+
 def layer_macs(spec, n_hidden=6, hidden=20, n_feat=9):
     """Algorithmic multiply-adds per event of each launch, in launch order
-    (the track stage's figure is per track)."""
-    n, c0, L0 = spec.n_levels, spec.base_channels, spec.n_bins
+    (the track stage's figure is per network evaluation of one track)."""
+    n, c0, U = spec.n_levels, spec.base_channels, units(spec)
+    L0 = spec.n_bins // U
     out = {"track": n_feat * hidden + (n_hidden - 1) * hidden * hidden + hidden * spec.bins_per_interval}
     for l in range(n):
         L, C = L0 >> l, c0 << l
@@ -66,7 +72,7 @@ def layer_macs(spec, n_hidden=6, hidden=20, n_feat=9):
         key = "dec0.c2+head" if l == 0 else f"dec{l}.c2"
         out[key] = L * C * C * 5 + (L * C if l == 0 else 0)
     out["peaks"] = 0
-    return out
+    return {k: (v * U if k != "track" else v) for k, v in out.items()}
 
 
 def layer_bytes(spec, eb):
@@ -74,7 +80,8 @@ def layer_bytes(spec, eb):
     read once, every output written once (eb bytes per element, the compute
     dtype; the histogram and the probability are FP32).  The track stage's
     figure is per track for its input (36 B) plus the histogram write."""
-    n, c0, L0 = spec.n_levels, spec.base_channels, spec.n_bins
+    n, c0, U = spec.n_levels, spec.base_channels, units(spec)
+    L0 = spec.n_bins // U
     out = {"track": None, "enc0.c1": L0 * 4 + L0 * c0 * eb}
     for l in range(n):
         L, C = L0 >> l, c0 << l
@@ -87,7 +94,7 @@ def layer_bytes(spec, eb):
         out[f"dec{l}.c1"] = L * 2 * C * eb + L * C * eb
         out["dec0.c2+head" if l == 0 else f"dec{l}.c2"] = L * C * eb + (L * 4 if l == 0 else L * C * eb)
     out["peaks"] = L0 * 4
-    return out
+    return {k: (v * U if v is not None else v) for k, v in out.items()}
 
 
 def cpu_threads():
@@ -174,12 +181,19 @@ def serve_bench(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--events", type=int, default=1000)
     ap.add_argument("--mix", default="poisson", choices=["poisson", "lognormal"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--dtype", default="fp32", choices=["fp32", "bf16", "fp16", "fp8_e4m3"])
+    ap.add_argument("--width", type=int, default=32, choices=[32, 64],
+                    help="UNet base channels (64 = the paper's deployed width)")
+    ap.add_argument("--levels", type=int, default=None, help="UNet levels (default 4; 3 with --layout interval)")
+    ap.add_argument("--layout", default="event", choices=["event", "interval"],
+                    help="one UNet sequence per event, or per 100-bin interval")
+    ap.add_argument("--boundary-mm", type=float, default=0.0,
+                    help="boundary tracks closer than this to a shared interval edge also feed the neighbour")
     ap.add_argument("--calib-events", type=int, default=256,
                     help="FP8: events (seed + 5) of the FP32 calibration run that sets the channel scales")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -223,11 +237,16 @@ def main():
         serve_bench(args)
         return
     E = args.events
+    from synth import NetShape
+    levels = args.levels or (3 if args.layout == "interval" else 4)
+    shape = NetShape(n_levels=levels, base_channels=args.width)
     batch = make_events(E, seed=args.seed, mix=args.mix)
-    w = make_weights(args.seed)
+    w = make_weights(args.seed, shape=shape)
     T = np.diff(batch.offsets)
+    variant = dict(n_levels=levels, base_channels=args.width, unet_layout=args.layout,
+                   boundary_mm=args.boundary_mm)
     spec = pv.default_spec(max_events=E, max_tracks_total=int(max(T.sum(), 1)), compute_dtype=args.dtype,
-                           max_tracks_per_event=max(1500, int(T.max())))
+                           max_tracks_per_event=max(1500, int(T.max())), **variant)
     amax = None
     if args.dtype == "fp8_e4m3":
         # set-up, before and outside the timed region: channel scales from an
@@ -235,7 +254,7 @@ def main():
         cb = make_events(args.calib_events, seed=args.seed + 5, mix=args.mix)
         CT = np.diff(cb.offsets)
         cspec = pv.default_spec(max_events=cb.n_events, max_tracks_total=int(max(CT.sum(), 1)),
-                                max_tracks_per_event=max(1500, int(CT.max())))
+                                max_tracks_per_event=max(1500, int(CT.max())), **variant)
         ceng = pv.Engine(weights_to_blob(w), cspec)
         cf, co = pv.upload_events(cb)
         amax = ceng.calibrate(cf, co)
@@ -351,11 +370,19 @@ def main():
         bound, achieved, peak_v, unit = "mfma", flops_per_launch / avg_dur_s / 1e12, peak, "TFLOP/s"
     else:
         bound, achieved, peak_v, unit = "hbm", bytes_per_launch / avg_dur_s / 1e9, HBM_PEAK_GBS, "GB/s"
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        tr = json.load(open(TRAFFIC_FILE)).get(f"{dom_name}|E={E}")
-        if tr and tr.get("source_sha256") == kernel_source_sha(dom_name):
-            traffic = tr.get("bytes_per_launch")
+    def measured_traffic(kernel):
+        """HBM bytes per launch from the committed counter passes, if they
+        were taken on this kernel's current source at this batch size."""
+        if not os.path.exists(TRAFFIC_FILE):
+            return None
+        tr = json.load(open(TRAFFIC_FILE)).get(f"{kernel}|E={E}")
+        if tr and tr.get("source_sha256") == kernel_source_sha(kernel):
+            return tr.get("bytes_per_launch")
+        return None
+
+    default_shape = (args.width == 32 and args.layout == "event" and levels == 4 and args.boundary_mm == 0
+                     and args.mix == "poisson" and args.seed == 0)
+    traffic = measured_traffic(dom_name) if default_shape else None
 
     stage = {"track": mean_ms[0], "unet": sum(mean_ms[1:-1]), "peaks": mean_ms[-1]}
     ms_per_step = wall / args.steps * 1e3
@@ -363,6 +390,11 @@ def main():
     p50 = statistics.median(us_ev)
     p99 = us_ev[min(len(us_ev) - 1, int(round(0.99 * (len(us_ev) - 1))))]
     unet_flops = sum(f for n, f in zip(names, flops_launch) if n not in ("track", "peaks"))
+    # track stage: network evaluations of every kept track (a boundary track
+    # counts once here), input bytes 36 per track plus the histogram rows
+    track_ms = mean_ms[0]
+    track_bytes = 36.0 * valid_tracks + E * spec.n_bins * 4
+    track_traffic = measured_traffic(kernels[0]) if default_shape else None
 
     result = {
         "metric": METRIC,
@@ -378,7 +410,11 @@ def main():
         "dtype": DTYPE_TAG[args.dtype],
         "data": "synthetic: seeded events (Poisson(5.6) PVs, Poisson(180) tracks) and seeded He-init weights",
         "config": {"workload": f"{E} events per batch, {args.mix} track counts (mean {T.mean():.1f}), "
-                               f"UNet 32/64/128/256 over 4000 bins, {args.dtype.upper()} convolutions (FP32 accumulate)"
+                               f"UNet {'/'.join(str(args.width << l) for l in range(levels))} over "
+                               + ("4000 bins" if args.layout == "event" else "each 100-bin interval")
+                               + (f", boundary tracks within {args.boundary_mm} mm feed two intervals"
+                                  if args.boundary_mm > 0 else "")
+                               + f", {args.dtype.upper()} convolutions (FP32 accumulate)"
                                + (f", FP8 scales from {args.calib_events} calibration events" if amax is not None else "")
                                + f", seed {args.seed}",
                    "events_per_batch": E, "tracks_total": int(T.sum()), "max_tracks": int(T.max()),
@@ -388,9 +424,15 @@ def main():
         "stages_ms": stage,
         "unet_tflops": unet_flops / (stage["unet"] / 1e3) / 1e12,
         "variants": dict((n, v) for n, v in zip(names, eng.variants()) if v >= 0),
+        "events_per_s_median_step": E / (statistics.median(step_ms) / 1e3),
+        "track_stage": {"ms": track_ms, "gflops": flops_launch[0] / track_ms / 1e6,
+                        "algorithmic_gbs": track_bytes / track_ms / 1e6,
+                        "measured_gbs": (track_traffic / track_ms / 1e6) if track_traffic else None},
         "roofline": {"bound": bound, "kernel": dom_name, "layers": dom["layers"],
                      "achieved": achieved, "peak": peak_v, "unit": unit, "frac": achieved / peak_v,
-                     "traffic": traffic, "flops_per_launch": flops_per_launch,
+                     "traffic": traffic,
+                     "hbm_frac": (traffic / avg_dur_s / (HBM_PEAK_GBS * 1e9)) if traffic else None,
+                     "flops_per_launch": flops_per_launch,
                      "algorithmic_bytes_per_launch": bytes_per_launch, "intensity_flop_per_byte": intensity,
                      "ridge_flop_per_byte": ridge, "avg_launch_ms": avg_dur_s * 1e3},
     }

@@ -18,7 +18,7 @@ int conv_variant_count(int dtype)
 bool conv_variant_ok(int dtype, int variant, int n, int cin, int taps, Epi epi)
 {
     if (dtype == PVF_FP32) return f32_variant_ok(variant, n, taps, epi);
-    if (dtype == PVF_FP8_E4M3) return fp8_variant_ok(variant, n, taps, epi);
+    if (dtype == PVF_FP8_E4M3) return fp8_variant_ok(variant, n, cin, taps, epi);
     return lp_variant_ok(variant, n, cin, taps, epi);
 }
 

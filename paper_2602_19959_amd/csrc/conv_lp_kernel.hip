@@ -54,6 +54,102 @@ __device__ __forceinline__ float lrelu(float x, float s) { return x >= 0.f ? x :
 
 template <int A, int B> struct Max { static constexpr int v = A > B ? A : B; };
 
+// Epilogue shared by the conv kernels (the LDS passed in is free: every
+// wave is past its last read of the stage buffers).  D layout of a 16x16
+// MFMA: lane holds rows 4*lg + v of column li.
+template <class T, int NT, int BM, int BN, int WM, int TMW, int TNW, int EPI>
+__device__ __forceinline__ void lp_epilogue(const f32x4 (&acc)[TMW][TNW], const ConvArgs& a, void* lds, int64_t m0,
+                                            int n0, int tid)
+{
+    constexpr int OP = BN + 8;                  // epilogue tile pitch (elements)
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int rw = (wave % WM) * TMW * 16;
+    const int cw = (wave / WM) * TNW * 16;
+
+    if constexpr (EPI == EPI_HEAD) {
+#pragma unroll
+        for (int i = 0; i < TMW; ++i) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                float s = 0.f;
+#pragma unroll
+                for (int j = 0; j < TNW; ++j) {
+                    const int col = n0 + cw + j * 16 + li;
+                    s += lrelu(acc[i][j][v] + a.bias[col], a.slope) * a.head_w[col];
+                }
+                s += __shfl_xor(s, 8);
+                s += __shfl_xor(s, 4);
+                s += __shfl_xor(s, 2);
+                s += __shfl_xor(s, 1);
+                const int64_t r = m0 + rw + i * 16 + 4 * lg + v;
+                if (li == 0 && r < a.m_rows) {
+                    const int64_t e = r / a.r_in;
+                    const int loc = (int)(r - e * a.r_in);
+                    if (loc >= kGuard && loc < a.r_in - kGuard)
+                        a.prob[e * a.l_out + (loc - kGuard)] = 1.f / (1.f + expf(-(s + a.head_b)));
+                }
+            }
+        }
+        return;
+    } else {
+        T* ot = reinterpret_cast<T*>(lds);   // [BM][OP]
+#pragma unroll
+        for (int j = 0; j < TNW; ++j) {
+            const int col = cw + j * 16 + li;
+            const int n = n0 + col;
+            const float b = n < a.n ? a.bias[EPI == EPI_CONVT ? n % a.cout : n] : 0.f;
+#pragma unroll
+            for (int i = 0; i < TMW; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    float y = acc[i][j][v] + b;
+                    if (EPI != EPI_CONVT) y = lrelu(y, a.slope);
+                    ot[(rw + i * 16 + 4 * lg + v) * OP + col] = (T)y;
+                }
+        }
+        __syncthreads();
+        T* out = static_cast<T*>(a.out);
+        constexpr int CH = BN / 8;                  // 16-byte chunks per tile row
+        const int n_valid = a.n - n0 < BN ? a.n - n0 : BN;
+        for (int idx = tid; idx < BM * CH; idx += NT) {
+            const int row = idx / CH, q = idx % CH;
+            const int64_t r = m0 + row;
+            if (8 * q >= n_valid || r >= a.m_rows) continue;
+            const int64_t e = r / a.r_in;
+            const int loc = (int)(r - e * a.r_in);
+            if (loc < kGuard || loc >= a.r_in - kGuard) continue;
+            const uint4 v = *reinterpret_cast<const uint4*>(ot + row * OP + 8 * q);
+            if constexpr (EPI == EPI_CONVT) {
+                const int n = n0 + 8 * q;
+                const int tj = n / a.cout, o = n - tj * a.cout;
+                const int64_t ro = e * a.r_out + kGuard + 2 * (loc - kGuard) + tj;
+                *reinterpret_cast<uint4*>(out + ro * a.ld_out + o) = v;
+            } else {
+                *reinterpret_cast<uint4*>(out + r * a.ld_out + n0 + 8 * q) = v;
+            }
+        }
+        if constexpr (EPI == EPI_POOL) {
+            T* pout = static_cast<T*>(a.pool_out);
+            for (int idx = tid; idx < (BM / 2) * CH; idx += NT) {
+                const int pr = idx / CH, q = idx % CH;
+                const int64_t r = m0 + 2 * pr;       // even: first row of a pooling pair
+                if (8 * q >= n_valid || r >= a.m_rows) continue;
+                const int64_t e = r / a.r_in;
+                const int loc = (int)(r - e * a.r_in);
+                if (loc < kGuard || loc >= a.r_in - kGuard) continue;
+                const T* x0 = ot + (2 * pr) * OP + 8 * q;
+                const T* x1 = x0 + OP;
+                T y[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) y[u] = (float)x0[u] >= (float)x1[u] ? x0[u] : x1[u];
+                const int64_t rp = e * a.r_pool + kGuard + (loc - kGuard) / 2;
+                *reinterpret_cast<uint4*>(pout + rp * a.ld_pool + n0 + 8 * q) = *reinterpret_cast<const uint4*>(y);
+            }
+        }
+    }
+}
+
 // KC: input channels per LDS stage (32 or 64); within a stage the k order is
 // (32-channel chunk, tap, MFMA), the same as with KC = 32, so KC does not
 // change a bit of the result.  PF = 1: the next stage is fetched into
@@ -200,91 +296,118 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_lp(ConvArgs a)
         }
     }
 
-    // D layout of a 16x16 MFMA: lane holds rows 4*lg + v of column li.
-    const int rw = wm * TMW * 16;
-    const int cw = wn * TNW * 16;
+    __syncthreads();   // the epilogue reuses the stage buffers
+    lp_epilogue<T, NT, BM, BN, WM, TMW, TNW, EPI>(acc, a, smem, m0, n0, tid);
+}
 
-    if constexpr (EPI == EPI_HEAD) {
+
+// PF = 2 form, double-buffered: stage k + 1 streams from global memory
+// straight into the second LDS buffer (global_load_lds_dwordx4: no registers,
+// no LDS store instructions) while stage k is on the matrix cores, so a
+// block's loads and its MFMAs overlap.  Each wave-wide load fills 1 KB of LDS
+// = 16 rows x 64 B; lane L fills slot L of that block (row L / 4, position
+// L % 4), so it fetches the chunk that the swizzle puts there.  Rows beyond
+// the batch (first and last tile) and columns beyond n (last N tile) are
+// clamped to valid addresses: they only feed outputs the epilogue discards.
+// Same k order as every other variant (32-channel stage, tap, MFMA).
+template <class T, int WM, int WN, int TMW, int TNW, int TAPS, int EPI>
+__global__ __launch_bounds__(WM * WN * 64) void conv_mfma_lp_db(ConvArgs a)
+{
+    using V = typename Lp<T>::vec8;
+    constexpr int NW = WM * WN;
+    constexpr int NT = NW * 64;
+    constexpr int BM = WM * TMW * 16;
+    constexpr int BN = WN * TNW * 16;
+    constexpr int KC = 32, NCH = 4;
+    constexpr int ROWB = KC * (int)sizeof(T);        // 64 bytes per LDS row
+    constexpr int RAD = (TAPS - 1) / 2;
+    constexpr int XR = (BM + TAPS - 1 + 15) / 16 * 16;
+    constexpr int WRW = BN * TAPS;
+    static_assert(WRW % 16 == 0, "weight rows fill whole 1 KB loads");
+    constexpr int XI = XR / 16, WI = WRW / 16;      // wave-wide loads per stage
+    constexpr int STAGE = (XR + WRW) * ROWB;         // bytes
+    constexpr int OP = BN + 8;
+    constexpr int SMEM = Max<2 * STAGE, (EPI == EPI_HEAD ? 0 : BM * OP * (int)sizeof(T))>::v;
+    __shared__ __attribute__((aligned(16))) char smem[SMEM];
+
+    const T* in = static_cast<const T*>(a.in);
+    const T* wt = static_cast<const T*>(a.w);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: scalar load loop
+    const int wm = wave % WM;
+    const int wn = wave / WM;
+    const int li = lane & 15;
+    const int lg = lane >> 4;
+    const int n_tiles = (a.n + BN - 1) / BN;
+    const int m_tiles = (int)((a.m_rows + BM - 1) / BM);
+    const int xcd = (int)(blockIdx.x % kXcds), slot = (int)(blockIdx.x / kXcds);
+    const int m_tile = (slot / n_tiles) * kXcds + xcd;
+    if (m_tile >= m_tiles) return;
+    const int64_t m0 = (int64_t)m_tile * BM;
+    const int n0 = (slot % n_tiles) * BN;
+    const int kw = TAPS * a.cin;
+
+    f32x4 acc[TMW][TNW];
 #pragma unroll
-        for (int i = 0; i < TMW; ++i) {
+    for (int i = 0; i < TMW; ++i)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                float s = 0.f;
-#pragma unroll
-                for (int j = 0; j < TNW; ++j) {
-                    const int col = n0 + cw + j * 16 + li;
-                    s += lrelu(acc[i][j][v] + a.bias[col], a.slope) * a.head_w[col];
-                }
-                s += __shfl_xor(s, 8);
-                s += __shfl_xor(s, 4);
-                s += __shfl_xor(s, 2);
-                s += __shfl_xor(s, 1);
-                const int64_t r = m0 + rw + i * 16 + 4 * lg + v;
-                if (li == 0 && r < a.m_rows) {
-                    const int64_t e = r / a.r_in;
-                    const int loc = (int)(r - e * a.r_in);
-                    if (loc >= kGuard && loc < a.r_in - kGuard)
-                        a.prob[e * a.l_out + (loc - kGuard)] = 1.f / (1.f + expf(-(s + a.head_b)));
-                }
+        for (int j = 0; j < TNW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const int lrow = lane >> 2, lpos = lane & 3;
+    auto issue = [&](int buf, int c0) {
+        char* base = smem + buf * STAGE;
+        for (int j = wave; j < XI + WI; j += NW) {
+            const bool xj = j < XI;
+            const int row = 16 * (xj ? j : j - XI) + lrow;      // row inside its region
+            const int c = lpos ^ swz<NCH>(row);                 // chunk held by this slot
+            const T* g;
+            if (xj) {
+                int64_t gr = m0 - RAD + row;
+                gr = gr < 0 ? 0 : (gr >= a.m_rows ? a.m_rows - 1 : gr);
+                g = in + gr * a.ld_in + c0 + 8 * c;
+            } else {
+                const int nn = row / TAPS, tap = row - nn * TAPS;
+                const int n = n0 + nn < a.n ? n0 + nn : a.n - 1;
+                g = wt + (int64_t)n * kw + tap * a.cin + c0 + 8 * c;
             }
+            char* dst = base + (xj ? 16 * j * ROWB : XR * ROWB + 16 * (j - XI) * ROWB);
+            __builtin_amdgcn_global_load_lds((const void*)g, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
         }
-        return;
-    } else {
-        T* ot = smem;   // [BM][OP], reuses the stage buffers after the last barrier
+    };
+
+    const int nk = a.cin / KC;
+    issue(0, 0);
+    for (int k = 0; k < nk; ++k) {
+        // this wave's loads of stage k have landed; the barrier makes every
+        // wave's visible and frees the other buffer (its last reads were stage k - 1)
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (k + 1 < nk) issue((k + 1) & 1, (k + 1) * KC);
+        const T* xs = reinterpret_cast<const T*>(smem + (k & 1) * STAGE);
+        const T* ws = xs + XR * KC;
+        // fragments of tap t + 1 are read while tap t is on the matrix cores
+        V av[2][TMW], bv[2][TNW];
+        auto frag = [&](int tap, int f) {
 #pragma unroll
-        for (int j = 0; j < TNW; ++j) {
-            const int col = cw + j * 16 + li;
-            const int n = n0 + col;
-            const float b = n < a.n ? a.bias[EPI == EPI_CONVT ? n % a.cout : n] : 0.f;
+            for (int i = 0; i < TMW; ++i)
+                av[f][i] = *reinterpret_cast<const V*>(xs + lds_at<NCH>(wm * TMW * 16 + i * 16 + li + tap, lg));
+#pragma unroll
+            for (int j = 0; j < TNW; ++j)
+                bv[f][j] = *reinterpret_cast<const V*>(ws + lds_at<NCH>((wn * TNW * 16 + j * 16 + li) * TAPS + tap, lg));
+        };
+        frag(0, 0);
+#pragma unroll
+        for (int tap = 0; tap < TAPS; ++tap) {
+            if (tap + 1 < TAPS) frag(tap + 1, (tap + 1) & 1);
 #pragma unroll
             for (int i = 0; i < TMW; ++i)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    float y = acc[i][j][v] + b;
-                    if (EPI != EPI_CONVT) y = lrelu(y, a.slope);
-                    ot[(rw + i * 16 + 4 * lg + v) * OP + col] = (T)y;
-                }
-        }
-        __syncthreads();
-        T* out = static_cast<T*>(a.out);
-        constexpr int CH = BN / 8;                  // 16-byte chunks per tile row
-        const int n_valid = a.n - n0 < BN ? a.n - n0 : BN;
-        for (int idx = tid; idx < BM * CH; idx += NT) {
-            const int row = idx / CH, q = idx % CH;
-            const int64_t r = m0 + row;
-            if (8 * q >= n_valid || r >= a.m_rows) continue;
-            const int64_t e = r / a.r_in;
-            const int loc = (int)(r - e * a.r_in);
-            if (loc < kGuard || loc >= a.r_in - kGuard) continue;
-            const uint4 v = *reinterpret_cast<const uint4*>(ot + row * OP + 8 * q);
-            if constexpr (EPI == EPI_CONVT) {
-                const int n = n0 + 8 * q;
-                const int tj = n / a.cout, o = n - tj * a.cout;
-                const int64_t ro = e * a.r_out + kGuard + 2 * (loc - kGuard) + tj;
-                *reinterpret_cast<uint4*>(out + ro * a.ld_out + o) = v;
-            } else {
-                *reinterpret_cast<uint4*>(out + r * a.ld_out + n0 + 8 * q) = v;
-            }
-        }
-        if constexpr (EPI == EPI_POOL) {
-            T* pout = static_cast<T*>(a.pool_out);
-            for (int idx = tid; idx < (BM / 2) * CH; idx += NT) {
-                const int pr = idx / CH, q = idx % CH;
-                const int64_t r = m0 + 2 * pr;       // even: first row of a pooling pair
-                if (8 * q >= n_valid || r >= a.m_rows) continue;
-                const int64_t e = r / a.r_in;
-                const int loc = (int)(r - e * a.r_in);
-                if (loc < kGuard || loc >= a.r_in - kGuard) continue;
-                const T* x0 = ot + (2 * pr) * OP + 8 * q;
-                const T* x1 = x0 + OP;
-                T y[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) y[u] = (float)x0[u] >= (float)x1[u] ? x0[u] : x1[u];
-                const int64_t rp = e * a.r_pool + kGuard + (loc - kGuard) / 2;
-                *reinterpret_cast<uint4*>(pout + rp * a.ld_pool + n0 + 8 * q) = *reinterpret_cast<const uint4*>(y);
-            }
+                for (int j = 0; j < TNW; ++j) acc[i][j] = Lp<T>::mfma(av[tap & 1][i], bv[tap & 1][j], acc[i][j]);
         }
     }
+    __syncthreads();   // the epilogue reuses the stage buffers
+    lp_epilogue<T, NT, BM, BN, WM, TMW, TNW, EPI>(acc, a, smem, m0, n0, tid);
 }
 
 template <class T, int WM, int WN, int TMW, int TNW, int KC, int PF, int TAPS, int EPI>
@@ -295,7 +418,10 @@ hipError_t run(const ConvArgs& a, hipStream_t s)
     const unsigned m_tiles = (unsigned)((a.m_rows + BM - 1) / BM);
     const unsigned n_tiles = (unsigned)((a.n + BN - 1) / BN);
     dim3 grid((m_tiles + kXcds - 1) / kXcds * kXcds * n_tiles);
-    hipLaunchKernelGGL((conv_mfma_lp<T, WM, WN, TMW, TNW, KC, PF, TAPS, EPI>), grid, dim3(WM * WN * 64), 0, s, a);
+    if constexpr (PF == 2)
+        hipLaunchKernelGGL((conv_mfma_lp_db<T, WM, WN, TMW, TNW, TAPS, EPI>), grid, dim3(WM * WN * 64), 0, s, a);
+    else
+        hipLaunchKernelGGL((conv_mfma_lp<T, WM, WN, TMW, TNW, KC, PF, TAPS, EPI>), grid, dim3(WM * WN * 64), 0, s, a);
     return hipGetLastError();
 }
 
@@ -314,6 +440,13 @@ constexpr Variant kVariants[] = {
     {4, 1, 4, 4, 64, 1},   //  9: 256 x 64, 64-channel stages, prefetch
     {2, 2, 4, 4, 32, 1},   // 10: 128 x 128, prefetch
     {4, 1, 4, 2, 32, 1},   // 11: 256 x 32, prefetch
+    {4, 2, 4, 4, 32, 2},   // 12: 256 x 128, double-buffered direct-to-LDS stages
+    {4, 1, 4, 4, 32, 2},   // 13: 256 x 64, double-buffered
+    {4, 1, 4, 2, 32, 2},   // 14: 256 x 32, double-buffered
+    {2, 2, 4, 4, 32, 2},   // 15: 128 x 128, double-buffered
+    {2, 1, 4, 2, 32, 2},   // 16: 128 x 32, double-buffered (128 threads)
+    {2, 2, 8, 4, 32, 2},   // 17: 256 x 128, double-buffered, 128 x 64 per wave
+    {2, 1, 8, 4, 32, 2},   // 18: 256 x 64, double-buffered, 128 x 64 per wave (128 threads)
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -332,6 +465,9 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_LP_CASE(4)
             PVF_LP_CASE(5)
             PVF_LP_CASE(11)
+            PVF_LP_CASE(13)
+            PVF_LP_CASE(14)
+            PVF_LP_CASE(16)
         default: return hipErrorInvalidValue;
         }
     } else {
@@ -348,6 +484,13 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_LP_CASE(9)
             PVF_LP_CASE(10)
             PVF_LP_CASE(11)
+            PVF_LP_CASE(12)
+            PVF_LP_CASE(13)
+            PVF_LP_CASE(14)
+            PVF_LP_CASE(15)
+            PVF_LP_CASE(16)
+            PVF_LP_CASE(17)
+            PVF_LP_CASE(18)
         default: return hipErrorInvalidValue;
         }
     }
@@ -379,7 +522,8 @@ bool lp_variant_ok(int v, int n, int cin, int taps, Epi epi)
     const Variant& x = kVariants[v];
     const int bn = x.wn * x.tnw * 16;
     if (cin % x.kc != 0) return false;
-    if (epi == EPI_HEAD) return (v == 0 || v == 1 || v == 4 || v == 5 || v == 11) && bn == n && x.wn == 1;
+    if (epi == EPI_HEAD)
+        return (v == 0 || v == 1 || v == 4 || v == 5 || v == 11 || v == 13 || v == 14 || v == 16) && bn == n && x.wn == 1;
     return bn <= (n < 32 ? 32 : n);
 }
 
@@ -396,6 +540,10 @@ int lp_default_variant(int n, int cin, int taps, Epi epi)
 std::string lp_kernel_name(int dtype, int v, int taps, Epi epi)
 {
     const Variant& x = kVariants[v];
+    if (x.pf == 2)
+        return std::string("conv_mfma_lp_db<") + (dtype == PVF_BF16 ? "__bf16" : "_Float16") + ", " +
+               std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " + std::to_string(x.tmw) + ", " +
+               std::to_string(x.tnw) + ", " + std::to_string(taps) + ", " + std::to_string((int)epi) + ">";
     return std::string("conv_mfma_lp<") + (dtype == PVF_BF16 ? "__bf16" : "_Float16") + ", " +
            std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " + std::to_string(x.tmw) + ", " +
            std::to_string(x.tnw) + ", " + std::to_string(x.kc) + ", " + std::to_string(x.pf) + ", " +

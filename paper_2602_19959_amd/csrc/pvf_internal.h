@@ -195,7 +195,7 @@ std::string lp_kernel_name(int dtype, int variant, int taps, Epi epi);
 
 hipError_t launch_conv_fp8(const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s);
 int fp8_variant_count();
-bool fp8_variant_ok(int variant, int n, int taps, Epi epi);
+bool fp8_variant_ok(int variant, int n, int cin, int taps, Epi epi);
 int fp8_default_variant(int n, int taps, Epi epi);
 std::string fp8_kernel_name(int variant, int taps, Epi epi);
 
