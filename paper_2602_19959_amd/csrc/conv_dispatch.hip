@@ -25,14 +25,14 @@ bool conv_variant_ok(int dtype, int variant, int n, int cin, int taps, Epi epi)
 int conv_default_variant(int dtype, int n, int cin, int taps, Epi epi)
 {
     if (dtype == PVF_FP32) return f32_default_variant(n, taps, epi);
-    if (dtype == PVF_FP8_E4M3) return fp8_default_variant(n, taps, epi);
+    if (dtype == PVF_FP8_E4M3) return fp8_default_variant(n, cin, taps, epi);
     return lp_default_variant(n, cin, taps, epi);
 }
 
-std::string conv_kernel_name(int dtype, int variant, int taps, Epi epi)
+std::string conv_kernel_name(int dtype, int variant, int cin, int taps, Epi epi)
 {
     if (dtype == PVF_FP32) return f32_kernel_name(variant, taps, epi);
-    if (dtype == PVF_FP8_E4M3) return fp8_kernel_name(variant, taps, epi);
+    if (dtype == PVF_FP8_E4M3) return fp8_kernel_name(variant, cin, taps, epi);
     return lp_kernel_name(dtype, variant, taps, epi);
 }
 

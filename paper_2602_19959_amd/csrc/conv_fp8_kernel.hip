@@ -144,8 +144,11 @@ __device__ __forceinline__ void fp8_epilogue(const f32x4 (&acc)[TMW][TNW], const
                 const int64_t e = r / a.r_in;
                 const int loc = (int)(r - e * a.r_in);
                 if (loc < kGuard || loc >= a.r_in - kGuard) continue;
-                const uint8_t* x0 = ot + (2 * pr) * OP + 16 * q;
-                const uint8_t* x1 = x0 + OP;
+                // two whole 16-byte rows from LDS, compared in registers
+                const uint4 r0 = *reinterpret_cast<const uint4*>(ot + (2 * pr) * OP + 16 * q);
+                const uint4 r1 = *reinterpret_cast<const uint4*>(ot + (2 * pr + 1) * OP + 16 * q);
+                const uint8_t* x0 = reinterpret_cast<const uint8_t*>(&r0);
+                const uint8_t* x1 = reinterpret_cast<const uint8_t*>(&r1);
                 uint8_t y[16];
 #pragma unroll
                 for (int u = 0; u < 16; ++u) y[u] = e4m3_to_f32(x0[u]) >= e4m3_to_f32(x1[u]) ? x0[u] : x1[u];
@@ -427,19 +430,21 @@ bool fp8_variant_ok(int v, int n, int cin, int taps, Epi epi)
     return bn <= (n < 32 ? 32 : n);
 }
 
-// picks of variant sweeps over 1000 events (ties within noise go to the
-// smaller tile)
-int fp8_default_variant(int n, int taps, Epi epi)
+// Picks of variant sweeps over 1000 events: the double-buffered 64-channel
+// stages wherever the layer has them (cin a multiple of 64) and enough
+// output channels; the single-buffered tiles for 32-channel inputs.
+int fp8_default_variant(int n, int cin, int taps, Epi epi)
 {
     if (epi == EPI_HEAD) return n == 64 ? 1 : 0;
-    if (n <= 32) return 0;
-    if (epi == EPI_CONVT && taps == 1) return n >= 128 ? 3 : 0;
-    if (epi == EPI_POOL) return 1;
-    return n <= 64 ? 1 : 3;
+    if (epi == EPI_CONVT && taps == 1) return n >= 128 ? 4 : 6;
+    if (cin % 64 != 0 || n <= 32) return 0;
+    if (epi == EPI_POOL && n <= 64) return 0;
+    return 5;
 }
 
-std::string fp8_kernel_name(int v, int taps, Epi epi)
+std::string fp8_kernel_name(int v, int cin, int taps, Epi epi)
 {
+    (void)cin;
     const Variant& x = kVariants[v];
     return std::string(x.db ? "conv_mfma_fp8_db<" : "conv_mfma_fp8<") + std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " + std::to_string(x.tmw) +
            ", " + std::to_string(x.tnw) + ", " + std::to_string(taps) + ", " + std::to_string((int)epi) + ">";

@@ -138,8 +138,10 @@ __device__ __forceinline__ void lp_epilogue(const f32x4 (&acc)[TMW][TNW], const 
                 const int64_t e = r / a.r_in;
                 const int loc = (int)(r - e * a.r_in);
                 if (loc < kGuard || loc >= a.r_in - kGuard) continue;
-                const T* x0 = ot + (2 * pr) * OP + 8 * q;
-                const T* x1 = x0 + OP;
+                const uint4 r0 = *reinterpret_cast<const uint4*>(ot + (2 * pr) * OP + 8 * q);
+                const uint4 r1 = *reinterpret_cast<const uint4*>(ot + (2 * pr + 1) * OP + 8 * q);
+                const T* x0 = reinterpret_cast<const T*>(&r0);
+                const T* x1 = reinterpret_cast<const T*>(&r1);
                 T y[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) y[u] = (float)x0[u] >= (float)x1[u] ? x0[u] : x1[u];
@@ -527,13 +529,16 @@ bool lp_variant_ok(int v, int n, int cin, int taps, Epi epi)
     return bn <= (n < 32 ? 32 : n);
 }
 
-// Defaults from a BF16 sweep on MI355X at 1000 events.
+// Defaults from BF16 sweeps on MI355X at 1000 events: the double-buffered
+// stages win where a layer has few channels (short K, little reuse), the
+// 256 x 128 single-buffered tile with two blocks per CU on the wide layers.
 int lp_default_variant(int n, int cin, int taps, Epi epi)
 {
     if (epi == EPI_HEAD) return n == 64 ? 1 : 0;
     if (epi == EPI_CONVT && taps == 1) return n >= 128 ? 6 : 4;
-    if (n <= 32) return 11;
-    if (n <= 64) return cin <= 32 ? 4 : 11;
+    (void)cin;
+    if (n <= 32) return 14;
+    if (n <= 64) return 13;
     return 3;
 }
 

@@ -436,7 +436,7 @@ void build_names(pvf_engine* e)
         c.in_src = std::move(src);
         c.variant = conv_default_variant(e->spec.compute_dtype, gemm_n, cin, taps, epi);
         e->names.push_back(name);
-        e->kernels.push_back(conv_kernel_name(e->spec.compute_dtype, c.variant, taps, epi));
+        e->kernels.push_back(conv_kernel_name(e->spec.compute_dtype, c.variant, cin, taps, epi));
         e->conv.push_back(c);
         e->out_channels.push_back(epi == EPI_HEAD ? 0 : cout);
     };
@@ -922,7 +922,7 @@ pvf_status pvf_set_launch_variant(pvf_engine* eng, int i, int v)
     auto& c = eng->conv[i];
     if (!conv_variant_ok(eng->spec.compute_dtype, v, c.n, c.cin, c.taps, c.epi)) return PVF_ERR_INVALID_ARGUMENT;
     c.variant = v;
-    eng->kernels[i] = conv_kernel_name(eng->spec.compute_dtype, v, c.taps, c.epi);
+    eng->kernels[i] = conv_kernel_name(eng->spec.compute_dtype, v, c.cin, c.taps, c.epi);
     return PVF_OK;
 }
 

@@ -179,7 +179,7 @@ hipError_t launch_conv(int dtype, const ConvArgs& a, int taps, Epi epi, int vari
 int conv_variant_count(int dtype);
 bool conv_variant_ok(int dtype, int variant, int n, int cin, int taps, Epi epi);
 int conv_default_variant(int dtype, int n, int cin, int taps, Epi epi);
-std::string conv_kernel_name(int dtype, int variant, int taps, Epi epi);
+std::string conv_kernel_name(int dtype, int variant, int cin, int taps, Epi epi);
 
 // per-precision implementations behind the functions above
 hipError_t launch_conv_f32(const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s);
@@ -196,8 +196,8 @@ std::string lp_kernel_name(int dtype, int variant, int taps, Epi epi);
 hipError_t launch_conv_fp8(const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s);
 int fp8_variant_count();
 bool fp8_variant_ok(int variant, int n, int cin, int taps, Epi epi);
-int fp8_default_variant(int n, int taps, Epi epi);
-std::string fp8_kernel_name(int variant, int taps, Epi epi);
+int fp8_default_variant(int n, int cin, int taps, Epi epi);
+std::string fp8_kernel_name(int variant, int cin, int taps, Epi epi);
 
 inline int act_bytes(int dtype) { return dtype == PVF_FP32 ? 4 : (dtype == PVF_FP8_E4M3 ? 1 : 2); }
 
