@@ -52,6 +52,12 @@ def fp8_calibration(n_events=64, seed=5, shape=None):
     return amax
 
 
+def engine_for(max_events, dtype, **spec):
+    """Engine of any compute dtype; FP8 gets the standard calibration table."""
+    amax = fp8_calibration() if dtype == "fp8_e4m3" else None
+    return make_engine(max_events, fp8_amax=amax, compute_dtype=dtype, **spec)
+
+
 def run(engine, batch, with_prob=True):
     """Upload `batch`, execute, wait, return host numpy outputs."""
     import paper_2602_19959_amd as pv

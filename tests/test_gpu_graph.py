@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from synth import make_events
-from tests.gpu_util import torch_cuda, make_engine, run
+from tests.gpu_util import torch_cuda, engine_for, run
 
 pytestmark = pytest.mark.gpu
 
@@ -15,11 +15,11 @@ def say(*a):
     print("[gpu-graph]", *a, flush=True)
 
 
-@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+@pytest.mark.parametrize("dtype", ["fp32", "bf16", "fp8_e4m3"])
 def test_track_schedules_identical(dtype):
     torch_cuda()
     batch = make_events(300, seed=4, mix="lognormal")
-    eng = make_engine(300, compute_dtype=dtype, max_tracks_per_event=1000)
+    eng = engine_for(300, dtype, max_tracks_per_event=1000)
     eng.set_track_schedule(True)
     q = run(eng, batch)
     eng.set_track_schedule(False)
@@ -32,7 +32,7 @@ def test_track_schedules_identical(dtype):
     eng.close()
 
 
-@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+@pytest.mark.parametrize("dtype", ["fp32", "bf16", "fp8_e4m3"])
 def test_graph_replays_match_eager(dtype):
     """Replay the captured graph several times, with other eager work and
     synchronisations in between, and compare every replay with the eager run."""
@@ -40,7 +40,7 @@ def test_graph_replays_match_eager(dtype):
     import paper_2602_19959_amd as pv
     A = make_events(64, seed=7, mix="lognormal")
     B = make_events(64, seed=8)
-    eng = make_engine(64, compute_dtype=dtype)
+    eng = engine_for(64, dtype)
     ref = run(eng, A)
     featA, offA = pv.upload_events(A)
     out = eng.alloc_outputs(64)

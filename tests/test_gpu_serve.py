@@ -1,13 +1,13 @@
 """Continuous-batching serving: requests admitted into a fixed HBM pool,
 packed event by event into steps on two lanes whose work overlaps, must give
-every event the same bits as the slice run alone (FP32 and BF16 kernels are
-batch-invariant)."""
+every event the same bits as the slice run alone (the FP32, BF16 and FP8
+kernels are batch-invariant)."""
 
 import numpy as np
 import pytest
 
 from synth import make_events
-from tests.gpu_util import torch_cuda, blob, make_engine, run
+from tests.gpu_util import torch_cuda, blob, engine_for, run, fp8_calibration
 
 pytestmark = pytest.mark.gpu
 
@@ -16,20 +16,21 @@ def say(*a):
     print("[gpu-serve]", *a, flush=True)
 
 
-@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+@pytest.mark.parametrize("dtype", ["fp32", "bf16", "fp8_e4m3"])
 @pytest.mark.parametrize("realtime", [False, True])
 def test_results_same_alone_and_in_the_mix(dtype, realtime):
     torch_cuda()
     from paper_2602_19959_amd.serve import Server, poisson_requests
     pool = make_events(400, seed=21, mix="lognormal")
     reqs = poisson_requests(rate_hz=2000.0, n=12, seed=3, pool=pool, min_events=5, max_events=90)
-    srv = Server(blob(), pool_bytes=3 << 30, lanes=2, lane_events=64, compute_dtype=dtype)
+    amax = fp8_calibration() if dtype == "fp8_e4m3" else None
+    srv = Server(blob(), pool_bytes=3 << 30, lanes=2, lane_events=64, compute_dtype=dtype, fp8_amax=amax)
     stats = srv.run(reqs, realtime=realtime)
     summ = stats.summary()
     say(dtype, "realtime" if realtime else "all-at-once", summ)
     assert summ["requests"] == 12 and stats.steps >= 3
     assert max(r.n_events for r in reqs) > 64           # some request spans several steps
-    eng = make_engine(100, compute_dtype=dtype)
+    eng = engine_for(100, dtype)
     for r in reqs:
         alone = run(eng, r.batch, with_prob=False)
         for k in ("n_vertices", "status"):
