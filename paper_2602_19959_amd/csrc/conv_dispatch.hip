@@ -24,7 +24,7 @@ bool conv_variant_ok(int dtype, int variant, int n, int cin, int taps, Epi epi)
 
 int conv_default_variant(int dtype, int n, int cin, int taps, Epi epi)
 {
-    if (dtype == PVF_FP32) return f32_default_variant(n, taps, epi);
+    if (dtype == PVF_FP32) return f32_default_variant(n, cin, taps, epi);
     if (dtype == PVF_FP8_E4M3) return fp8_default_variant(n, cin, taps, epi);
     return lp_default_variant(n, cin, taps, epi);
 }

@@ -44,6 +44,15 @@ __device__ __forceinline__ float e4m3_to_f32(uint8_t b)
 
 template <int A, int B> struct Max { static constexpr int v = A > B ? A : B; };
 
+// Occupancy target handed to the register allocator: as many waves per SIMD
+// as the block's LDS allows on one CU (160 KB), at most 4 (128 registers).
+constexpr int occupancy_target(int lds_bytes, int waves_per_block)
+{
+    const int blocks = lds_bytes > 0 ? 163840 / lds_bytes : 8;
+    const int w = blocks * waves_per_block / 4;
+    return w < 1 ? 1 : (w > 4 ? 4 : w);
+}
+
 // Epilogue shared by the FP8 kernels (the LDS passed in is free).  D layout
 // of a 16x16 MFMA: lane holds rows 4*lg + v of column li.
 template <int NT, int BM, int BN, int WM, int TMW, int TNW, int EPI>
@@ -160,7 +169,10 @@ __device__ __forceinline__ void fp8_epilogue(const f32x4 (&acc)[TMW][TNW], const
 }
 
 template <int WM, int WN, int TMW, int TNW, int TAPS, int EPI>
-__global__ __launch_bounds__(WM * WN * 64) void conv_mfma_fp8(ConvArgs a)
+__global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(occupancy_target(
+    Max<(WM * TMW * 16 + TAPS - 1) * 32 + WN * TNW * 16 * TAPS * 32,
+        (EPI == EPI_HEAD ? 0 : WM * TMW * 16 * (WN * TNW * 16 + 16))>::v, WM * WN))))
+void conv_mfma_fp8(ConvArgs a)
 {
     constexpr int NT = WM * WN * 64;
     constexpr int BM = WM * TMW * 16;
@@ -436,10 +448,10 @@ bool fp8_variant_ok(int v, int n, int cin, int taps, Epi epi)
 int fp8_default_variant(int n, int cin, int taps, Epi epi)
 {
     if (epi == EPI_HEAD) return n == 64 ? 1 : 0;
-    if (epi == EPI_CONVT && taps == 1) return n >= 128 ? 4 : 6;
-    if (cin % 64 != 0 || n <= 32) return 0;
-    if (epi == EPI_POOL && n <= 64) return 0;
-    return 5;
+    if (epi == EPI_CONVT && taps == 1) return n >= 256 ? 2 : (n >= 128 ? 4 : 6);
+    if (n <= 32) return 0;
+    if (cin >= 128) return 5;
+    return 1;
 }
 
 std::string fp8_kernel_name(int v, int cin, int taps, Epi epi)

@@ -43,6 +43,16 @@ __device__ __forceinline__ int lds_at(int r, int q) { return (r * 4 + (q ^ swz(r
 
 __device__ __forceinline__ float lrelu(float x, float s) { return x >= 0.f ? x : s * x; }
 
+// Occupancy target handed to the register allocator: as many waves per SIMD
+// as the block's LDS allows on one CU (160 KB), at most 4 (128 registers);
+// none for the register-prefetch variants, which need the registers.
+constexpr int occupancy_target(int lds_bytes, int waves_per_block)
+{
+    const int blocks = lds_bytes > 0 ? 163840 / lds_bytes : 8;
+    const int w = blocks * waves_per_block / 4;
+    return w < 1 ? 1 : (w > 4 ? 4 : w);
+}
+
 // Epilogue shared by the FP32 kernels, straight from the accumulators.
 // Output D layout of the 16x16 MFMA: lane holds rows 4*lg + v (v = 0..3) of
 // column li.
@@ -143,8 +153,20 @@ __device__ __forceinline__ void f32_epilogue(const f32x4 (&acc)[TMW][TNW], const
     }
 }
 
+// (register estimate: 4 per accumulator tile and per fragment, about 56
+// others, 40 more for the 4 x 4-tile waves; the target never asks for fewer)
+template <int TMW, int TNW> struct F32Regs {
+    static constexpr int v = 4 * TMW * TNW + 4 * (TMW + TNW) + 56 + (TMW * TNW >= 16 ? 40 : 0);
+};
+template <int WM, int WN, int TMW, int TNW, int PF, int TAPS>
+struct F32Occ {
+    static constexpr int lds = occupancy_target(4 * KC * (WM * TMW * 16 + TAPS - 1 + WN * TNW * 16 * TAPS), WM * WN);
+    static constexpr int regs = 512 / F32Regs<TMW, TNW>::v;
+    static constexpr int v = PF ? 1 : (lds < regs ? lds : regs);
+};
 template <int WM, int WN, int TMW, int TNW, int PF, int TAPS, int EPI>
-__global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32(ConvArgs a)
+__global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(F32Occ<WM, WN, TMW, TNW, PF, TAPS>::v)))
+void conv_mfma_f32(ConvArgs a)
 {
     constexpr int NT = WM * WN * 64;
     constexpr int BM = WM * TMW * 16;
@@ -462,10 +484,12 @@ bool f32_variant_ok(int v, int n, int taps, Epi epi)
 // Defaults from a sweep on MI355X at 1000 events: the 256 x 32 tile with the
 // fewest registers (most blocks per CU) wins every 5-tap layer; the
 // transposed convs prefer wider N tiles.
-int f32_default_variant(int n, int taps, Epi epi)
+int f32_default_variant(int n, int cin, int taps, Epi epi)
 {
-    if (epi == EPI_CONVT && taps == 1) return n >= 128 ? 9 : (n >= 64 ? 5 : 0);
+    if (epi == EPI_CONVT && taps == 1) return n >= 64 ? 5 : 0;
     if (epi == EPI_HEAD) return n == 64 ? 3 : 0;
+    if (epi == EPI_STORE && cin >= 128 && n >= 128) return 3;
+    if (n == 64 && cin <= 32) return 5;
     return 0;
 }
 

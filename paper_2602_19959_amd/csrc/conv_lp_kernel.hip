@@ -54,6 +54,23 @@ __device__ __forceinline__ float lrelu(float x, float s) { return x >= 0.f ? x :
 
 template <int A, int B> struct Max { static constexpr int v = A > B ? A : B; };
 
+// Occupancy target handed to the register allocator: as many waves per SIMD
+// as the block's LDS allows on one CU (160 KB), at most 4 (128 registers);
+// none for the register-prefetch variants, which need the registers.
+// Without it the allocator takes up to 512 registers for 4-wave blocks and
+// caps a CU at two of them, where LDS would allow four or five.
+constexpr int occupancy_target(int lds_bytes, int waves_per_block)
+{
+    const int blocks = lds_bytes > 0 ? 163840 / lds_bytes : 8;
+    const int w = blocks * waves_per_block / 4;
+    return w < 1 ? 1 : (w > 4 ? 4 : w);
+}
+template <int T_BYTES, int BM, int BN, int KC, int TAPS, int EPI, int STAGES, int XPAD>
+struct LpLds {
+    static constexpr int stage = (BM + XPAD) * KC * T_BYTES + BN * TAPS * KC * T_BYTES;
+    static constexpr int v = Max<STAGES * stage, (EPI == EPI_HEAD ? 0 : BM * (BN + 8) * T_BYTES)>::v;
+};
+
 // Epilogue shared by the conv kernels (the LDS passed in is free: every
 // wave is past its last read of the stage buffers).  D layout of a 16x16
 // MFMA: lane holds rows 4*lg + v of column li.
@@ -157,7 +174,9 @@ __device__ __forceinline__ void lp_epilogue(const f32x4 (&acc)[TMW][TNW], const 
 // change a bit of the result.  PF = 1: the next stage is fetched into
 // registers while the current one computes.
 template <class T, int WM, int WN, int TMW, int TNW, int KC, int PF, int TAPS, int EPI>
-__global__ __launch_bounds__(WM * WN * 64) void conv_mfma_lp(ConvArgs a)
+__global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(PF ? 1 : occupancy_target(
+    LpLds<(int)sizeof(T), WM * TMW * 16, WN * TNW * 16, KC, TAPS, EPI, 1, TAPS - 1>::v, WM * WN))))
+void conv_mfma_lp(ConvArgs a)
 {
     using V = typename Lp<T>::vec8;
     constexpr int NT = WM * WN * 64;
@@ -313,7 +332,9 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_lp(ConvArgs a)
 // clamped to valid addresses: they only feed outputs the epilogue discards.
 // Same k order as every other variant (32-channel stage, tap, MFMA).
 template <class T, int WM, int WN, int TMW, int TNW, int TAPS, int EPI>
-__global__ __launch_bounds__(WM * WN * 64) void conv_mfma_lp_db(ConvArgs a)
+__global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(occupancy_target(
+    LpLds<(int)sizeof(T), WM * TMW * 16, WN * TNW * 16, 32, TAPS, EPI, 2, 16>::v, WM * WN))))
+void conv_mfma_lp_db(ConvArgs a)
 {
     using V = typename Lp<T>::vec8;
     constexpr int NW = WM * WN;
@@ -537,7 +558,7 @@ int lp_default_variant(int n, int cin, int taps, Epi epi)
     if (epi == EPI_HEAD) return n == 64 ? 1 : 0;
     if (epi == EPI_CONVT && taps == 1) return n >= 128 ? 6 : 4;
     (void)cin;
-    if (n <= 32) return 14;
+    if (n <= 32) return epi == EPI_POOL ? 0 : 14;
     if (n <= 64) return 13;
     return 3;
 }

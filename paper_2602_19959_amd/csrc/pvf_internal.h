@@ -185,7 +185,7 @@ std::string conv_kernel_name(int dtype, int variant, int cin, int taps, Epi epi)
 hipError_t launch_conv_f32(const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s);
 int f32_variant_count();
 bool f32_variant_ok(int variant, int n, int taps, Epi epi);
-int f32_default_variant(int n, int taps, Epi epi);
+int f32_default_variant(int n, int cin, int taps, Epi epi);
 std::string f32_kernel_name(int variant, int taps, Epi epi);
 hipError_t launch_conv_lp(int dtype, const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s);
 int lp_variant_count();
