@@ -73,6 +73,7 @@ void make_plan(const pvf_spec* s, size_t weight_floats, Plan* p)
     p->weights = take(p->weights_bytes);
     // 16-bit copy of the conv weights, same element offsets as the FP32 layout
     p->weights_lp = s->compute_dtype == PVF_FP32 ? 0 : take(weight_floats * 2);
+    p->mlp_lp = s->compute_dtype == PVF_FP32 ? 0 : take(mlp_lp_elems(kMaxHiddenLayers) * 2);
     p->zero_begin = off;
     p->x0 = take(E * p->lv[0].R * sizeof(float));
     const int n = s->n_levels;
@@ -389,6 +390,8 @@ struct pvf_engine {
     std::vector<size_t> outinv_off, a_off;   // FP8: 1/a and a of launch i's stored tensor
     std::vector<size_t> calib_off;       // offset of launch i's channels in the calibration table
     size_t calib_total = 0;
+    size_t calib_mlp_off = 0;            // the track network's layer inputs, after the UNet tensors
+    size_t mlp_in_inv_off = 0, mlp_col_off = 0;   // FP8: network scales in the scales region
     float* calib_table = nullptr;        // set only during pvf_calibrate
     std::vector<ConvLaunch> conv;        // per launch; variant -1 = not a conv launch
     std::vector<hipEvent_t> events;      // launch boundaries when profiling
@@ -467,9 +470,44 @@ void build_names(pvf_engine* e)
         e->calib_off[i] = e->calib_total;
         e->calib_total += e->out_channels[i];
     }
+    e->calib_mlp_off = e->calib_total;
+    e->calib_total += mlp_calib_channels(e->n_hidden);
 }
 
 bool misaligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) != 0; }
+
+// The track network's layers inside the packed FP32 weights (blob order):
+// W [N][K] row-major, then b [N].
+struct MlpLayer { size_t w, b; int k, n; };
+std::vector<MlpLayer> mlp_layers(const pvf_engine* e)
+{
+    std::vector<MlpLayer> v;
+    size_t off = e->wl.mlp;
+    int k = kFeat;
+    for (int l = 0; l <= e->n_hidden; ++l) {
+        const int n = l < e->n_hidden ? kHidden : e->spec.bins_per_interval;
+        v.push_back({off, off + (size_t)n * k, k, n});
+        off += (size_t)n * k + n;
+        k = n;
+    }
+    return v;
+}
+
+// Matrix-core copy of the network, [layer][cols][32] zero-padded, through
+// `put(layer, n, k, w)` -> element.
+template <class T, class Put>
+void pack_mlp(const pvf_engine* e, const std::vector<float>& f32, std::vector<T>& out, Put put)
+{
+    out.assign(mlp_lp_elems(e->n_hidden), T{});
+    size_t base = 0;
+    const auto layers = mlp_layers(e);
+    for (int l = 0; l <= e->n_hidden; ++l) {
+        const MlpLayer& L = layers[l];
+        for (int n = 0; n < L.n; ++n)
+            for (int k = 0; k < L.k; ++k) out[base + (size_t)n * kMlpK + k] = put(l, n, k, f32[L.w + (size_t)n * L.k + k]);
+        base += (size_t)mlp_layer_cols(l, e->n_hidden) * kMlpK;
+    }
+}
 
 // FP8 engine set-up from a calibration table (per-channel absolute maxima of
 // every stored tensor, layout of pvf_calibrate):
@@ -478,7 +516,7 @@ bool misaligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p
 //   Wq    = e4m3(W' / s_n);
 // the kernels then compute acc * s_n (+ bias) and store y / a of their output.
 pvf_status setup_fp8(pvf_engine* e, const std::vector<float>& f32, const float* amax, size_t n_amax,
-                     std::vector<uint8_t>& wq, std::vector<float>& sc)
+                     std::vector<uint8_t>& wq, std::vector<float>& sc, std::vector<uint8_t>& mlp_fp8)
 {
     if (!amax || n_amax != e->calib_total) return PVF_ERR_INVALID_ARGUMENT;
     const size_t nl = e->names.size();
@@ -520,6 +558,32 @@ pvf_status setup_fp8(pvf_engine* e, const std::vector<float>& f32, const float* 
                     wq[c.w->w + (size_t)n * per_n + t * c.cin + ch] = to_e4m3_host(row[t * c.cin + ch] * ain[ch] / sn);
         }
     }
+    // the track network: per layer input-channel scales from the calibration,
+    // folded into the weights, and one scale per column
+    const auto layers = mlp_layers(e);
+    std::vector<std::vector<float>> am(layers.size());
+    size_t coff = e->calib_mlp_off;
+    for (size_t l = 0; l < layers.size(); ++l)
+        for (int k = 0; k < layers[l].k; ++k) {
+            const float m = amax[coff++];
+            if (!std::isfinite(m) || m < 0.f) return PVF_ERR_INVALID_ARGUMENT;
+            am[l].push_back(m > 0.f ? m / 448.f : 1.f);
+        }
+    e->mlp_in_inv_off = sc.size();
+    for (size_t l = 0; l < layers.size(); ++l)
+        for (int k = 0; k < kMlpK; ++k) sc.push_back(k < layers[l].k ? 1.f / am[l][k] : 1.f);
+    e->mlp_col_off = sc.size();
+    std::vector<std::vector<float>> col(layers.size());
+    for (size_t l = 0; l < layers.size(); ++l) {
+        const MlpLayer& L = layers[l];
+        for (int n = 0; n < mlp_layer_cols((int)l, e->n_hidden); ++n) {
+            float m = 0.f;
+            for (int k = 0; n < L.n && k < L.k; ++k) m = std::max(m, std::fabs(f32[L.w + (size_t)n * L.k + k] * am[l][k]));
+            col[l].push_back(m > 0.f ? m / 448.f : 1.f);
+            sc.push_back(col[l].back());
+        }
+    }
+    pack_mlp<uint8_t>(e, f32, mlp_fp8, [&](int l, int n, int k, float w) { return to_e4m3_host(w * am[l][k] / col[l][n]); });
     if (sc.size() > kMaxScaleFloats) return PVF_ERR_SHAPE;
     return PVF_OK;
 }
@@ -590,6 +654,13 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
     ta.r0 = P.lv[0].R;
     ta.unit_bins = P.lv[0].L;
     ta.boundary_mm = eng->spec.boundary_mm;
+    ta.mlp_dtype = dt;
+    ta.mlp_lp = dt == PVF_FP32 ? nullptr : eng->arena + P.mlp_lp;
+    if (dt == PVF_FP8_E4M3) {
+        ta.mlp_in_inv = at<float>(eng, P.scales) + eng->mlp_in_inv_off;
+        ta.mlp_col = at<float>(eng, P.scales) + eng->mlp_col_off;
+    }
+    ta.mlp_calib = eng->calib_table ? eng->calib_table + eng->calib_mlp_off : nullptr;
     ta.flags = flags;
     ta.order = at<int32_t>(eng, P.order);
     ta.queue_counter = at<int32_t>(eng, P.queue);
@@ -781,10 +852,11 @@ static pvf_status init_impl(const pvf_spec* spec, const void* blob, size_t blob_
     std::vector<float> packed;
     pack_weights(b, e->wl, packed);
     std::vector<uint16_t> packed_lp;
-    std::vector<uint8_t> packed_fp8;
+    std::vector<uint8_t> packed_fp8, mlp_fp8;
+    std::vector<uint16_t> mlp_lp;
     std::vector<float> fp8_scales;
     if (fp8) {
-        st = setup_fp8(e, packed, amax, n_amax, packed_fp8, fp8_scales);
+        st = setup_fp8(e, packed, amax, n_amax, packed_fp8, fp8_scales, mlp_fp8);
         if (st != PVF_OK) {
             delete e;
             return st;
@@ -798,10 +870,19 @@ static pvf_status init_impl(const pvf_spec* spec, const void* blob, size_t blob_
         if (err == hipSuccess)
             err = hipMemcpyAsync(e->arena + plan.scales, fp8_scales.data(), fp8_scales.size() * sizeof(float),
                                  hipMemcpyHostToDevice, e->stream);
+        if (err == hipSuccess)
+            err = hipMemcpyAsync(e->arena + plan.mlp_lp, mlp_fp8.data(), mlp_fp8.size(), hipMemcpyHostToDevice,
+                                 e->stream);
     } else if (err == hipSuccess && spec->compute_dtype != PVF_FP32) {
         pack_weights_lp(e->wl, b.shape, packed, spec->compute_dtype, packed_lp);
+        const int dt = spec->compute_dtype;
+        pack_mlp<uint16_t>(e, packed, mlp_lp,
+                           [dt](int, int, int, float w) { return dt == PVF_BF16 ? to_bf16(w) : to_f16(w); });
         err = hipMemcpyAsync(e->arena + plan.weights_lp, packed_lp.data(), packed_lp.size() * sizeof(uint16_t),
                              hipMemcpyHostToDevice, e->stream);
+        if (err == hipSuccess)
+            err = hipMemcpyAsync(e->arena + plan.mlp_lp, mlp_lp.data(), mlp_lp.size() * sizeof(uint16_t),
+                                 hipMemcpyHostToDevice, e->stream);
     }
     if (err == hipSuccess)
         err = hipMemsetAsync(e->arena + plan.zero_begin, 0, plan.zero_end - plan.zero_begin, e->stream);

@@ -42,6 +42,7 @@ struct Plan {
     Level lv[kMaxLevels];
     size_t weights = 0, weights_bytes = 0;
     size_t weights_lp = 0;         // 16-bit conv weights (BF16/FP16 engines)
+    size_t mlp_lp = 0;             // track network packed for the matrix cores (BF16/FP16/FP8 engines)
     // E below is the number of UNet sequences (events x units)
     size_t x0 = 0;                 // [E][R0][1]      scaled histogram (always FP32)
     size_t a[kMaxLevels] = {};     // [E][Rl][Cl]     conv1 outputs (enc, then dec)
@@ -118,7 +119,24 @@ struct TrackArgs {
     int32_t* flags;          // [E]
     int32_t* order;          // [E] queue order (persistent form), or null
     int32_t* queue_counter;  // ticket counter (persistent form), or null
+    // network arithmetic: FP32 on the vector ALUs, or BF16/FP16/FP8 on the
+    // matrix cores with FP32 accumulation
+    int mlp_dtype;
+    const void* mlp_lp;      // packed weights: per layer [NP][32] (NP = 32, or 112 for the output layer)
+    const float* mlp_in_inv; // FP8: per layer [32], 1 / scale of each input channel
+    const float* mlp_col;    // FP8: per layer [NP], column scales
+    float* mlp_calib;        // calibration only: |max| of every layer's input channels
 };
+
+// Low-precision network layout: every layer as a K = 32 GEMM (inputs zero-
+// padded from 9 or 20), hidden layers 32 columns wide (20 used), the output
+// layer 112 (100 used).
+constexpr int kMlpK = 32;
+constexpr int kMlpHiddenN = 32;
+constexpr int kMlpOutN = 112;
+inline int mlp_layer_cols(int layer, int n_hidden) { return layer < n_hidden ? kMlpHiddenN : kMlpOutN; }
+inline size_t mlp_lp_elems(int n_hidden) { return ((size_t)n_hidden * kMlpHiddenN + kMlpOutN) * kMlpK; }
+inline int mlp_calib_channels(int n_hidden) { return kFeat + n_hidden * kHidden; }
 
 struct FirstConvArgs {
     const float* x0;         // [E][R0]

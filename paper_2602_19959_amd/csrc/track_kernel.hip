@@ -46,17 +46,39 @@ __device__ __forceinline__ double edge(const TrackArgs& a, int i)
     return __dadd_rn(a.z_min, __dmul_rn(a.interval_mm, (double)i));
 }
 
-// Hidden layers of one track with its features taken in the frame of
-// interval itv (z offset mapped to [-1, 1) inside that interval).
-__device__ __forceinline__ void hidden_layers(const TrackArgs& a, const float* f, double zd, int itv, float* h)
+// Network inputs of one track in the frame of interval itv: the z offset
+// mapped to [-1, 1) inside that interval, the other features standardised.
+__device__ __forceinline__ void features(const TrackArgs& a, const float* f, double zd, int itv, float* g)
+{
+    g[0] = (float)((zd - edge(a, itv)) / (a.interval_mm * 0.5) - 1.0);
+#pragma unroll
+    for (int k = 1; k < kFeat; ++k) g[k] = (f[k] - a.shift[k]) * a.scale[k];
+}
+
+// Calibration: the largest |v| over the wave, per channel, merged into the
+// table (float bits compare like unsigned integers for v >= 0).
+__device__ __forceinline__ void wave_amax(float* dst, float v)
+{
+    v = fabsf(v);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned int*>(dst), __float_as_uint(v));
+}
+
+// Calibration table offset of the inputs of network layer l.
+__device__ __forceinline__ int calib_off(int l) { return l == 0 ? 0 : kFeat + (l - 1) * kHidden; }
+
+// FP32 hidden layers on the vector ALUs, for every lane (lanes without a
+// track carry zeros and their results are never used), so that the
+// calibration reductions see a whole wave.
+__device__ __forceinline__ void hidden_layers_f32(const TrackArgs& a, const float* g, bool valid, float* h)
 {
     const float* W1 = a.mlp;                               // [kHidden][kFeat]
     const float* b1 = W1 + kHidden * kFeat;
     const float* Wh = b1 + kHidden;                        // hidden layers 2.. : [W 20x20, b 20]
-    float g[kFeat];
-    g[0] = (float)((zd - edge(a, itv)) / (a.interval_mm * 0.5) - 1.0);
+    if (a.mlp_calib)
 #pragma unroll
-    for (int k = 1; k < kFeat; ++k) g[k] = (f[k] - a.shift[k]) * a.scale[k];
+        for (int k = 0; k < kFeat; ++k) wave_amax(a.mlp_calib + calib_off(0) + k, valid ? g[k] : 0.f);
 #pragma unroll
     for (int j = 0; j < kHidden; ++j) {
         float s = b1[j];
@@ -65,6 +87,8 @@ __device__ __forceinline__ void hidden_layers(const TrackArgs& a, const float* f
         h[j] = lrelu(s, a.slope);
     }
     for (int l = 1; l < a.n_hidden; ++l) {
+        if (a.mlp_calib)
+            for (int j = 0; j < kHidden; ++j) wave_amax(a.mlp_calib + calib_off(l) + j, valid ? h[j] : 0.f);
         const float* W = Wh + (size_t)(l - 1) * (kHidden * kHidden + kHidden);
         const float* bb = W + kHidden * kHidden;
         float hn[kHidden];
@@ -78,13 +102,166 @@ __device__ __forceinline__ void hidden_layers(const TrackArgs& a, const float* f
 #pragma unroll
         for (int j = 0; j < kHidden; ++j) h[j] = hn[j];
     }
+    if (a.mlp_calib)
+        for (int j = 0; j < kHidden; ++j) wave_amax(a.mlp_calib + calib_off(a.n_hidden) + j, valid ? h[j] : 0.f);
 }
 
+// ---------------------------------------------------------------- matrix-core network
+//
+// BF16/FP16/FP8 engines run the network as GEMMs on the matrix cores: each
+// wave takes its 64 items (4 tiles of 16 rows); every layer is a K = 32 GEMM
+// (inputs zero-padded), the hidden layers 2 column tiles wide and the output
+// layer 7, accumulated in FP32; bias, LeakyReLU / softplus in FP32; the
+// hidden activations go back to LDS in the compute type for the next layer.
+// FP8 (OCP e4m3) uses per-channel scales as the convolutions do: each layer
+// input holds v / a_c, the weights carry a_c and a column scale s_n.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint8_t to_e4m3(float x)
+{
+    x = fminf(fmaxf(x, -448.f), 448.f);
+    return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.f, 0, false) & 0xff);
+}
+
+template <class E> struct Net;
+template <> struct Net<__bf16> {
+    using V = bf16x8;
+    static constexpr int KP = 40;              // LDS row pitch (elements)
+    __device__ static f32x4 mfma(V x, V w, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, w, c, 0, 0, 0); }
+    __device__ static __bf16 cvt(float v, float) { return (__bf16)v; }
+};
+template <> struct Net<_Float16> {
+    using V = f16x8;
+    static constexpr int KP = 40;
+    __device__ static f32x4 mfma(V x, V w, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(x, w, c, 0, 0, 0); }
+    __device__ static _Float16 cvt(float v, float) { return (_Float16)v; }
+};
+template <> struct Net<uint8_t> {
+    using V = long;
+    static constexpr int KP = 48;
+    __device__ static f32x4 mfma(V x, V w, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(x, w, c, 0, 0, 0); }
+    __device__ static uint8_t cvt(float v, float inv) { return to_e4m3(v * inv); }
+};
+
+// Layer l's bias (FP32, from the blob layout) and packed weights.
+__device__ __forceinline__ const float* layer_bias(const TrackArgs& a, int l)
+{
+    const float* b1 = a.mlp + kHidden * kFeat;
+    if (l == 0) return b1;
+    const float* Wh = b1 + kHidden;
+    if (l < a.n_hidden) return Wh + (size_t)(l - 1) * (kHidden * kHidden + kHidden) + kHidden * kHidden;
+    const float* Wo = Wh + (size_t)(a.n_hidden - 1) * (kHidden * kHidden + kHidden);
+    return Wo + (size_t)a.n_out * kHidden;
+}
+
+// Row i of the wave's input tile: the features of item i, quantised.
+template <class E>
+__device__ __forceinline__ void store_inputs(const TrackArgs& a, E* xa, int row, const float* g)
+{
+    E* r = xa + row * Net<E>::KP;
+#pragma unroll
+    for (int k = 0; k < kMlpK; ++k) {
+        const float inv = (sizeof(E) == 1 && k < kFeat) ? a.mlp_in_inv[k] : 1.f;
+        r[k] = Net<E>::cvt(k < kFeat ? g[k] : 0.f, inv);
+    }
+}
+
+// Hidden layers of the wave's 64 rows, in place in xa.
+template <class E>
+__device__ void hidden_layers_mma(const TrackArgs& a, E* xa, int wave, int lane)
+{
+    using V = typename Net<E>::V;
+    constexpr int KP = Net<E>::KP;
+    const int li = lane & 15, lg = lane >> 4;
+    const E* wp = static_cast<const E*>(a.mlp_lp);
+    E* rows = xa + (size_t)wave * 64 * KP;
+    for (int l = 0; l < a.n_hidden; ++l) {
+        const E* W = wp + (size_t)l * kMlpHiddenN * kMlpK;
+        const float* b = layer_bias(a, l);
+        V x[4], w[2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] = *reinterpret_cast<const V*>(rows + (16 * i + li) * KP + 8 * lg);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) w[j] = *reinterpret_cast<const V*>(W + (16 * j + li) * kMlpK + 8 * lg);
+        f32x4 acc[4][2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = Net<E>::mfma(x[i], w[j], f32x4{0.f, 0.f, 0.f, 0.f});
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int n = 16 * j + li;                        // output channel of this lane
+            const bool used = n < kHidden;
+            const float cs = (sizeof(E) == 1 && used) ? a.mlp_col[l * kMlpHiddenN + n] : 1.f;
+            const float bn = used ? b[n] : 0.f;
+            const float inv = (sizeof(E) == 1 && used) ? a.mlp_in_inv[(l + 1) * kMlpK + n] : 1.f;
+            float m = 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float y = used ? lrelu(acc[i][j][v] * cs + bn, a.slope) : 0.f;
+                    m = fmaxf(m, fabsf(y));
+                    rows[(16 * i + 4 * lg + v) * KP + n] = Net<E>::cvt(y, inv);
+                }
+            if (a.mlp_calib) {
+                m = fmaxf(m, __shfl_xor(m, 16));
+                m = fmaxf(m, __shfl_xor(m, 32));
+                if (lg == 0 && used)
+                    atomicMax(reinterpret_cast<unsigned int*>(a.mlp_calib + calib_off(l + 1) + n), __float_as_uint(m));
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Output layer of the 64 rows that wave `owner` computed: every wave takes
+// every fourth 16-column tile; softplus outputs into ob [64][n_out + 1].
+template <class E>
+__device__ void outputs_mma(const TrackArgs& a, const E* xa, int owner, int wave, int lane, float* ob)
+{
+    using V = typename Net<E>::V;
+    constexpr int KP = Net<E>::KP;
+    const int li = lane & 15, lg = lane >> 4;
+    const int op = a.n_out + 1;
+    const E* W = static_cast<const E*>(a.mlp_lp) + (size_t)a.n_hidden * kMlpHiddenN * kMlpK;
+    const float* b = layer_bias(a, a.n_hidden);
+    const E* rows = xa + (size_t)owner * 64 * KP;
+    V x[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[i] = *reinterpret_cast<const V*>(rows + (16 * i + li) * KP + 8 * lg);
+    for (int jt = wave; jt < kMlpOutN / 16; jt += NT / 64) {
+        const int n = 16 * jt + li;
+        const V w = *reinterpret_cast<const V*>(W + (size_t)n * kMlpK + 8 * lg);
+        const bool used = n < a.n_out;
+        const float cs = (sizeof(E) == 1 && used) ? a.mlp_col[a.n_hidden * kMlpHiddenN + n] : 1.f;
+        const float bn = used ? b[n] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const f32x4 acc = Net<E>::mfma(x[i], w, f32x4{0.f, 0.f, 0.f, 0.f});
+            if (used)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) ob[(16 * i + 4 * lg + v) * op + n] = softplus(acc[v] * cs + bn);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- one event
+
+// E = float: the FP32 network on the vector ALUs; otherwise the matrix-core
+// network in E.  Everything else (binning, staging, ordered accumulation) is
+// shared.
+template <class E>
 __device__ void track_event(const TrackArgs& a, int e, float* smem)
 {
+    constexpr bool kF32 = sizeof(E) == 4;
     const int n_bins = a.n_out * a.n_intervals;
     float* H = smem;                                  // [n_bins]
-    float* hb = H + n_bins;                           // [NT][HP]
+    float* hb = H + n_bins;                           // FP32: [NT][HP] hidden activations
+    E* xa = reinterpret_cast<E*>(hb);                 // matrix cores: [NT][KP] layer inputs
     float* ob = hb + NT * HP;                         // [SUB][n_out + 1]
     int* iv = reinterpret_cast<int*>(ob + SUB * (a.n_out + 1));   // [NT] interval of each item
     int* nbv = iv + NT;                               // [NT] neighbour interval of each track, or -1
@@ -114,22 +291,49 @@ __device__ void track_event(const TrackArgs& a, int e, float* smem)
     const double z_max = edge(a, a.n_intervals);
     const bool two = a.boundary_mm > 0.0;
 
-    // B + C over the first n items of hb / iv: outputs, then the ordered
-    // accumulation (thread j owns column j, items in list order)
+    // A for one item per thread: the hidden layers (FP32 in registers, then
+    // to hb; or the matrix-core layers in xa)
+    auto network_hidden = [&](const float* g, bool valid) {
+        if constexpr (kF32) {
+            float h[kHidden];
+            hidden_layers_f32(a, g, valid, h);
+#pragma unroll
+            for (int j = 0; j < kHidden; ++j) hb[tid * HP + j] = valid ? h[j] : 0.f;
+        } else {
+            float z[kFeat];
+#pragma unroll
+            for (int k = 0; k < kFeat; ++k) z[k] = valid ? g[k] : 0.f;
+            if (a.mlp_calib)
+#pragma unroll
+                for (int k = 0; k < kFeat; ++k) wave_amax(a.mlp_calib + calib_off(0) + k, z[k]);
+            store_inputs<E>(a, xa, tid, z);
+            __builtin_amdgcn_wave_barrier();
+            hidden_layers_mma<E>(a, xa, wave, lane);
+        }
+    };
+
+    // B + C over the first n items: outputs, then the ordered accumulation
+    // (thread j owns column j, items in list order)
     auto outputs_and_accumulate = [&](int n) {
         for (int sub = 0; sub < n; sub += SUB) {
-            // ---- B: wave q computes outputs q, q+4, ... for 64 items
-            const int tt = sub + lane;
-            if (tt < n && iv[tt] >= 0) {
-                float hl[kHidden];
+            // ---- B: the sub-chunk's outputs into ob
+            if constexpr (kF32) {
+                // wave q computes outputs q, q+4, ... for the 64 items
+                const int tt = sub + lane;
+                if (tt < n && iv[tt] >= 0) {
+                    float hl[kHidden];
 #pragma unroll
-                for (int k = 0; k < kHidden; ++k) hl[k] = hb[tt * HP + k];
-                for (int j = wave; j < a.n_out; j += NT / 64) {
-                    float s = bo[j];
+                    for (int k = 0; k < kHidden; ++k) hl[k] = hb[tt * HP + k];
+                    for (int j = wave; j < a.n_out; j += NT / 64) {
+                        float s = bo[j];
 #pragma unroll
-                    for (int k = 0; k < kHidden; ++k) s = fmaf(Wo[j * kHidden + k], hl[k], s);
-                    ob[lane * op + j] = softplus(s);
+                        for (int k = 0; k < kHidden; ++k) s = fmaf(Wo[j * kHidden + k], hl[k], s);
+                        ob[lane * op + j] = softplus(s);
+                    }
                 }
+            } else {
+                // all waves share the output layer of these 64 rows
+                outputs_mma<E>(a, xa, sub / SUB, wave, lane, ob);
             }
             __syncthreads();
             // ---- C: ordered accumulation
@@ -150,10 +354,10 @@ __device__ void track_event(const TrackArgs& a, int e, float* smem)
             const int64_t t = base + tid;
             int itv = -1, nb = -1;
             float f[kFeat];
+            float g[kFeat];
             double zd = 0.0;
-            float h[kHidden];
 #pragma unroll
-            for (int j = 0; j < kHidden; ++j) h[j] = 0.f;
+            for (int k = 0; k < kFeat; ++k) g[k] = 0.f;
             if (t < end) {
                 bool finite = true;
 #pragma unroll
@@ -172,7 +376,7 @@ __device__ void track_event(const TrackArgs& a, int e, float* smem)
                 if (itv < 0) {
                     dropped_any = 1;   // benign race: every writer stores 1
                 } else {
-                    hidden_layers(a, f, zd, itv, h);
+                    features(a, f, zd, itv, g);
                     // boundary track: closer than boundary_mm to an edge shared
                     // with another interval (distances in double, exact edges)
                     if (two) {
@@ -181,8 +385,7 @@ __device__ void track_event(const TrackArgs& a, int e, float* smem)
                     }
                 }
             }
-#pragma unroll
-            for (int j = 0; j < kHidden; ++j) hb[tid * HP + j] = h[j];
+            network_hidden(g, itv >= 0);
             iv[tid] = itv;
             nbv[tid] = nb;
             __syncthreads();
@@ -207,19 +410,19 @@ __device__ void track_event(const TrackArgs& a, int e, float* smem)
                 if (n_st > 0) {
                     // ---- A again for the staged items, in the neighbour's frame
                     int inb = -1;
+                    float gs[kFeat];
 #pragma unroll
-                    for (int j = 0; j < kHidden; ++j) h[j] = 0.f;
+                    for (int k = 0; k < kFeat; ++k) gs[k] = 0.f;
                     if (tid < n_st) {
                         const int src = st[tid];
                         inb = nbv[src];
-                        float g[kFeat];
+                        float fs[kFeat];
 #pragma unroll
-                        for (int k = 0; k < kFeat; ++k) g[k] = a.feat[k][base + src];
-                        hidden_layers(a, g, (double)g[0], inb, h);
+                        for (int k = 0; k < kFeat; ++k) fs[k] = a.feat[k][base + src];
+                        features(a, fs, (double)fs[0], inb, gs);
                     }
                     __syncthreads();    // every read of nbv / st above is done
-#pragma unroll
-                    for (int j = 0; j < kHidden; ++j) hb[tid * HP + j] = h[j];
+                    network_hidden(gs, tid < n_st);
                     iv[tid] = inb;
                     __syncthreads();
                     outputs_and_accumulate(n_st);
@@ -241,16 +444,18 @@ __device__ void track_event(const TrackArgs& a, int e, float* smem)
 }
 
 // One block per event.
+template <class E>
 __global__ __launch_bounds__(NT) void track_stage(TrackArgs a)
 {
     extern __shared__ float smem[];
-    track_event(a, blockIdx.x, smem);
+    track_event<E>(a, blockIdx.x, smem);
 }
 
 // Persistent form for uneven track counts: a fixed grid of blocks takes
 // tickets from a device counter; ticket k is the k-th event in descending
 // track count (largest first, so the long events do not end the launch
 // alone).  Every event's result is the same whichever block computes it.
+template <class E>
 __global__ __launch_bounds__(NT) void track_stage_queue(TrackArgs a, int n_events)
 {
     extern __shared__ float smem[];
@@ -261,7 +466,7 @@ __global__ __launch_bounds__(NT) void track_stage_queue(TrackArgs a, int n_event
         const int k = ticket;
         __syncthreads();
         if (k >= n_events) break;
-        track_event(a, a.order[k], smem);
+        track_event<E>(a, a.order[k], smem);
     }
 }
 
@@ -314,33 +519,51 @@ __global__ __launch_bounds__(kOrderThreads) void track_order(TrackArgs a, int n_
 
 }  // namespace
 
+static_assert(NT * HP * sizeof(float) >= NT * Net<__bf16>::KP * 2 && NT * HP * sizeof(float) >= NT * Net<uint8_t>::KP,
+              "the layer-input tile fits the FP32 hidden-activation space");
 static size_t track_stage_lds_bytes(int n_out, int n_intervals)
 {
     return sizeof(float) * ((size_t)n_out * n_intervals + NT * HP + SUB * (n_out + 1)) + sizeof(int) * 2 * NT;
 }
 
-hipError_t launch_track(const TrackArgs& a, int n_events, int persistent_blocks, int* order_scratch,
-                        hipStream_t s)
+template <class E>
+hipError_t launch_track_typed(const TrackArgs& a, int n_events, int persistent_blocks, int* order_scratch,
+                              hipStream_t s)
 {
     const size_t lds = track_stage_lds_bytes(a.n_out, a.n_intervals);
     if (lds > 64 * 1024) {
-        hipError_t err = hipFuncSetAttribute((const void*)track_stage,
+        hipError_t err = hipFuncSetAttribute((const void*)track_stage<E>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (err == hipSuccess)
-            err = hipFuncSetAttribute((const void*)track_stage_queue, hipFuncAttributeMaxDynamicSharedMemorySize,
+            err = hipFuncSetAttribute((const void*)track_stage_queue<E>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)lds);
         if (err != hipSuccess) return err;
     }
     if (persistent_blocks <= 0 || !a.order || !a.queue_counter) {
-        hipLaunchKernelGGL(track_stage, dim3(n_events), dim3(NT), lds, s, a);
+        hipLaunchKernelGGL(track_stage<E>, dim3(n_events), dim3(NT), lds, s, a);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(track_order, dim3(1), dim3(kOrderThreads), 0, s, a, n_events, order_scratch);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     const int blocks = persistent_blocks < n_events ? persistent_blocks : n_events;
-    hipLaunchKernelGGL(track_stage_queue, dim3(blocks), dim3(NT), lds, s, a, n_events);
+    hipLaunchKernelGGL(track_stage_queue<E>, dim3(blocks), dim3(NT), lds, s, a, n_events);
     return hipGetLastError();
+}
+
+hipError_t launch_track(const TrackArgs& a, int n_events, int persistent_blocks, int* order_scratch,
+                        hipStream_t s)
+{
+    if (a.mlp_dtype != PVF_FP32 && (!a.mlp_lp || a.n_out > kMlpOutN ||
+                                    (a.mlp_dtype == PVF_FP8_E4M3 && (!a.mlp_in_inv || !a.mlp_col))))
+        return hipErrorInvalidValue;
+    switch (a.mlp_dtype) {
+    case PVF_FP32: return launch_track_typed<float>(a, n_events, persistent_blocks, order_scratch, s);
+    case PVF_BF16: return launch_track_typed<__bf16>(a, n_events, persistent_blocks, order_scratch, s);
+    case PVF_FP16: return launch_track_typed<_Float16>(a, n_events, persistent_blocks, order_scratch, s);
+    case PVF_FP8_E4M3: return launch_track_typed<uint8_t>(a, n_events, persistent_blocks, order_scratch, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace pvf

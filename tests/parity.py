@@ -96,11 +96,13 @@ def compare_peaks(gpu_t, gpu_z, gpu_prob, gpu_S, ref, geo):
 #   |dz| <= 0.05 mm: at least MATCH_MIN[dtype] of the oracle's, and at most
 #   EXTRA_MAX[dtype] (as a fraction of the oracle's count) unmatched extras.
 # FP8 (e4m3, 3 mantissa bits: unit roundoff 2^-4) with per-channel scales
-# from a calibration batch of other events: the same emulation over all 14
-# matrix-core convolutions gave max|dp| 0.12-0.18 and 97.5-98.6% of vertices
-# matched over several seeds; the bounds leave room for the rounding-order
-# differences of the kernels.
-P_ABS = {"bf16": 2e-2, "fp16": 5e-3, "fp8_e4m3": 0.25}
+# from a calibration batch of other events, for the UNet convolutions and the
+# track network's GEMMs alike: the emulation of that path gives max|dp|
+# 0.23-0.24 and 96.5-97.7% of vertices matched on these 16 events (0.12-0.18
+# with the network in FP32); the bound is 1.25x the emulated maximum.
+# BF16 and FP16 keep their bounds with the network in 16 bits (emulated
+# 1.5e-2 and 1.6e-3).
+P_ABS = {"bf16": 2e-2, "fp16": 5e-3, "fp8_e4m3": 0.3}
 MATCH_MIN = {"bf16": 0.995, "fp16": 0.999, "fp8_e4m3": 0.95}
 EXTRA_MAX = {"bf16": 0.005, "fp16": 0.001, "fp8_e4m3": 0.05}
 DZ_MATCH = 0.05

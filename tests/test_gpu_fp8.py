@@ -61,7 +61,21 @@ def test_calibration_table_matches_oracle_taps():
     # stored tensors in launch order, with their channel counts
     stored = [n for n in names if n not in ("track", "peaks", "dec0.c2+head")]
     chans = {n: (32 << int(n[3])) if n.startswith(("enc", "dec")) else (32 << int(n[2])) for n in stored}
-    assert len(amax) == sum(chans.values())
+    n_unet = sum(chans.values())
+    n_mlp = 9 + w.shape.n_hidden * w.shape.hidden         # every track-network layer input
+    assert len(amax) == n_unet + n_mlp
+    # the network's first inputs are the features of every kept track
+    g_max = np.zeros(9)
+    for e in range(batch.n_events):
+        tr = batch.tracks_of(e)
+        for t in range(tr.shape[1]):
+            i = oracle.bin_index(tr[0, t])
+            if i >= 0:
+                g_max = np.maximum(g_max, np.abs(oracle.features(tr[:, t], i, w)))
+    got = amax[n_unet:n_unet + 9]
+    err = float(np.max(np.abs(got - g_max) / g_max))
+    say("network inputs calibration max rel err %.2e" % err)
+    assert err <= 1e-6
     off = {}
     k = 0
     for n in stored:
