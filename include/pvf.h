@@ -166,20 +166,21 @@ pvf_status pvf_init(const pvf_spec *spec, const void *weights_blob, size_t blob_
                     void *d_arena, size_t arena_bytes, void *stream, pvf_engine **out);
 
 /* FP8 engine (spec.compute_dtype = PVF_FP8_E4M3).  amax: host floats, the
- * per-channel absolute maxima of every stored activation measured by
- * pvf_calibrate on a higher-precision engine of the same network, n_amax of
- * them.  Each stored FP8 tensor then holds x / a_c with a_c = amax_c / 448;
- * each convolution folds its input scales into its weights and quantises
- * every output column with its own scale (per-output-channel).  pvf_init
- * with an FP8 spec returns PVF_ERR_INVALID_ARGUMENT (the scales are needed). */
+ * calibration table that pvf_calibrate measured on a higher-precision engine
+ * of the same network, n_amax of them.  Each stored FP8 tensor then holds
+ * x / a_c with a_c = amax_c / 448; each convolution and each layer of the
+ * track network folds its input scales into its weights and quantises every
+ * output column with its own scale (per-output-channel).  pvf_init with an
+ * FP8 spec returns PVF_ERR_INVALID_ARGUMENT (the scales are needed). */
 pvf_status pvf_init_fp8(const pvf_spec *spec, const void *weights_blob, size_t blob_bytes, const float *amax,
                         size_t n_amax, void *d_arena, size_t arena_bytes, void *stream, pvf_engine **out);
 
 /* Calibration for FP8 (set-up call, synchronises nothing but clears d_amax
  * on the stream): runs the batch like pvf_execute on an FP32/BF16/FP16
- * engine and writes into d_amax (device floats) the per-channel absolute
- * maxima of every stored activation, in launch order.  n must equal
- * pvf_calibration_size(eng).  Not for graph capture. */
+ * engine and writes into d_amax (device floats) per-channel absolute maxima:
+ * first of every stored UNet activation, in launch order, then of every
+ * track-network layer input (9 features, then 20 channels per hidden
+ * layer).  n must equal pvf_calibration_size(eng).  Not for graph capture. */
 int64_t pvf_calibration_size(const pvf_engine *eng);
 pvf_status pvf_calibrate(pvf_engine *eng, const pvf_tracks *tracks, const pvf_vertices *out, float *d_amax,
                          int64_t n);
