@@ -32,6 +32,11 @@ METRIC = "events/sec on 1 MI355X (FP32 vs BF16/FP8 at stated tol); p99 µs/event
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "fp8_e4m3": 5000.0}
 DTYPE_TAG = {"fp32": "f32", "bf16": "bf16", "fp16": "f16", "fp8_e4m3": "fp8_e4m3"}
 HBM_PEAK_GBS = 8000.0
+# error bounds against the FP64 oracle that the GPU tests enforce for each
+# reduced-precision path (max |p - p_ref|; vertices matched within 0.05 mm)
+STATED_TOL = {"bf16": {"max_abs_dp": 2e-2, "vertices_matched_min": 0.995, "extra_vertices_max": 0.005},
+              "fp16": {"max_abs_dp": 5e-3, "vertices_matched_min": 0.999, "extra_vertices_max": 0.001},
+              "fp8_e4m3": {"max_abs_dp": 0.3, "vertices_matched_min": 0.95, "extra_vertices_max": 0.05}}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = {"conv_mfma_f32": "conv_kernel.hip", "conv_mfma_lp": "conv_lp_kernel.hip",
                   "track_stage": "track_kernel.hip", "peak_finder": "peaks_kernel.hip",
@@ -213,6 +218,8 @@ def main():
                     help="time every tile variant per launch first and keep the fastest (the built-in "
                          "defaults are the picks of such sweeps on this workload)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-compare-dtypes", dest="compare_dtypes", action="store_false",
+                    help="FP32 runs only: skip the BF16 and FP8 passes on the same batch")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size kernel "
                          "for scaling hardware byte counters)")
@@ -245,201 +252,221 @@ def main():
     T = np.diff(batch.offsets)
     variant = dict(n_levels=levels, base_channels=args.width, unet_layout=args.layout,
                    boundary_mm=args.boundary_mm)
-    spec = pv.default_spec(max_events=E, max_tracks_total=int(max(T.sum(), 1)), compute_dtype=args.dtype,
-                           max_tracks_per_event=max(1500, int(T.max())), **variant)
-    amax = None
-    if args.dtype == "fp8_e4m3":
-        # set-up, before and outside the timed region: channel scales from an
-        # FP32 run over other events
-        cb = make_events(args.calib_events, seed=args.seed + 5, mix=args.mix)
-        CT = np.diff(cb.offsets)
-        cspec = pv.default_spec(max_events=cb.n_events, max_tracks_total=int(max(CT.sum(), 1)),
-                                max_tracks_per_event=max(1500, int(CT.max())), **variant)
-        ceng = pv.Engine(weights_to_blob(w), cspec)
-        cf, co = pv.upload_events(cb)
-        amax = ceng.calibrate(cf, co)
-        ceng.close()
-        del cf, co
-        print(f"[bench] FP8 calibration over {cb.n_events} events: {amax.size} channel scales",
-              file=sys.stderr, flush=True)
-    eng = pv.Engine(weights_to_blob(w), spec, fp8_amax=amax)
-    eng.set_track_schedule(args.schedule == "queue")
-    feat, off = pv.upload_events(batch)
-    out = eng.alloc_outputs(E, with_prob=False)
-    names = eng.launch_names()
-    if args.autotune:
-        t_tune = time.perf_counter()
-        picked = eng.autotune(feat, off, eng.alloc_outputs(E, with_prob=False), reps=2)
-        print(f"[bench] autotuned in {time.perf_counter() - t_tune:.1f} s: "
-              + ", ".join(f"{n}={v}" for n, v in zip(names, picked) if v >= 0), file=sys.stderr, flush=True)
-    kernels = eng.launch_kernels()
-    print(f"[bench] E={E} mix={args.mix} tracks={int(T.sum())} arena={eng.arena_bytes / 1e9:.2f} GB "
-          f"launches={len(names)}", file=sys.stderr, flush=True)
+    def measure(dtype, copy_mib):
+        """One dtype on this batch: build (and for FP8 calibrate) an engine,
+        warm up, time the steps, and return (result dict, engine)."""
+        spec = pv.default_spec(max_events=E, max_tracks_total=int(max(T.sum(), 1)), compute_dtype=dtype,
+                               max_tracks_per_event=max(1500, int(T.max())), **variant)
+        amax = None
+        if dtype == "fp8_e4m3":
+            # set-up, before and outside the timed region: channel scales from an
+            # FP32 run over other events
+            cb = make_events(args.calib_events, seed=args.seed + 5, mix=args.mix)
+            CT = np.diff(cb.offsets)
+            cspec = pv.default_spec(max_events=cb.n_events, max_tracks_total=int(max(CT.sum(), 1)),
+                                    max_tracks_per_event=max(1500, int(CT.max())), **variant)
+            ceng = pv.Engine(weights_to_blob(w), cspec)
+            cf, co = pv.upload_events(cb)
+            amax = ceng.calibrate(cf, co)
+            ceng.close()
+            del cf, co
+            print(f"[bench] FP8 calibration over {cb.n_events} events: {amax.size} channel scales",
+                  file=sys.stderr, flush=True)
+        eng = pv.Engine(weights_to_blob(w), spec, fp8_amax=amax)
+        eng.set_track_schedule(args.schedule == "queue")
+        feat, off = pv.upload_events(batch)
+        out = eng.alloc_outputs(E, with_prob=False)
+        names = eng.launch_names()
+        if args.autotune:
+            t_tune = time.perf_counter()
+            picked = eng.autotune(feat, off, eng.alloc_outputs(E, with_prob=False), reps=2)
+            print(f"[bench] autotuned in {time.perf_counter() - t_tune:.1f} s: "
+                  + ", ".join(f"{n}={v}" for n, v in zip(names, picked) if v >= 0), file=sys.stderr, flush=True)
+        kernels = eng.launch_kernels()
+        print(f"[bench] E={E} mix={args.mix} tracks={int(T.sum())} arena={eng.arena_bytes / 1e9:.2f} GB "
+              f"launches={len(names)}", file=sys.stderr, flush=True)
 
-    if args.copy_calibration_mib > 0:
-        n = args.copy_calibration_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        print(f"[bench] calibration copy of {args.copy_calibration_mib} MiB done", file=sys.stderr, flush=True)
+        if copy_mib > 0:
+            n = copy_mib * (1 << 20) // 4
+            src = torch.ones(n, dtype=torch.float32, device="cuda")
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
+            print(f"[bench] calibration copy of {copy_mib} MiB done", file=sys.stderr, flush=True)
 
-    for _ in range(args.warmup):
-        eng.execute(feat, off, out)
-    eng.synchronize()
-    torch.cuda.synchronize()
-
-    per_launch = [[] for _ in names]
-    step_ms = []
-    s = eng.stream
-    if args.graph:
-        eng.graph_capture(feat, off, out)
-        eng.graph_launch()
+        for _ in range(args.warmup):
+            eng.execute(feat, off, out)
         eng.synchronize()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            ev0 = torch.cuda.Event(enable_timing=True)
-            ev1 = torch.cuda.Event(enable_timing=True)
-            ev0.record(s)
+
+        per_launch = [[] for _ in names]
+        step_ms = []
+        s = eng.stream
+        if args.graph:
+            eng.graph_capture(feat, off, out)
             eng.graph_launch()
-            ev1.record(s)
-            s.synchronize()
-            step_ms.append(ev0.elapsed_time(ev1))
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        eng.profile(True)                       # per-launch split from eager passes
-        for _ in range(3):
-            eng.execute(feat, off, out)
-            s.synchronize()
-            for i, ms in enumerate(eng.profile_read()):
-                per_launch[i].append(ms)
-        eng.profile(False)
-    else:
-        eng.profile(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            ev0 = torch.cuda.Event(enable_timing=True)
-            ev1 = torch.cuda.Event(enable_timing=True)
-            ev0.record(s)
-            eng.execute(feat, off, out)
-            ev1.record(s)
-            s.synchronize()
-            step_ms.append(ev0.elapsed_time(ev1))
-            for i, ms in enumerate(eng.profile_read()):
-                per_launch[i].append(ms)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        eng.profile(False)
+            eng.synchronize()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                ev0 = torch.cuda.Event(enable_timing=True)
+                ev1 = torch.cuda.Event(enable_timing=True)
+                ev0.record(s)
+                eng.graph_launch()
+                ev1.record(s)
+                s.synchronize()
+                step_ms.append(ev0.elapsed_time(ev1))
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            eng.profile(True)                       # per-launch split from eager passes
+            for _ in range(3):
+                eng.execute(feat, off, out)
+                s.synchronize()
+                for i, ms in enumerate(eng.profile_read()):
+                    per_launch[i].append(ms)
+            eng.profile(False)
+        else:
+            eng.profile(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                ev0 = torch.cuda.Event(enable_timing=True)
+                ev1 = torch.cuda.Event(enable_timing=True)
+                ev0.record(s)
+                eng.execute(feat, off, out)
+                ev1.record(s)
+                s.synchronize()
+                step_ms.append(ev0.elapsed_time(ev1))
+                for i, ms in enumerate(eng.profile_read()):
+                    per_launch[i].append(ms)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            eng.profile(False)
 
-    host = out.to_host()
-    if np.any(host["status"] & (pv.EV_TOO_MANY_TRACKS | pv.EV_BAD_INPUT)):
-        print("[bench] unexpected bypassed events", file=sys.stderr)
-        sys.exit(1)
+        host = out.to_host()
+        if np.any(host["status"] & (pv.EV_TOO_MANY_TRACKS | pv.EV_BAD_INPUT)):
+            print("[bench] unexpected bypassed events", file=sys.stderr)
+            sys.exit(1)
 
-    macs = layer_macs(spec)
-    valid_tracks = float(T.sum())
-    mean_ms = [statistics.mean(v) for v in per_launch]
-    flops_launch = [2.0 * (macs[n] * valid_tracks if n == "track" else macs[n] * E) for n in names]
-    print(f"[bench] {'launch':14s} {'kernel':36s} {'ms':>8s} {'TFLOP/s':>8s}", file=sys.stderr)
-    for n, k, ms, fl in zip(names, kernels, mean_ms, flops_launch):
-        print(f"[bench] {n:14s} {k:36s} {ms:8.3f} {fl / ms / 1e9:8.2f}", file=sys.stderr)
+        macs = layer_macs(spec)
+        valid_tracks = float(T.sum())
+        mean_ms = [statistics.mean(v) for v in per_launch]
+        flops_launch = [2.0 * (macs[n] * valid_tracks if n == "track" else macs[n] * E) for n in names]
+        print(f"[bench] {'launch':14s} {'kernel':36s} {'ms':>8s} {'TFLOP/s':>8s}", file=sys.stderr)
+        for n, k, ms, fl in zip(names, kernels, mean_ms, flops_launch):
+            print(f"[bench] {n:14s} {k:36s} {ms:8.3f} {fl / ms / 1e9:8.2f}", file=sys.stderr)
 
-    # dominant kernel instance: largest total time per step
-    by_kernel = {}
-    for n, k, ms, fl in zip(names, kernels, mean_ms, flops_launch):
-        d = by_kernel.setdefault(k, {"ms": 0.0, "flops": 0.0, "launches": 0, "layers": []})
-        d["ms"] += ms
-        d["flops"] += fl
-        d["launches"] += 1
-        d["layers"].append(n)
-    dom_name, dom = max(by_kernel.items(), key=lambda kv: kv[1]["ms"])
-    avg_dur_s = dom["ms"] / dom["launches"] / 1e3
-    flops_per_launch = dom["flops"] / dom["launches"]
-    eb = {"fp32": 4, "fp8_e4m3": 1}.get(args.dtype, 2)
-    lbytes = layer_bytes(spec, eb)
-    lbytes["track"] = (36.0 * valid_tracks + E * spec.n_bins * 4) / E
-    bytes_per_launch = sum(lbytes[n] * E for n in dom["layers"]) / dom["launches"]
-    peak = PEAK_TFLOPS[args.dtype]
-    ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)          # flop per byte
-    intensity = flops_per_launch / bytes_per_launch
-    if intensity >= ridge:
-        bound, achieved, peak_v, unit = "mfma", flops_per_launch / avg_dur_s / 1e12, peak, "TFLOP/s"
-    else:
-        bound, achieved, peak_v, unit = "hbm", bytes_per_launch / avg_dur_s / 1e9, HBM_PEAK_GBS, "GB/s"
-    def measured_traffic(kernel):
-        """HBM bytes per launch from the committed counter passes, if they
-        were taken on this kernel's current source at this batch size."""
-        if not os.path.exists(TRAFFIC_FILE):
+        # dominant kernel instance: largest total time per step
+        by_kernel = {}
+        for n, k, ms, fl in zip(names, kernels, mean_ms, flops_launch):
+            d = by_kernel.setdefault(k, {"ms": 0.0, "flops": 0.0, "launches": 0, "layers": []})
+            d["ms"] += ms
+            d["flops"] += fl
+            d["launches"] += 1
+            d["layers"].append(n)
+        dom_name, dom = max(by_kernel.items(), key=lambda kv: kv[1]["ms"])
+        avg_dur_s = dom["ms"] / dom["launches"] / 1e3
+        flops_per_launch = dom["flops"] / dom["launches"]
+        eb = {"fp32": 4, "fp8_e4m3": 1}.get(dtype, 2)
+        lbytes = layer_bytes(spec, eb)
+        lbytes["track"] = (36.0 * valid_tracks + E * spec.n_bins * 4) / E
+        bytes_per_launch = sum(lbytes[n] * E for n in dom["layers"]) / dom["launches"]
+        peak = PEAK_TFLOPS[dtype]
+        ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)          # flop per byte
+        intensity = flops_per_launch / bytes_per_launch
+        if intensity >= ridge:
+            bound, achieved, peak_v, unit = "mfma", flops_per_launch / avg_dur_s / 1e12, peak, "TFLOP/s"
+        else:
+            bound, achieved, peak_v, unit = "hbm", bytes_per_launch / avg_dur_s / 1e9, HBM_PEAK_GBS, "GB/s"
+        def measured_traffic(kernel):
+            """HBM bytes per launch from the committed counter passes, if they
+            were taken on this kernel's current source at this batch size."""
+            if not os.path.exists(TRAFFIC_FILE):
+                return None
+            tr = json.load(open(TRAFFIC_FILE)).get(f"{kernel}|E={E}")
+            if tr and tr.get("source_sha256") == kernel_source_sha(kernel):
+                return tr.get("bytes_per_launch")
             return None
-        tr = json.load(open(TRAFFIC_FILE)).get(f"{kernel}|E={E}")
-        if tr and tr.get("source_sha256") == kernel_source_sha(kernel):
-            return tr.get("bytes_per_launch")
-        return None
 
-    default_shape = (args.width == 32 and args.layout == "event" and levels == 4 and args.boundary_mm == 0
-                     and args.mix == "poisson" and args.seed == 0)
-    traffic = measured_traffic(dom_name) if default_shape else None
+        default_shape = (args.width == 32 and args.layout == "event" and levels == 4 and args.boundary_mm == 0
+                         and args.mix == "poisson" and args.seed == 0)
+        traffic = measured_traffic(dom_name) if default_shape else None
 
-    stage = {"track": mean_ms[0], "unet": sum(mean_ms[1:-1]), "peaks": mean_ms[-1]}
-    ms_per_step = wall / args.steps * 1e3
-    us_ev = sorted(m * 1e3 / E for m in step_ms)
-    p50 = statistics.median(us_ev)
-    p99 = us_ev[min(len(us_ev) - 1, int(round(0.99 * (len(us_ev) - 1))))]
-    unet_flops = sum(f for n, f in zip(names, flops_launch) if n not in ("track", "peaks"))
-    # track stage: network evaluations of every kept track (a boundary track
-    # counts once here), input bytes 36 per track plus the histogram rows
-    track_ms = mean_ms[0]
-    track_bytes = 36.0 * valid_tracks + E * spec.n_bins * 4
-    track_traffic = measured_traffic(kernels[0]) if default_shape else None
+        stage = {"track": mean_ms[0], "unet": sum(mean_ms[1:-1]), "peaks": mean_ms[-1]}
+        ms_per_step = wall / args.steps * 1e3
+        us_ev = sorted(m * 1e3 / E for m in step_ms)
+        p50 = statistics.median(us_ev)
+        p99 = us_ev[min(len(us_ev) - 1, int(round(0.99 * (len(us_ev) - 1))))]
+        unet_flops = sum(f for n, f in zip(names, flops_launch) if n not in ("track", "peaks"))
+        # track stage: network evaluations of every kept track (a boundary track
+        # counts once here), input bytes 36 per track plus the histogram rows
+        track_ms = mean_ms[0]
+        track_bytes = 36.0 * valid_tracks + E * spec.n_bins * 4
+        track_traffic = measured_traffic(kernels[0]) if default_shape else None
 
-    result = {
-        "metric": METRIC,
-        "value": E * args.steps / wall,
-        "unit": "events/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": DTYPE_TAG[args.dtype],
-        "data": "synthetic: seeded events (Poisson(5.6) PVs, Poisson(180) tracks) and seeded He-init weights",
-        "config": {"workload": f"{E} events per batch, {args.mix} track counts (mean {T.mean():.1f}), "
-                               f"UNet {'/'.join(str(args.width << l) for l in range(levels))} over "
-                               + ("4000 bins" if args.layout == "event" else "each 100-bin interval")
-                               + (f", boundary tracks within {args.boundary_mm} mm feed two intervals"
-                                  if args.boundary_mm > 0 else "")
-                               + f", {args.dtype.upper()} convolutions (FP32 accumulate)"
-                               + (f", FP8 scales from {args.calib_events} calibration events" if amax is not None else "")
-                               + f", seed {args.seed}",
-                   "events_per_batch": E, "tracks_total": int(T.sum()), "max_tracks": int(T.max()),
-                   "track_schedule": args.schedule, "hip_graph": bool(args.graph)},
-        "p50_us_per_event": p50,
-        "p99_us_per_event": p99,
-        "stages_ms": stage,
-        "unet_tflops": unet_flops / (stage["unet"] / 1e3) / 1e12,
-        "variants": dict((n, v) for n, v in zip(names, eng.variants()) if v >= 0),
-        "events_per_s_median_step": E / (statistics.median(step_ms) / 1e3),
-        "track_stage": {"ms": track_ms, "gflops": flops_launch[0] / track_ms / 1e6,
-                        "algorithmic_gbs": track_bytes / track_ms / 1e6,
-                        "measured_gbs": (track_traffic / track_ms / 1e6) if track_traffic else None},
-        "roofline": {"bound": bound, "kernel": dom_name, "layers": dom["layers"],
-                     "achieved": achieved, "peak": peak_v, "unit": unit, "frac": achieved / peak_v,
-                     "traffic": traffic,
-                     "hbm_frac": (traffic / avg_dur_s / (HBM_PEAK_GBS * 1e9)) if traffic else None,
-                     "flops_per_launch": flops_per_launch,
-                     "algorithmic_bytes_per_launch": bytes_per_launch, "intensity_flop_per_byte": intensity,
-                     "ridge_flop_per_byte": ridge, "avg_launch_ms": avg_dur_s * 1e3},
-    }
+        result = {
+            "metric": METRIC,
+            "value": E * args.steps / wall,
+            "unit": "events/s",
+            "n_gpus": 1,
+            "steps": args.steps,
+            "warmup": args.warmup,
+            "ms_per_step": ms_per_step,
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": DTYPE_TAG[dtype],
+            "data": "synthetic: seeded events (Poisson(5.6) PVs, Poisson(180) tracks) and seeded He-init weights",
+            "config": {"workload": f"{E} events per batch, {args.mix} track counts (mean {T.mean():.1f}), "
+                                   f"UNet {'/'.join(str(args.width << l) for l in range(levels))} over "
+                                   + ("4000 bins" if args.layout == "event" else "each 100-bin interval")
+                                   + (f", boundary tracks within {args.boundary_mm} mm feed two intervals"
+                                      if args.boundary_mm > 0 else "")
+                                   + f", {dtype.upper()} convolutions (FP32 accumulate)"
+                                   + (f", FP8 scales from {args.calib_events} calibration events" if amax is not None else "")
+                                   + f", seed {args.seed}",
+                       "events_per_batch": E, "tracks_total": int(T.sum()), "max_tracks": int(T.max()),
+                       "track_schedule": args.schedule, "hip_graph": bool(args.graph)},
+            "p50_us_per_event": p50,
+            "p99_us_per_event": p99,
+            "stages_ms": stage,
+            "unet_tflops": unet_flops / (stage["unet"] / 1e3) / 1e12,
+            "variants": dict((n, v) for n, v in zip(names, eng.variants()) if v >= 0),
+            "events_per_s_median_step": E / (statistics.median(step_ms) / 1e3),
+            "track_stage": {"ms": track_ms, "gflops": flops_launch[0] / track_ms / 1e6,
+                            "algorithmic_gbs": track_bytes / track_ms / 1e6,
+                            "measured_gbs": (track_traffic / track_ms / 1e6) if track_traffic else None},
+            "roofline": {"bound": bound, "kernel": dom_name, "layers": dom["layers"],
+                         "achieved": achieved, "peak": peak_v, "unit": unit, "frac": achieved / peak_v,
+                         "traffic": traffic,
+                         "hbm_frac": (traffic / avg_dur_s / (HBM_PEAK_GBS * 1e9)) if traffic else None,
+                         "flops_per_launch": flops_per_launch,
+                         "algorithmic_bytes_per_launch": bytes_per_launch, "intensity_flop_per_byte": intensity,
+                         "ridge_flop_per_byte": ridge, "avg_launch_ms": avg_dur_s * 1e3},
+        }
+        return result, eng
+
+    result, eng = measure(args.dtype, args.copy_calibration_mib)
+    eng.close()
+    if args.compare_dtypes and args.dtype == "fp32":
+        # the same batch and timing in the reduced-precision paths, each with
+        # the error bound the GPU tests hold it to against the FP64 oracle
+        result["other_dtypes"] = {}
+        for dt in ("bf16", "fp8_e4m3"):
+            r, e2 = measure(dt, 0)
+            e2.close()
+            result["other_dtypes"][dt] = {
+                "value": r["value"], "unit": "events/s", "ms_per_step": r["ms_per_step"],
+                "p50_us_per_event": r["p50_us_per_event"], "p99_us_per_event": r["p99_us_per_event"],
+                "stages_ms": r["stages_ms"], "dtype": r["dtype"],
+                "roofline": {k: r["roofline"][k] for k in ("bound", "kernel", "achieved", "peak", "unit", "frac")},
+                "stated_tolerance": STATED_TOL[dt]}
+            print(f"[bench] {dt}: {r['value']:.0f} events/s", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] CPU baseline (FP64 oracle)...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(batch, w, args.cpu_seconds)
-    eng.close()
     print(json.dumps(result), flush=True)
 
 

@@ -407,6 +407,12 @@ namespace {
 template <class T>
 T* at(pvf_engine* e, size_t off) { return reinterpret_cast<T*>(e->arena + off); }
 
+std::string track_kernel_name(bool persistent, int dtype)
+{
+    static const char* const kType[] = {"float", "__bf16", "_Float16", "unsigned char"};
+    return std::string(persistent ? "track_stage_queue<" : "track_stage<") + kType[dtype] + ">";
+}
+
 void build_names(pvf_engine* e)
 {
     const int n = e->spec.n_levels;
@@ -443,7 +449,7 @@ void build_names(pvf_engine* e)
         e->conv.push_back(c);
         e->out_channels.push_back(epi == EPI_HEAD ? 0 : cout);
     };
-    plain("track", e->track_blocks > 0 ? "track_stage_queue" : "track_stage", 0);
+    plain("track", track_kernel_name(e->track_blocks > 0, e->spec.compute_dtype), 0);
     for (int l = 0; l < n; ++l) {
         const std::string L = std::to_string(l);
         const int C = c0 << l;
@@ -475,6 +481,7 @@ void build_names(pvf_engine* e)
 }
 
 bool misaligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) != 0; }
+
 
 // The track network's layers inside the packed FP32 weights (blob order):
 // W [N][K] row-major, then b [N].
@@ -1050,7 +1057,7 @@ pvf_status pvf_set_track_schedule(pvf_engine* eng, int persistent)
 {
     if (!eng || (persistent != 0 && persistent != 1)) return PVF_ERR_INVALID_ARGUMENT;
     eng->track_blocks = persistent ? 2 * eng->cu_count : 0;
-    eng->kernels[0] = persistent ? "track_stage_queue" : "track_stage";
+    eng->kernels[0] = track_kernel_name(persistent, eng->spec.compute_dtype);
     return PVF_OK;
 }
 

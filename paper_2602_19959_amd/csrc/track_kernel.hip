@@ -294,11 +294,14 @@ __device__ void track_event(const TrackArgs& a, int e, float* smem)
     // A for one item per thread: the hidden layers (FP32 in registers, then
     // to hb; or the matrix-core layers in xa)
     auto network_hidden = [&](const float* g, bool valid) {
+        // a wave without a single kept item skips the network (its rows are
+        // never accumulated, and it adds nothing to a calibration maximum)
+        const bool any = __ballot(valid) != 0;
         if constexpr (kF32) {
             float h[kHidden];
-            hidden_layers_f32(a, g, valid, h);
+            if (any) hidden_layers_f32(a, g, valid, h);
 #pragma unroll
-            for (int j = 0; j < kHidden; ++j) hb[tid * HP + j] = valid ? h[j] : 0.f;
+            for (int j = 0; j < kHidden; ++j) hb[tid * HP + j] = (any && valid) ? h[j] : 0.f;
         } else {
             float z[kFeat];
 #pragma unroll
@@ -308,7 +311,7 @@ __device__ void track_event(const TrackArgs& a, int e, float* smem)
                 for (int k = 0; k < kFeat; ++k) wave_amax(a.mlp_calib + calib_off(0) + k, z[k]);
             store_inputs<E>(a, xa, tid, z);
             __builtin_amdgcn_wave_barrier();
-            hidden_layers_mma<E>(a, xa, wave, lane);
+            if (any) hidden_layers_mma<E>(a, xa, wave, lane);
         }
     };
 
