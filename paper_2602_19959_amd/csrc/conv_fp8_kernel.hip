@@ -14,8 +14,11 @@
 //
 // MFMA: v_mfma_f32_16x16x32_fp8_fp8.  One stage = 32 input channels (32 bytes
 // per row); each lane reads 8 consecutive channels (8 bytes) of its row (A)
-// and of its column (B); the 32 lanes an LDS pass serves read 512 consecutive
-// bytes, so rows need no padding or swizzle.
+// and of its column (B).  32-byte LDS rows, two 16-byte chunks; chunk q of
+// row r sits at q ^ bit 3 of r (swz32): measured on gfx950 with a read-pattern
+// probe, the fragment reads (16 consecutive rows, or rows TAPS apart for the
+// weights, at any tap offset) then run at the conflict-free rate, where the
+// unswizzled rows took two LDS passes per read.
 #include "pvf_internal.h"
 
 namespace pvf {
@@ -24,6 +27,10 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int KC = 32;            // input channels (bytes) per stage and row
+
+__device__ __forceinline__ int swz32(int r) { return (r >> 3) & 1; }
+// byte offset of the 8-byte piece p (0..3) of row r in a 32-byte-row tile
+__device__ __forceinline__ int at32(int r, int p) { return r * KC + 16 * ((p >> 1) ^ swz32(r)) + 8 * (p & 1); }
 
 __device__ __forceinline__ float lrelu(float x, float s) { return x >= 0.f ? x : s * x; }
 
@@ -222,7 +229,7 @@ void conv_mfma_fp8(ConvArgs a)
             const int64_t g = m0 - RAD + row;
             uint4 v = {0u, 0u, 0u, 0u};
             if (g >= 0 && g < a.m_rows) v = *reinterpret_cast<const uint4*>(in + g * a.ld_in + c0 + 16 * q);
-            *reinterpret_cast<uint4*>(xs + row * KC + 16 * q) = v;
+            *reinterpret_cast<uint4*>(xs + row * KC + 16 * (q ^ swz32(row))) = v;
         }
         for (int idx = tid; idx < WV; idx += NT) {
             const int q = idx % NCH, rest = idx / NCH;
@@ -230,7 +237,7 @@ void conv_mfma_fp8(ConvArgs a)
             uint4 v = {0u, 0u, 0u, 0u};
             if (n0 + nn < a.n)
                 v = *reinterpret_cast<const uint4*>(wt + (int64_t)(n0 + nn) * kw + tap * a.cin + c0 + 16 * q);
-            *reinterpret_cast<uint4*>(ws + rest * KC + 16 * q) = v;
+            *reinterpret_cast<uint4*>(ws + rest * KC + 16 * (q ^ swz32(rest))) = v;
         }
         __syncthreads();
 #pragma unroll
@@ -238,10 +245,10 @@ void conv_mfma_fp8(ConvArgs a)
             long av[TMW], bv[TNW];
 #pragma unroll
             for (int i = 0; i < TMW; ++i)
-                av[i] = *reinterpret_cast<const long*>(xs + (wm * TMW * 16 + i * 16 + li + tap) * KC + 8 * lg);
+                av[i] = *reinterpret_cast<const long*>(xs + at32(wm * TMW * 16 + i * 16 + li + tap, lg));
 #pragma unroll
             for (int j = 0; j < TNW; ++j)
-                bv[j] = *reinterpret_cast<const long*>(ws + ((wn * TNW * 16 + j * 16 + li) * TAPS + tap) * KC + 8 * lg);
+                bv[j] = *reinterpret_cast<const long*>(ws + at32((wn * TNW * 16 + j * 16 + li) * TAPS + tap, lg));
 #pragma unroll
             for (int i = 0; i < TMW; ++i)
 #pragma unroll
@@ -262,10 +269,12 @@ void conv_mfma_fp8(ConvArgs a)
 // (global_load_lds_dwordx4) while stage k computes, and the fragments of the
 // next (chunk, tap) are read during the current MFMAs.  Same k order as
 // conv_mfma_fp8 (32-channel chunk, tap), so the same bits.  Chunk c of row r
-// sits at c ^ 2*bit3(r): 16 consecutive rows then read 8-byte pieces from
-// distinct banks.  Out-of-range rows and columns are clamped (their outputs
+// sits at c ^ bits 2..3 of r: measured on gfx950 with a read-pattern probe,
+// the 8-byte fragment reads (16 consecutive rows, or rows TAPS apart, at any
+// tap offset) then run at the conflict-free rate, twice as fast as with
+// c ^ 2*bit3(r).  Out-of-range rows and columns are clamped (their outputs
 // are discarded).
-__device__ __forceinline__ int swz64(int r) { return ((r >> 3) & 1) << 1; }
+__device__ __forceinline__ int swz64(int r) { return (r >> 2) & 3; }
 
 template <int WM, int WN, int TMW, int TNW, int TAPS, int EPI>
 __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_fp8_db(ConvArgs a)

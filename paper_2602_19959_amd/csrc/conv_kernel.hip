@@ -35,9 +35,11 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int KC = 16;         // input channels per LDS stage = 4 chunks of 16 B
 
 // LDS rows are KC floats (4 chunks of 16 B) with no padding; chunk q of row r
-// is stored at position q ^ swz(r).  The 32 lanes a 16-byte LDS read serves
-// at once (16 consecutive rows x 2 chunks) then hit 32 distinct chunk slots,
-// for the halo tile, the weight tile and the staging writes alike.
+// is stored at position q ^ swz(r), swz(r) = 2 * bit 3 of r.  Read-pattern
+// probes on gfx950 show that bits 1..2 of r would make every fragment read
+// conflict-free (with this one only the halo reads of tap 0 are), yet the
+// dominant FP32 layer ran 6% slower with it in repeated A/B runs (same
+// instruction stream apart from the address arithmetic; cause not pinned down).
 __device__ __forceinline__ int swz(int r) { return (r >> 2) & 2; }
 __device__ __forceinline__ int lds_at(int r, int q) { return (r * 4 + (q ^ swz(r))) * 4; }   // in floats
 

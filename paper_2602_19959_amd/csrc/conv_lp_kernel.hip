@@ -39,13 +39,14 @@ template <> struct Lp<_Float16> {
 };
 
 // LDS rows hold one stage's KC channels as NCH = KC/8 chunks of 16 B, with no
-// padding; chunk c of row r sits at position c ^ swz(r).  A 16-byte LDS read
-// serves 32 lanes at once (16 consecutive rows x 2 chunks); the swizzle spreads
-// the rows that share a bank offset over distinct chunk slots.
+// padding; chunk c of row r sits at position c ^ swz(r): bits 1..2 of r for
+// 64-byte rows, twice that for 128-byte rows.  Measured on gfx950 with a
+// read-pattern probe, the fragment reads (16 consecutive rows, or rows TAPS
+// apart for the weights, at any tap offset) then run at the conflict-free rate.
 template <int NCH>
 __device__ __forceinline__ int swz(int r)
 {
-    return NCH == 4 ? ((r >> 2) & 2) : (((r >> 2) & 3) << 1);
+    return NCH == 4 ? ((r >> 1) & 3) : (((r >> 1) & 3) << 1);
 }
 template <int NCH>
 __device__ __forceinline__ int lds_at(int r, int c) { return (r * NCH + (c ^ swz<NCH>(r))) * 8; }   // elements
