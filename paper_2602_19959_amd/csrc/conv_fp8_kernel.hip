@@ -25,6 +25,7 @@ namespace pvf {
 namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int KC = 32;            // input channels (bytes) per stage and row
 
@@ -60,8 +61,10 @@ constexpr int occupancy_target(int lds_bytes, int waves_per_block)
     return w < 1 ? 1 : (w > 4 ? 4 : w);
 }
 
-// Epilogue shared by the FP8 kernels (the LDS passed in is free).  D layout
-// of a 16x16 MFMA: lane holds rows 4*lg + v of column li.
+// Epilogue shared by the FP8 kernels (the LDS passed in is free).  The
+// kernels issue the MFMA as D^T = W X^T (weight fragment in the A slot), so
+// lane (li, lg) of a 16 x 16 tile holds channels 4 lg + v (v = 0..3) of tile
+// row li: four consecutive FP8 outputs of one position, one 4-byte LDS store.
 template <int NT, int BM, int BN, int WM, int TMW, int TNW, int EPI>
 __device__ __forceinline__ void fp8_epilogue(const f32x4 (&acc)[TMW][TNW], const ConvArgs& a, void* lds, int64_t m0,
                                              int n0, int tid)
@@ -71,63 +74,54 @@ __device__ __forceinline__ void fp8_epilogue(const f32x4 (&acc)[TMW][TNW], const
     const int li = lane & 15, lg = lane >> 4;
     const int rw = (wave % WM) * TMW * 16;
     const int cw = (wave / WM) * TNW * 16;
+    const RowMap rows(m0, a.r_in);
     if constexpr (EPI == EPI_HEAD) {
 #pragma unroll
         for (int i = 0; i < TMW; ++i) {
+            float s = 0.f;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                float s = 0.f;
+            for (int j = 0; j < TNW; ++j) {
+                const int c = n0 + cw + j * 16 + 4 * lg;
 #pragma unroll
-                for (int j = 0; j < TNW; ++j) {
-                    const int col = n0 + cw + j * 16 + li;
-                    s += lrelu(acc[i][j][v] * a.col_scale[col] + a.bias[col], a.slope) * a.head_w[col];
-                }
-                s += __shfl_xor(s, 8);
-                s += __shfl_xor(s, 4);
-                s += __shfl_xor(s, 2);
-                s += __shfl_xor(s, 1);
-                const int64_t r = m0 + rw + i * 16 + 4 * lg + v;
-                if (li == 0 && r < a.m_rows) {
-                    const int64_t e = r / a.r_in;
-                    const int loc = (int)(r - e * a.r_in);
-                    if (loc >= kGuard && loc < a.r_in - kGuard)
-                        a.prob[e * a.l_out + (loc - kGuard)] = 1.f / (1.f + expf(-(s + a.head_b)));
-                }
+                for (int v = 0; v < 4; ++v)
+                    s += lrelu(acc[i][j][v] * a.col_scale[c + v] + a.bias[c + v], a.slope) * a.head_w[c + v];
+            }
+            s += __shfl_xor(s, 16);
+            s += __shfl_xor(s, 32);
+            const int t = rw + i * 16 + li;
+            if (lg == 0 && m0 + t < a.m_rows) {
+                int64_t e;
+                int loc;
+                rows.at(t, e, loc);
+                if (loc >= kGuard && loc < a.r_in - kGuard)
+                    a.prob[e * a.l_out + (loc - kGuard)] = 1.f / (1.f + expf(-(s + a.head_b)));
             }
         }
         return;
     } else {
         uint8_t* ot = static_cast<uint8_t*>(lds);   // [BM][OP] bytes
-        // A lane holds 4 rows (4 lg + v) of one column; a 4 x 4 byte transpose
-        // inside each quad of lanes (two DPP exchanges, two byte permutes)
-        // gives lane 4k + m row 4 lg + m of columns 4k .. 4k + 3, written as
-        // one 4-byte LDS store instead of four single-byte ones.
-        const int m = li & 3, kq = li >> 2;
 #pragma unroll
         for (int j = 0; j < TNW; ++j) {
-            const int col = cw + j * 16 + li;
-            const int n = n0 + col;
-            const int oc = EPI == EPI_CONVT ? n % a.cout : n;      // output channel
-            const float cs = n < a.n ? a.col_scale[n] : 0.f;
-            const float b = n < a.n ? a.bias[oc] : 0.f;
-            const float inv = n < a.n ? a.out_inv_scale[oc] : 0.f;
+            const int col = cw + j * 16 + 4 * lg;
+            float cs[4], b[4], inv[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int n = min(n0 + col + v, a.n - 1);   // columns beyond n are never stored
+                const int oc = EPI == EPI_CONVT ? n % a.cout : n;
+                cs[v] = a.col_scale[n];
+                b[v] = a.bias[oc];
+                inv[v] = a.out_inv_scale[oc];
+            }
 #pragma unroll
             for (int i = 0; i < TMW; ++i) {
                 uint32_t w = 0;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    float y = acc[i][j][v] * cs + b;
+                    float y = acc[i][j][v] * cs[v] + b[v];
                     if (EPI != EPI_CONVT) y = lrelu(y, a.slope);
-                    w |= (uint32_t)to_e4m3(y * inv) << (8 * v);
+                    w |= (uint32_t)to_e4m3(y * inv[v]) << (8 * v);
                 }
-                // quad exchange 1 (lanes m ^ 1): even m keeps bytes 0, 2 and
-                // takes the partner's 0, 2; odd m the partner's 1, 3 and its own 1, 3
-                const uint32_t p1 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0xB1, 0xF, 0xF, false);
-                const uint32_t x = __builtin_amdgcn_perm(p1, w, (m & 1) ? 0x03070105u : 0x06020400u);
-                // quad exchange 2 (lanes m ^ 2)
-                const uint32_t p2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);
-                const uint32_t y4 = __builtin_amdgcn_perm(p2, x, (m & 2) ? 0x03020706u : 0x05040100u);
-                *reinterpret_cast<uint32_t*>(ot + (rw + i * 16 + 4 * lg + m) * OP + cw + j * 16 + 4 * kq) = y4;
+                *reinterpret_cast<uint32_t*>(ot + (rw + i * 16 + li) * OP + col) = w;
             }
         }
         __syncthreads();
@@ -136,10 +130,10 @@ __device__ __forceinline__ void fp8_epilogue(const f32x4 (&acc)[TMW][TNW], const
         const int n_valid = a.n - n0 < BN ? a.n - n0 : BN;
         for (int idx = tid; idx < BM * CH; idx += NT) {
             const int row = idx / CH, q = idx % CH;
-            const int64_t r = m0 + row;
-            if (16 * q >= n_valid || r >= a.m_rows) continue;
-            const int64_t e = r / a.r_in;
-            const int loc = (int)(r - e * a.r_in);
+            if (16 * q >= n_valid || m0 + row >= a.m_rows) continue;
+            int64_t e;
+            int loc;
+            rows.at(row, e, loc);
             if (loc < kGuard || loc >= a.r_in - kGuard) continue;
             const uint4 v = *reinterpret_cast<const uint4*>(ot + row * OP + 16 * q);
             if constexpr (EPI == EPI_CONVT) {
@@ -148,17 +142,17 @@ __device__ __forceinline__ void fp8_epilogue(const f32x4 (&acc)[TMW][TNW], const
                 const int64_t ro = e * a.r_out + kGuard + 2 * (loc - kGuard) + tj;
                 *reinterpret_cast<uint4*>(out + ro * a.ld_out + o) = v;
             } else {
-                *reinterpret_cast<uint4*>(out + r * a.ld_out + n0 + 16 * q) = v;
+                *reinterpret_cast<uint4*>(out + (m0 + row) * a.ld_out + n0 + 16 * q) = v;
             }
         }
         if constexpr (EPI == EPI_POOL) {
             uint8_t* pout = static_cast<uint8_t*>(a.pool_out);
             for (int idx = tid; idx < (BM / 2) * CH; idx += NT) {
                 const int pr = idx / CH, q = idx % CH;
-                const int64_t r = m0 + 2 * pr;
-                if (16 * q >= n_valid || r >= a.m_rows) continue;
-                const int64_t e = r / a.r_in;
-                const int loc = (int)(r - e * a.r_in);
+                if (16 * q >= n_valid || m0 + 2 * pr >= a.m_rows) continue;
+                int64_t e;
+                int loc;
+                rows.at(2 * pr, e, loc);
                 if (loc < kGuard || loc >= a.r_in - kGuard) continue;
                 // two whole 16-byte rows from LDS, compared in registers
                 const uint4 r0 = *reinterpret_cast<const uint4*>(ot + (2 * pr) * OP + 16 * q);
@@ -223,22 +217,47 @@ void conv_mfma_fp8(ConvArgs a)
 #pragma unroll
         for (int j = 0; j < TNW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // Staging: thread tid owns chunk q = tid % NCH of LDS rows tid / NCH + u * RS
+    // in the halo tile and in the tap-major weight tile (row = tap * BN +
+    // column); every load of a stage is in flight before the first LDS store.
+    // Halo rows outside the batch and columns beyond n are clamped to valid
+    // ones: they only feed outputs the epilogue discards.
+    constexpr int RS = NT / NCH;
+    constexpr int WROWS = TAPS * BN;
+    constexpr int XPT = (XV + NT - 1) / NT, WPT = (WV + NT - 1) / NT;
+    static_assert(RS % 16 == 0, "chunk rows of one thread share their swizzle");
+    const int q = tid % NCH, row0 = tid / NCH;
+    const int lds0 = row0 * KC + 16 * (q ^ swz32(row0));   // + u * RS * KC for chunk u
+    auto x_has = [&](int u) __attribute__((always_inline)) { return (u + 1) * RS <= XROWS || row0 + u * RS < XROWS; };
+    auto w_has = [&](int u) __attribute__((always_inline)) { return (u + 1) * RS <= WROWS || row0 + u * RS < WROWS; };
+    const uint8_t* xsrc[XPT];
+    const uint8_t* wsrc[WPT];
+#pragma unroll
+    for (int u = 0; u < XPT; ++u) {
+        int64_t g = m0 - RAD + min(row0 + u * RS, XROWS - 1);
+        g = g < 0 ? 0 : (g >= a.m_rows ? a.m_rows - 1 : g);
+        xsrc[u] = in + g * a.ld_in + 16 * q;
+    }
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) {
+        const int wr = min(row0 + u * RS, WROWS - 1);
+        const int tap = wr / BN, nn = wr % BN;
+        const int n = n0 + nn < a.n ? n0 + nn : a.n - 1;
+        wsrc[u] = wt + (int64_t)n * kw + tap * a.cin + 16 * q;
+    }
+
     for (int c0 = 0; c0 < a.cin; c0 += KC) {
-        for (int idx = tid; idx < XV; idx += NT) {
-            const int row = idx / NCH, q = idx % NCH;
-            const int64_t g = m0 - RAD + row;
-            uint4 v = {0u, 0u, 0u, 0u};
-            if (g >= 0 && g < a.m_rows) v = *reinterpret_cast<const uint4*>(in + g * a.ld_in + c0 + 16 * q);
-            *reinterpret_cast<uint4*>(xs + row * KC + 16 * (q ^ swz32(row))) = v;
-        }
-        for (int idx = tid; idx < WV; idx += NT) {
-            const int q = idx % NCH, rest = idx / NCH;
-            const int tap = rest % TAPS, nn = rest / TAPS;
-            uint4 v = {0u, 0u, 0u, 0u};
-            if (n0 + nn < a.n)
-                v = *reinterpret_cast<const uint4*>(wt + (int64_t)(n0 + nn) * kw + tap * a.cin + c0 + 16 * q);
-            *reinterpret_cast<uint4*>(ws + rest * KC + 16 * (q ^ swz32(rest))) = v;
-        }
+        u32x4 xr[XPT], wr[WPT];
+#pragma unroll
+        for (int u = 0; u < XPT; ++u) xr[u] = *reinterpret_cast<const u32x4*>(xsrc[u] + c0);
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) wr[u] = *reinterpret_cast<const u32x4*>(wsrc[u] + c0);
+#pragma unroll
+        for (int u = 0; u < XPT; ++u)
+            if (x_has(u)) *reinterpret_cast<u32x4*>(xs + lds0 + u * RS * KC) = xr[u];
+#pragma unroll
+        for (int u = 0; u < WPT; ++u)
+            if (w_has(u)) *reinterpret_cast<u32x4*>(ws + lds0 + u * RS * KC) = wr[u];
         __syncthreads();
 #pragma unroll
         for (int tap = 0; tap < TAPS; ++tap) {
@@ -248,12 +267,12 @@ void conv_mfma_fp8(ConvArgs a)
                 av[i] = *reinterpret_cast<const long*>(xs + at32(wm * TMW * 16 + i * 16 + li + tap, lg));
 #pragma unroll
             for (int j = 0; j < TNW; ++j)
-                bv[j] = *reinterpret_cast<const long*>(ws + at32((wn * TNW * 16 + j * 16 + li) * TAPS + tap, lg));
+                bv[j] = *reinterpret_cast<const long*>(ws + at32(tap * BN + wn * TNW * 16 + j * 16 + li, lg));
 #pragma unroll
             for (int i = 0; i < TMW; ++i)
 #pragma unroll
                 for (int j = 0; j < TNW; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av[i], bv[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(bv[j], av[i], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }
@@ -317,25 +336,36 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_fp8_db(ConvArgs a)
 #pragma unroll
         for (int j = 0; j < TNW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // Wave-wide load j fills LDS rows 16 j .. 16 j + 15 of the stage (halo
+    // rows first, then the tap-major weight rows tap * BN + column); this
+    // wave issues j = wave + t * NW, from a per-lane source computed once.
+    constexpr int NJ = XI + WI, JT = (NJ + NW - 1) / NW;
     const int lrow = lane >> 2, lpos = lane & 3;
-    auto issue = [&](int buf, int c0) {
+    const uint8_t* src[JT];
+#pragma unroll
+    for (int t = 0; t < JT; ++t) {
+        const int j = min(wave + t * NW, NJ - 1);
+        const bool xj = j < XI;
+        const int row = 16 * (xj ? j : j - XI) + lrow;
+        const int c = lpos ^ swz64(row);
+        if (xj) {
+            int64_t gr = m0 - RAD + row;
+            gr = gr < 0 ? 0 : (gr >= a.m_rows ? a.m_rows - 1 : gr);
+            src[t] = in + gr * a.ld_in + 16 * c;
+        } else {
+            const int tap = row / BN, nn = row % BN;
+            const int n = n0 + nn < a.n ? n0 + nn : a.n - 1;
+            src[t] = wt + (int64_t)n * kw + tap * a.cin + 16 * c;
+        }
+    }
+    auto issue = [&](int buf, int c0) __attribute__((always_inline)) {
         uint8_t* base = smem + buf * STAGE;
-        for (int j = wave; j < XI + WI; j += NW) {
-            const bool xj = j < XI;
-            const int row = 16 * (xj ? j : j - XI) + lrow;
-            const int c = lpos ^ swz64(row);
-            const uint8_t* g;
-            if (xj) {
-                int64_t gr = m0 - RAD + row;
-                gr = gr < 0 ? 0 : (gr >= a.m_rows ? a.m_rows - 1 : gr);
-                g = in + gr * a.ld_in + c0 + 16 * c;
-            } else {
-                const int nn = row / TAPS, tap = row - nn * TAPS;
-                const int n = n0 + nn < a.n ? n0 + nn : a.n - 1;
-                g = wt + (int64_t)n * kw + tap * a.cin + c0 + 16 * c;
-            }
-            uint8_t* dst = base + (xj ? 16 * j * KB : XR * KB + 16 * (j - XI) * KB);
-            __builtin_amdgcn_global_load_lds((const void*)g, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+#pragma unroll
+        for (int t = 0; t < JT; ++t) {
+            const int j = wave + t * NW;
+            if ((t + 1) * NW <= NJ || j < NJ)
+                __builtin_amdgcn_global_load_lds((const void*)(src[t] + c0),
+                                                 (__attribute__((address_space(3))) void*)(base + 16 * j * KB), 16, 0, 0);
         }
     };
     // 8-byte piece lg of 32-channel chunk `sub` of row r: byte offset in the row
@@ -358,7 +388,7 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_fp8_db(ConvArgs a)
             }
 #pragma unroll
             for (int j = 0; j < TNW; ++j) {
-                const int r = (wn * TNW * 16 + j * 16 + li) * TAPS + tap;
+                const int r = tap * BN + wn * TNW * 16 + j * 16 + li;
                 bv[f][j] = *reinterpret_cast<const long*>(ws + r * KB + piece(r, sub, lg));
             }
         };
@@ -370,7 +400,7 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_fp8_db(ConvArgs a)
             for (int i = 0; i < TMW; ++i)
 #pragma unroll
                 for (int j = 0; j < TNW; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av[st & 1][i], bv[st & 1][j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(bv[st & 1][j], av[st & 1][i], acc[i][j], 0, 0, 0);
         }
     }
     __syncthreads();   // the epilogue reuses the stage buffers

@@ -8,9 +8,10 @@
 //     BN x 5 x 32 weight tile go to LDS once (unpadded, XOR-swizzled per
 //     16-byte chunk) and all five taps read them;
 //   * v_mfma_f32_16x16x32_{bf16,f16}: each lane feeds 8 consecutive
-//     channels of its row (A) and of its column (B) with one 16-byte LDS
-//     read; A and B use the same lane-to-k map, so the MFMA sums the whole
-//     32-channel step;
+//     channels of its weight column and of its position row with one 16-byte
+//     LDS read; both use the same lane-to-k map, so the MFMA sums the whole
+//     32-channel step.  The weights take the A slot (D^T = W X^T), which
+//     leaves four consecutive output channels of one position in each lane;
 //   * the k order (stage, tap, MFMA) is fixed by the kernel alone, so every
 //     tile-shape variant gives the same bits and results do not depend on
 //     the batch;
@@ -25,6 +26,7 @@ namespace pvf {
 namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
@@ -73,8 +75,10 @@ struct LpLds {
 };
 
 // Epilogue shared by the conv kernels (the LDS passed in is free: every
-// wave is past its last read of the stage buffers).  D layout of a 16x16
-// MFMA: lane holds rows 4*lg + v of column li.
+// wave is past its last read of the stage buffers).  The kernels issue the
+// MFMA as D^T = W X^T (weight fragment in the A slot), so lane (li, lg) of a
+// 16 x 16 tile holds channels 4 lg + v (v = 0..3) of tile row li: four
+// consecutive channels of one position, packed into one 8-byte LDS store.
 template <class T, int NT, int BM, int BN, int WM, int TMW, int TNW, int EPI>
 __device__ __forceinline__ void lp_epilogue(const f32x4 (&acc)[TMW][TNW], const ConvArgs& a, void* lds, int64_t m0,
                                             int n0, int tid)
@@ -84,29 +88,27 @@ __device__ __forceinline__ void lp_epilogue(const f32x4 (&acc)[TMW][TNW], const 
     const int li = lane & 15, lg = lane >> 4;
     const int rw = (wave % WM) * TMW * 16;
     const int cw = (wave / WM) * TNW * 16;
+    const RowMap rows(m0, a.r_in);
 
     if constexpr (EPI == EPI_HEAD) {
 #pragma unroll
         for (int i = 0; i < TMW; ++i) {
+            float s = 0.f;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                float s = 0.f;
+            for (int j = 0; j < TNW; ++j) {
+                const int c = n0 + cw + j * 16 + 4 * lg;
 #pragma unroll
-                for (int j = 0; j < TNW; ++j) {
-                    const int col = n0 + cw + j * 16 + li;
-                    s += lrelu(acc[i][j][v] + a.bias[col], a.slope) * a.head_w[col];
-                }
-                s += __shfl_xor(s, 8);
-                s += __shfl_xor(s, 4);
-                s += __shfl_xor(s, 2);
-                s += __shfl_xor(s, 1);
-                const int64_t r = m0 + rw + i * 16 + 4 * lg + v;
-                if (li == 0 && r < a.m_rows) {
-                    const int64_t e = r / a.r_in;
-                    const int loc = (int)(r - e * a.r_in);
-                    if (loc >= kGuard && loc < a.r_in - kGuard)
-                        a.prob[e * a.l_out + (loc - kGuard)] = 1.f / (1.f + expf(-(s + a.head_b)));
-                }
+                for (int v = 0; v < 4; ++v) s += lrelu(acc[i][j][v] + a.bias[c + v], a.slope) * a.head_w[c + v];
+            }
+            s += __shfl_xor(s, 16);
+            s += __shfl_xor(s, 32);
+            const int t = rw + i * 16 + li;
+            if (lg == 0 && m0 + t < a.m_rows) {
+                int64_t e;
+                int loc;
+                rows.at(t, e, loc);
+                if (loc >= kGuard && loc < a.r_in - kGuard)
+                    a.prob[e * a.l_out + (loc - kGuard)] = 1.f / (1.f + expf(-(s + a.head_b)));
             }
         }
         return;
@@ -114,17 +116,25 @@ __device__ __forceinline__ void lp_epilogue(const f32x4 (&acc)[TMW][TNW], const 
         T* ot = reinterpret_cast<T*>(lds);   // [BM][OP]
 #pragma unroll
         for (int j = 0; j < TNW; ++j) {
-            const int col = cw + j * 16 + li;
+            const int col = cw + j * 16 + 4 * lg;
             const int n = n0 + col;
-            const float b = n < a.n ? a.bias[EPI == EPI_CONVT ? n % a.cout : n] : 0.f;
+            float b[4];
 #pragma unroll
-            for (int i = 0; i < TMW; ++i)
+            for (int v = 0; v < 4; ++v) {
+                const int nv = min(n + v, a.n - 1);    // columns beyond n are never stored
+                b[v] = a.bias[EPI == EPI_CONVT ? nv % a.cout : nv];
+            }
+#pragma unroll
+            for (int i = 0; i < TMW; ++i) {
+                T y[4];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    float y = acc[i][j][v] + b;
-                    if (EPI != EPI_CONVT) y = lrelu(y, a.slope);
-                    ot[(rw + i * 16 + 4 * lg + v) * OP + col] = (T)y;
+                    float x = acc[i][j][v] + b[v];
+                    if (EPI != EPI_CONVT) x = lrelu(x, a.slope);
+                    y[v] = (T)x;
                 }
+                *reinterpret_cast<uint2*>(ot + (rw + i * 16 + li) * OP + col) = *reinterpret_cast<const uint2*>(y);
+            }
         }
         __syncthreads();
         T* out = static_cast<T*>(a.out);
@@ -132,10 +142,10 @@ __device__ __forceinline__ void lp_epilogue(const f32x4 (&acc)[TMW][TNW], const 
         const int n_valid = a.n - n0 < BN ? a.n - n0 : BN;
         for (int idx = tid; idx < BM * CH; idx += NT) {
             const int row = idx / CH, q = idx % CH;
-            const int64_t r = m0 + row;
-            if (8 * q >= n_valid || r >= a.m_rows) continue;
-            const int64_t e = r / a.r_in;
-            const int loc = (int)(r - e * a.r_in);
+            if (8 * q >= n_valid || m0 + row >= a.m_rows) continue;
+            int64_t e;
+            int loc;
+            rows.at(row, e, loc);
             if (loc < kGuard || loc >= a.r_in - kGuard) continue;
             const uint4 v = *reinterpret_cast<const uint4*>(ot + row * OP + 8 * q);
             if constexpr (EPI == EPI_CONVT) {
@@ -144,17 +154,17 @@ __device__ __forceinline__ void lp_epilogue(const f32x4 (&acc)[TMW][TNW], const 
                 const int64_t ro = e * a.r_out + kGuard + 2 * (loc - kGuard) + tj;
                 *reinterpret_cast<uint4*>(out + ro * a.ld_out + o) = v;
             } else {
-                *reinterpret_cast<uint4*>(out + r * a.ld_out + n0 + 8 * q) = v;
+                *reinterpret_cast<uint4*>(out + (m0 + row) * a.ld_out + n0 + 8 * q) = v;
             }
         }
         if constexpr (EPI == EPI_POOL) {
             T* pout = static_cast<T*>(a.pool_out);
             for (int idx = tid; idx < (BM / 2) * CH; idx += NT) {
                 const int pr = idx / CH, q = idx % CH;
-                const int64_t r = m0 + 2 * pr;       // even: first row of a pooling pair
-                if (8 * q >= n_valid || r >= a.m_rows) continue;
-                const int64_t e = r / a.r_in;
-                const int loc = (int)(r - e * a.r_in);
+                if (8 * q >= n_valid || m0 + 2 * pr >= a.m_rows) continue;   // even: first row of a pooling pair
+                int64_t e;
+                int loc;
+                rows.at(2 * pr, e, loc);
                 if (loc < kGuard || loc >= a.r_in - kGuard) continue;
                 const uint4 r0 = *reinterpret_cast<const uint4*>(ot + (2 * pr) * OP + 8 * q);
                 const uint4 r1 = *reinterpret_cast<const uint4*>(ot + (2 * pr + 1) * OP + 8 * q);
@@ -225,68 +235,50 @@ void conv_mfma_lp(ConvArgs a)
 #pragma unroll
         for (int j = 0; j < TNW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    uint4 xr[PF ? XPT : 1], wr[PF ? WPT : 1];
-    auto fetch = [&](int c0) {
-#pragma unroll
-        for (int u = 0; u < XPT; ++u) {
-            const int idx = tid + u * NT;
-            xr[u] = uint4{0u, 0u, 0u, 0u};
-            if (idx < XV) {
-                const int row = idx / NCH, q = idx % NCH;
-                const int64_t g = m0 - RAD + row;
-                if (g >= 0 && g < a.m_rows) xr[u] = *reinterpret_cast<const uint4*>(in + g * a.ld_in + c0 + 8 * q);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < WPT; ++u) {
-            const int idx = tid + u * NT;
-            wr[u] = uint4{0u, 0u, 0u, 0u};
-            if (idx < WV) {
-                const int q = idx % NCH, rest = idx / NCH;
-                const int tap = rest % TAPS, nn = rest / TAPS;
-                if (n0 + nn < a.n)
-                    wr[u] = *reinterpret_cast<const uint4*>(wt + (int64_t)(n0 + nn) * kw + tap * a.cin + c0 + 8 * q);
-            }
-        }
+    // Staging: thread tid owns chunk q = tid % NCH of LDS rows tid / NCH + u * RS
+    // (RS = NT / NCH), in the halo tile and in the weight tile alike.  Weight
+    // rows are tap-major (row = tap * BN + column), so the chunk of stage c0
+    // sits at a fixed offset from a per-thread base and the address math is
+    // one add per chunk.  Halo rows outside the batch and columns beyond n are
+    // clamped to valid ones: they only feed outputs the epilogue discards.
+    constexpr int RS = NT / NCH;
+    constexpr int WROWS = TAPS * BN;
+    static_assert(RS % 8 == 0, "chunk rows of one thread share their swizzle");
+    const int q = tid % NCH, row0 = tid / NCH;
+    const int lds0 = lds_at<NCH>(row0, q);       // + u * RS * KC for chunk u
+    // chunk u exists for this thread (a compile-time true for all but the last)
+    auto x_has = [&](int u) __attribute__((always_inline)) { return (u + 1) * RS <= XROWS || row0 + u * RS < XROWS; };
+    auto w_has = [&](int u) __attribute__((always_inline)) { return (u + 1) * RS <= WROWS || row0 + u * RS < WROWS; };
+    auto x_src = [&](int u) __attribute__((always_inline)) {
+        const int row = (u + 1) * RS <= XROWS ? row0 + u * RS : min(row0 + u * RS, XROWS - 1);
+        int64_t g = m0 - RAD + row;
+        g = g < 0 ? 0 : (g >= a.m_rows ? a.m_rows - 1 : g);
+        return in + g * a.ld_in + 8 * q;
     };
-    auto stage = [&]() {
-#pragma unroll
-        for (int u = 0; u < XPT; ++u) {
-            const int idx = tid + u * NT;
-            if (idx < XV) *reinterpret_cast<uint4*>(xs + lds_at<NCH>(idx / NCH, idx % NCH)) = xr[u];
-        }
-#pragma unroll
-        for (int u = 0; u < WPT; ++u) {
-            const int idx = tid + u * NT;
-            if (idx < WV) *reinterpret_cast<uint4*>(ws + lds_at<NCH>(idx / NCH, idx % NCH)) = wr[u];
-        }
+    auto w_src = [&](int u) __attribute__((always_inline)) {
+        const int wr = (u + 1) * RS <= WROWS ? row0 + u * RS : min(row0 + u * RS, WROWS - 1);
+        const int tap = wr / BN, nn = wr % BN;
+        const int n = n0 + nn < a.n ? n0 + nn : a.n - 1;
+        return wt + (int64_t)n * kw + tap * a.cin + 8 * q;
     };
-
-    // PF = 0: load and store each chunk in turn (fewest live registers)
-    auto copy_direct = [&](int c0) {
-        for (int idx = tid; idx < XV; idx += NT) {
-            const int row = idx / NCH, q = idx % NCH;
-            const int64_t g = m0 - RAD + row;
-            uint4 v = {0u, 0u, 0u, 0u};
-            if (g >= 0 && g < a.m_rows) v = *reinterpret_cast<const uint4*>(in + g * a.ld_in + c0 + 8 * q);
-            *reinterpret_cast<uint4*>(xs + lds_at<NCH>(row, q)) = v;
-        }
-        for (int idx = tid; idx < WV; idx += NT) {
-            const int q = idx % NCH, rest = idx / NCH;
-            const int tap = rest % TAPS, nn = rest / TAPS;
-            uint4 v = {0u, 0u, 0u, 0u};
-            if (n0 + nn < a.n)
-                v = *reinterpret_cast<const uint4*>(wt + (int64_t)(n0 + nn) * kw + tap * a.cin + c0 + 8 * q);
-            *reinterpret_cast<uint4*>(ws + lds_at<NCH>(rest, q)) = v;
-        }
+    u32x4 xr[XPT], wr[WPT];
+    auto fetch = [&](int c0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < XPT; ++u) xr[u] = *reinterpret_cast<const u32x4*>(x_src(u) + c0);
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) wr[u] = *reinterpret_cast<const u32x4*>(w_src(u) + c0);
+    };
+    auto stage = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < XPT; ++u)
+            if (x_has(u)) *reinterpret_cast<u32x4*>(xs + lds0 + u * RS * KC) = xr[u];
+#pragma unroll
+        for (int u = 0; u < WPT; ++u)
+            if (w_has(u)) *reinterpret_cast<u32x4*>(ws + lds0 + u * RS * KC) = wr[u];
     };
 
-    if constexpr (PF) {
-        fetch(0);
-        stage();
-    } else {
-        copy_direct(0);
-    }
+    fetch(0);
+    stage();
     __syncthreads();
     for (int c0 = 0; c0 < a.cin; c0 += KC) {
         const bool more = c0 + KC < a.cin;
@@ -303,17 +295,17 @@ void conv_mfma_lp(ConvArgs a)
                     av[i] = *reinterpret_cast<const V*>(xs + lds_at<NCH>(wm * TMW * 16 + i * 16 + li + tap, 4 * sub + lg));
 #pragma unroll
                 for (int j = 0; j < TNW; ++j)
-                    bv[j] = *reinterpret_cast<const V*>(ws + lds_at<NCH>((wn * TNW * 16 + j * 16 + li) * TAPS + tap, 4 * sub + lg));
+                    bv[j] = *reinterpret_cast<const V*>(ws + lds_at<NCH>(tap * BN + wn * TNW * 16 + j * 16 + li, 4 * sub + lg));
 #pragma unroll
                 for (int i = 0; i < TMW; ++i)
 #pragma unroll
-                    for (int j = 0; j < TNW; ++j) acc[i][j] = Lp<T>::mfma(av[i], bv[j], acc[i][j]);
+                    for (int j = 0; j < TNW; ++j) acc[i][j] = Lp<T>::mfma(bv[j], av[i], acc[i][j]);
             }
         }
         __syncthreads();
         if (more) {
-            if constexpr (PF) stage();
-            else copy_direct(c0 + KC);
+            if constexpr (!PF) fetch(c0 + KC);   // all loads in flight before the first store
+            stage();
             __syncthreads();
         }
     }
@@ -378,25 +370,37 @@ void conv_mfma_lp_db(ConvArgs a)
 #pragma unroll
         for (int j = 0; j < TNW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // Wave-wide load j fills LDS rows 16 j .. 16 j + 15 of the stage (halo
+    // rows first, then the tap-major weight rows tap * BN + column); this
+    // wave issues j = wave + t * NW.  Each lane's source is fixed apart from
+    // the stage's channel offset, so it is computed once.
+    constexpr int NJ = XI + WI, JT = (NJ + NW - 1) / NW;
     const int lrow = lane >> 2, lpos = lane & 3;
-    auto issue = [&](int buf, int c0) {
+    const T* src[JT];
+#pragma unroll
+    for (int t = 0; t < JT; ++t) {
+        const int j = min(wave + t * NW, NJ - 1);
+        const bool xj = j < XI;
+        const int row = 16 * (xj ? j : j - XI) + lrow;       // row inside its region
+        const int c = lpos ^ swz<NCH>(row);                   // chunk held by this slot
+        if (xj) {
+            int64_t gr = m0 - RAD + row;
+            gr = gr < 0 ? 0 : (gr >= a.m_rows ? a.m_rows - 1 : gr);
+            src[t] = in + gr * a.ld_in + 8 * c;
+        } else {
+            const int tap = row / BN, nn = row % BN;
+            const int n = n0 + nn < a.n ? n0 + nn : a.n - 1;
+            src[t] = wt + (int64_t)n * kw + tap * a.cin + 8 * c;
+        }
+    }
+    auto issue = [&](int buf, int c0) __attribute__((always_inline)) {
         char* base = smem + buf * STAGE;
-        for (int j = wave; j < XI + WI; j += NW) {
-            const bool xj = j < XI;
-            const int row = 16 * (xj ? j : j - XI) + lrow;      // row inside its region
-            const int c = lpos ^ swz<NCH>(row);                 // chunk held by this slot
-            const T* g;
-            if (xj) {
-                int64_t gr = m0 - RAD + row;
-                gr = gr < 0 ? 0 : (gr >= a.m_rows ? a.m_rows - 1 : gr);
-                g = in + gr * a.ld_in + c0 + 8 * c;
-            } else {
-                const int nn = row / TAPS, tap = row - nn * TAPS;
-                const int n = n0 + nn < a.n ? n0 + nn : a.n - 1;
-                g = wt + (int64_t)n * kw + tap * a.cin + c0 + 8 * c;
-            }
-            char* dst = base + (xj ? 16 * j * ROWB : XR * ROWB + 16 * (j - XI) * ROWB);
-            __builtin_amdgcn_global_load_lds((const void*)g, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+#pragma unroll
+        for (int t = 0; t < JT; ++t) {
+            const int j = wave + t * NW;
+            if ((t + 1) * NW <= NJ || j < NJ)
+                __builtin_amdgcn_global_load_lds((const void*)(src[t] + c0),
+                                                 (__attribute__((address_space(3))) void*)(base + 16 * j * ROWB), 16, 0, 0);
         }
     };
 
@@ -418,7 +422,7 @@ void conv_mfma_lp_db(ConvArgs a)
                 av[f][i] = *reinterpret_cast<const V*>(xs + lds_at<NCH>(wm * TMW * 16 + i * 16 + li + tap, lg));
 #pragma unroll
             for (int j = 0; j < TNW; ++j)
-                bv[f][j] = *reinterpret_cast<const V*>(ws + lds_at<NCH>((wn * TNW * 16 + j * 16 + li) * TAPS + tap, lg));
+                bv[f][j] = *reinterpret_cast<const V*>(ws + lds_at<NCH>(tap * BN + wn * TNW * 16 + j * 16 + li, lg));
         };
         frag(0, 0);
 #pragma unroll
@@ -427,7 +431,7 @@ void conv_mfma_lp_db(ConvArgs a)
 #pragma unroll
             for (int i = 0; i < TMW; ++i)
 #pragma unroll
-                for (int j = 0; j < TNW; ++j) acc[i][j] = Lp<T>::mfma(av[tap & 1][i], bv[tap & 1][j], acc[i][j]);
+                for (int j = 0; j < TNW; ++j) acc[i][j] = Lp<T>::mfma(bv[tap & 1][j], av[tap & 1][i], acc[i][j]);
         }
     }
     __syncthreads();   // the epilogue reuses the stage buffers
@@ -551,16 +555,21 @@ bool lp_variant_ok(int v, int n, int cin, int taps, Epi epi)
     return bn <= (n < 32 ? 32 : n);
 }
 
-// Defaults from BF16 sweeps on MI355X at 1000 events: the double-buffered
-// stages win where a layer has few channels (short K, little reuse), the
-// 256 x 128 single-buffered tile with two blocks per CU on the wide layers.
+// Defaults from the autotuner's BF16 picks on MI355X at 1000 events (widths
+// 32 and 64, event and interval layouts).  The small-channel layers take the
+// 128-row or 64-channel-stage tiles, the wide ones the 256 x 128
+// single-buffered tile (two blocks per CU), and the 1x1 transposed convs the
+// double-buffered 128 x 128 tile.
 int lp_default_variant(int n, int cin, int taps, Epi epi)
 {
-    if (epi == EPI_HEAD) return n == 64 ? 1 : 0;
-    if (epi == EPI_CONVT && taps == 1) return n >= 128 ? 6 : 4;
-    (void)cin;
-    if (n <= 32) return epi == EPI_POOL ? 0 : 14;
-    if (n <= 64) return 13;
+    if (epi == EPI_HEAD) return n == 64 ? 1 : 5;
+    if (epi == EPI_CONVT && taps == 1) return n >= 512 ? 17 : (n >= 128 ? 15 : (cin % 64 == 0 ? 8 : 4));
+    if (n <= 32) return epi == EPI_POOL ? 5 : (cin % 64 == 0 ? 8 : 14);
+    if (n <= 64) {
+        if (epi == EPI_POOL) return 4;
+        if (cin <= 32) return 1;
+        return cin >= 128 ? 13 : (cin % 64 == 0 ? 8 : 13);
+    }
     return 3;
 }
 

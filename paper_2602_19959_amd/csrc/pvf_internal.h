@@ -72,6 +72,32 @@ struct WeightLayout {
 
 enum Epi { EPI_STORE = 0, EPI_POOL = 1, EPI_CONVT = 2, EPI_HEAD = 3 };
 
+// Row m0 + t of a channels-last batch with R rows per event -> (event, row
+// within the event), for the rows of one output tile (t < 2^20).  The tile's
+// first event is found once; the rest is a 32-bit divide by R done with a
+// float estimate (off by at most one for quotients below 2^23) and one
+// correction, instead of a 64-bit integer division per row.
+struct RowMap {
+    int64_t e0;
+    int loc0, R;
+    float inv;
+    __device__ RowMap(int64_t m0, int rows_per_event)
+        : e0(m0 / rows_per_event), loc0((int)(m0 - m0 / rows_per_event * rows_per_event)), R(rows_per_event),
+          inv(1.f / (float)rows_per_event)
+    {
+    }
+    __device__ __forceinline__ void at(int t, int64_t& e, int& loc) const
+    {
+        const int x = loc0 + t;
+        int q = (int)((float)x * inv);
+        int rem = x - q * R;
+        if (rem >= R) { rem -= R; ++q; }
+        else if (rem < 0) { rem += R; --q; }
+        e = e0 + q;
+        loc = rem;
+    }
+};
+
 struct ConvArgs {
     const void* in;      // input rows, channels-last (element type = compute dtype)
     int ld_in;           // floats per input row
