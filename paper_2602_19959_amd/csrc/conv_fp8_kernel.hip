@@ -487,7 +487,7 @@ bool fp8_variant_ok(int v, int n, int cin, int taps, Epi epi)
 int fp8_default_variant(int n, int cin, int taps, Epi epi)
 {
     if (epi == EPI_HEAD) return n == 64 ? 1 : 0;
-    if (epi == EPI_CONVT && taps == 1) return n >= 256 ? 2 : (n >= 128 ? 4 : 6);
+    if (epi == EPI_CONVT && taps == 1) return n >= 128 ? 4 : 6;
     if (n <= 32) return 0;
     if (cin >= 128) return 5;
     return 1;

@@ -55,17 +55,19 @@ constexpr int occupancy_target(int lds_bytes, int waves_per_block)
     return w < 1 ? 1 : (w > 4 ? 4 : w);
 }
 
-// Epilogue shared by the FP32 kernels, straight from the accumulators.
-// Output D layout of the 16x16 MFMA: lane holds rows 4*lg + v (v = 0..3) of
-// column li.
+// Epilogue shared by the FP32 kernels, straight from the accumulators.  The
+// kernels issue the MFMA as D^T = W X^T (weight fragment in the A slot), so
+// lane (li, lg) of a 16 x 16 tile holds channels 4 lg + v (v = 0..3) of tile
+// row li: four consecutive outputs of one position, one 16-byte store.
 template <int WM, int TMW, int TNW, int EPI>
 __device__ __forceinline__ void f32_epilogue(const f32x4 (&acc)[TMW][TNW], const ConvArgs& a, int64_t m0, int n0,
                                              int tid)
 {
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
-    const int64_t rbase = m0 + (wave % WM) * TMW * 16;
-    const int cbase = n0 + (wave / WM) * TNW * 16;
+    const int rw = (wave % WM) * TMW * 16;
+    const int cbase = n0 + (wave / WM) * TNW * 16 + 4 * lg;   // this lane's first channel of tile j = 0
+    const RowMap rows(m0, a.r_in);
     float* out = static_cast<float*>(a.out);
     float* pout = static_cast<float*>(a.pool_out);
 
@@ -73,81 +75,63 @@ __device__ __forceinline__ void f32_epilogue(const f32x4 (&acc)[TMW][TNW], const
         // the block holds every channel of its rows (BN == n, one wave in N)
 #pragma unroll
         for (int i = 0; i < TMW; ++i) {
+            float s = 0.f;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                float s = 0.f;
+            for (int j = 0; j < TNW; ++j) {
+                const int c = cbase + j * 16;
 #pragma unroll
-                for (int j = 0; j < TNW; ++j) {
-                    const int col = cbase + j * 16 + li;
-                    s += lrelu(acc[i][j][v] + a.bias[col], a.slope) * a.head_w[col];
-                }
-                s += __shfl_xor(s, 8);
-                s += __shfl_xor(s, 4);
-                s += __shfl_xor(s, 2);
-                s += __shfl_xor(s, 1);
-                const int64_t r = rbase + i * 16 + 4 * lg + v;
-                if (li == 0 && r < a.m_rows) {
-                    const int64_t e = r / a.r_in;
-                    const int loc = (int)(r - e * a.r_in);
-                    if (loc >= kGuard && loc < a.r_in - kGuard) {
-                        const float logit = s + a.head_b;
-                        a.prob[e * a.l_out + (loc - kGuard)] = 1.f / (1.f + expf(-logit));
-                    }
-                }
+                for (int v = 0; v < 4; ++v) s += lrelu(acc[i][j][v] + a.bias[c + v], a.slope) * a.head_w[c + v];
+            }
+            s += __shfl_xor(s, 16);
+            s += __shfl_xor(s, 32);
+            const int t = rw + i * 16 + li;
+            if (lg == 0 && m0 + t < a.m_rows) {
+                int64_t e;
+                int loc;
+                rows.at(t, e, loc);
+                if (loc >= kGuard && loc < a.r_in - kGuard)
+                    a.prob[e * a.l_out + (loc - kGuard)] = 1.f / (1.f + expf(-(s + a.head_b)));
             }
         }
         return;
     }
 
 #pragma unroll
-    for (int j = 0; j < TNW; ++j) {
-        const int col = cbase + j * 16 + li;
-        if (col >= a.n) continue;
-        if constexpr (EPI == EPI_CONVT) {
-            const int tj = col / a.cout;           // which of the two output rows
-            const int o = col - tj * a.cout;
-            const float b = a.bias[o];
+    for (int i = 0; i < TMW; ++i) {
+        const int t = rw + i * 16 + li;
+        int64_t e;
+        int loc;
+        rows.at(t, e, loc);
+        const bool ok = m0 + t < a.m_rows && loc >= kGuard && loc < a.r_in - kGuard;
 #pragma unroll
-            for (int i = 0; i < TMW; ++i)
+        for (int j = 0; j < TNW; ++j) {
+            const int c = cbase + j * 16;
+            const bool col_ok = c < a.n;            // n % 4 == 0: a lane's four channels are all in or all out
+            const int cc = col_ok ? c : 0;
+            if constexpr (EPI == EPI_CONVT) {
+                const int tj = cc / a.cout;          // which of the two output rows
+                const int o = cc - tj * a.cout;
+                f32x4 y;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int64_t r = rbase + i * 16 + 4 * lg + v;
-                    if (r >= a.m_rows) continue;
-                    const int64_t e = r / a.r_in;
-                    const int loc = (int)(r - e * a.r_in);
-                    if (loc < kGuard || loc >= a.r_in - kGuard) continue;
+                for (int v = 0; v < 4; ++v) y[v] = acc[i][j][v] + a.bias[o + v];
+                if (ok && col_ok) {
                     const int64_t ro = e * a.r_out + kGuard + 2 * (loc - kGuard) + tj;
-                    out[ro * a.ld_out + o] = acc[i][j][v] + b;
+                    *reinterpret_cast<f32x4*>(out + ro * a.ld_out + o) = y;
                 }
-        } else {
-            const float b = a.bias[col];
+            } else {
+                f32x4 y;
 #pragma unroll
-            for (int i = 0; i < TMW; ++i) {
-                float y[4];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) y[v] = lrelu(acc[i][j][v] + b, a.slope);
-                const int64_t r0 = rbase + i * 16 + 4 * lg;   // multiple of 4
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int64_t r = r0 + v;
-                    if (r >= a.m_rows) continue;
-                    const int64_t e = r / a.r_in;
-                    const int loc = (int)(r - e * a.r_in);
-                    if (loc < kGuard || loc >= a.r_in - kGuard) continue;
-                    out[r * a.ld_out + col] = y[v];
-                }
+                for (int v = 0; v < 4; ++v) y[v] = lrelu(acc[i][j][v] + a.bias[cc + v], a.slope);
+                if (ok && col_ok) *reinterpret_cast<f32x4*>(out + (m0 + t) * a.ld_out + c) = y;
                 if constexpr (EPI == EPI_POOL) {
                     // rows per event and the guard are even, so an even row is
-                    // the first of a pooling pair
+                    // the first of a pooling pair; its partner is lane li ^ 1
+                    f32x4 p;
 #pragma unroll
-                    for (int p = 0; p < 2; ++p) {
-                        const int64_t r = r0 + 2 * p;
-                        if (r >= a.m_rows) continue;
-                        const int64_t e = r / a.r_in;
-                        const int loc = (int)(r - e * a.r_in);
-                        if (loc < kGuard || loc >= a.r_in - kGuard) continue;
+                    for (int v = 0; v < 4; ++v) p[v] = fmaxf(y[v], __shfl_xor(y[v], 1));
+                    if (ok && col_ok && (li & 1) == 0) {
                         const int64_t rp = e * a.r_pool + kGuard + (loc - kGuard) / 2;
-                        pout[rp * a.ld_pool + col] = fmaxf(y[2 * p], y[2 * p + 1]);
+                        *reinterpret_cast<f32x4*>(pout + rp * a.ld_pool + c) = p;
                     }
                 }
             }
@@ -213,51 +197,49 @@ void conv_mfma_f32(ConvArgs a)
 
     // PF = 1: software pipeline, the next chunk's tiles are fetched into
     // registers while the current chunk's MFMAs run from LDS.  PF = 0: fetch,
-    // stage and compute in turn (fewer registers, more blocks per CU).
+    // stage and compute in turn (fewer registers, more blocks per CU), every
+    // load of a stage in flight before the first LDS store.
+    // Thread tid owns chunk q = tid % 4 of LDS rows tid / 4 + u * RS in the halo
+    // tile and in the tap-major weight tile (row = tap * BN + column); its
+    // sources are fixed apart from the stage's channel offset.  Halo rows
+    // outside the batch and columns beyond n are clamped to valid ones: they
+    // only feed outputs the epilogue discards.
+    constexpr int RS = NT / 4;
+    constexpr int WROWS = TAPS * BN;
+    static_assert(RS % 16 == 0, "chunk rows of one thread share their swizzle");
+    const int q = tid % 4, row0 = tid / 4;
+    const int lds0 = lds_at(row0, q);             // + u * RS * KC for chunk u
+    auto x_has = [&](int u) __attribute__((always_inline)) { return (u + 1) * RS <= XROWS || row0 + u * RS < XROWS; };
+    auto w_has = [&](int u) __attribute__((always_inline)) { return (u + 1) * RS <= WROWS || row0 + u * RS < WROWS; };
+    const float* xsrc[XPT];
+    const float* wsrc[WPT];
+#pragma unroll
+    for (int u = 0; u < XPT; ++u) {
+        int64_t g = m0 - RAD + min(row0 + u * RS, XROWS - 1);
+        g = g < 0 ? 0 : (g >= a.m_rows ? a.m_rows - 1 : g);
+        xsrc[u] = in + g * a.ld_in + 4 * q;
+    }
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) {
+        const int wr = min(row0 + u * RS, WROWS - 1);
+        const int tap = wr / BN, nn = wr % BN;
+        const int n = n0 + nn < a.n ? n0 + nn : a.n - 1;
+        wsrc[u] = wt + (int64_t)n * kw + tap * a.cin + 4 * q;
+    }
     f32x4 xr[XPT], wr[WPT];
-    auto fetch = [&](int c0) {
+    auto fetch = [&](int c0) __attribute__((always_inline)) {
 #pragma unroll
-        for (int u = 0; u < XPT; ++u) {
-            const int idx = tid + u * NT;
-            xr[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-            if (idx < XV) {
-                const int row = idx / (KC / 4), q = idx % (KC / 4);
-                const int64_t g = m0 - RAD + row;
-                if (g >= 0 && g < a.m_rows)
-                    xr[u] = *reinterpret_cast<const f32x4*>(in + g * a.ld_in + c0 + 4 * q);
-            }
-        }
+        for (int u = 0; u < XPT; ++u) xr[u] = *reinterpret_cast<const f32x4*>(xsrc[u] + c0);
 #pragma unroll
-        for (int u = 0; u < WPT; ++u) {
-            const int idx = tid + u * NT;
-            wr[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-            if (idx < WV) {
-                const int q = idx % (KC / 4);
-                const int rest = idx / (KC / 4);
-                const int tap = rest % TAPS, nn = rest / TAPS;
-                if (n0 + nn < a.n)
-                    wr[u] = *reinterpret_cast<const f32x4*>(wt + (int64_t)(n0 + nn) * kw + tap * a.cin + c0 + 4 * q);
-            }
-        }
+        for (int u = 0; u < WPT; ++u) wr[u] = *reinterpret_cast<const f32x4*>(wsrc[u] + c0);
     };
-    auto stage = [&]() {
+    auto stage = [&]() __attribute__((always_inline)) {
 #pragma unroll
-        for (int u = 0; u < XPT; ++u) {
-            const int idx = tid + u * NT;
-            if (idx < XV) {
-                const int row = idx / (KC / 4), q = idx % (KC / 4);
-                *reinterpret_cast<f32x4*>(xs + lds_at(row, q)) = xr[u];
-            }
-        }
+        for (int u = 0; u < XPT; ++u)
+            if (x_has(u)) *reinterpret_cast<f32x4*>(xs + lds0 + u * RS * KC) = xr[u];
 #pragma unroll
-        for (int u = 0; u < WPT; ++u) {
-            const int idx = tid + u * NT;
-            if (idx < WV) {
-                const int q = idx % (KC / 4);
-                const int rest = idx / (KC / 4);
-                *reinterpret_cast<f32x4*>(ws + lds_at(rest, q)) = wr[u];
-            }
-        }
+        for (int u = 0; u < WPT; ++u)
+            if (w_has(u)) *reinterpret_cast<f32x4*>(ws + lds0 + u * RS * KC) = wr[u];
     };
 
     fetch(0);
@@ -274,14 +256,14 @@ void conv_mfma_f32(ConvArgs a)
                 av[i] = *reinterpret_cast<const f32x4*>(xs + lds_at(wm * TMW * 16 + i * 16 + li + tap, lg));
 #pragma unroll
             for (int j = 0; j < TNW; ++j)
-                bv[j] = *reinterpret_cast<const f32x4*>(ws + lds_at((wn * TNW * 16 + j * 16 + li) * TAPS + tap, lg));
+                bv[j] = *reinterpret_cast<const f32x4*>(ws + lds_at(tap * BN + wn * TNW * 16 + j * 16 + li, lg));
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
                 for (int i = 0; i < TMW; ++i)
 #pragma unroll
                     for (int j = 0; j < TNW; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][s], bv[j][s], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[j][s], av[i][s], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
         if (more) {
@@ -341,25 +323,36 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32_db(ConvArgs a)
 #pragma unroll
         for (int j = 0; j < TNW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // Wave-wide load j fills LDS rows 16 j .. 16 j + 15 of the stage (halo
+    // rows first, then the tap-major weight rows tap * BN + column); this
+    // wave issues j = wave + t * NW, from a per-lane source computed once.
+    constexpr int NJ = XI + WI, JT = (NJ + NW - 1) / NW;
     const int lrow = lane >> 2, lpos = lane & 3;
-    auto issue = [&](int buf, int c0) {
+    const float* src[JT];
+#pragma unroll
+    for (int t = 0; t < JT; ++t) {
+        const int j = min(wave + t * NW, NJ - 1);
+        const bool xj = j < XI;
+        const int row = 16 * (xj ? j : j - XI) + lrow;
+        const int c = lpos ^ swz(row);
+        if (xj) {
+            int64_t gr = m0 - RAD + row;
+            gr = gr < 0 ? 0 : (gr >= a.m_rows ? a.m_rows - 1 : gr);
+            src[t] = in + gr * a.ld_in + 4 * c;
+        } else {
+            const int tap = row / BN, nn = row % BN;
+            const int n = n0 + nn < a.n ? n0 + nn : a.n - 1;
+            src[t] = wt + (int64_t)n * kw + tap * a.cin + 4 * c;
+        }
+    }
+    auto issue = [&](int buf, int c0) __attribute__((always_inline)) {
         float* base = smem + buf * STAGE;
-        for (int j = wave; j < XI + WI; j += NW) {
-            const bool xj = j < XI;
-            const int row = 16 * (xj ? j : j - XI) + lrow;
-            const int c = lpos ^ swz(row);
-            const float* g;
-            if (xj) {
-                int64_t gr = m0 - RAD + row;
-                gr = gr < 0 ? 0 : (gr >= a.m_rows ? a.m_rows - 1 : gr);
-                g = in + gr * a.ld_in + c0 + 4 * c;
-            } else {
-                const int nn = row / TAPS, tap = row - nn * TAPS;
-                const int n = n0 + nn < a.n ? n0 + nn : a.n - 1;
-                g = wt + (int64_t)n * kw + tap * a.cin + c0 + 4 * c;
-            }
-            float* dst = base + (xj ? 16 * j * KC : XR * KC + 16 * (j - XI) * KC);
-            __builtin_amdgcn_global_load_lds((const void*)g, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+#pragma unroll
+        for (int t = 0; t < JT; ++t) {
+            const int j = wave + t * NW;
+            if ((t + 1) * NW <= NJ || j < NJ)
+                __builtin_amdgcn_global_load_lds((const void*)(src[t] + c0),
+                                                 (__attribute__((address_space(3))) void*)(base + 16 * j * KC), 16, 0, 0);
         }
     };
     (void)ROWB;
@@ -379,7 +372,7 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32_db(ConvArgs a)
                 av[f][i] = *reinterpret_cast<const f32x4*>(xs + lds_at(wm * TMW * 16 + i * 16 + li + tap, lg));
 #pragma unroll
             for (int j = 0; j < TNW; ++j)
-                bv[f][j] = *reinterpret_cast<const f32x4*>(ws + lds_at((wn * TNW * 16 + j * 16 + li) * TAPS + tap, lg));
+                bv[f][j] = *reinterpret_cast<const f32x4*>(ws + lds_at(tap * BN + wn * TNW * 16 + j * 16 + li, lg));
         };
         frag(0, 0);
 #pragma unroll
@@ -391,7 +384,7 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_f32_db(ConvArgs a)
                 for (int i = 0; i < TMW; ++i)
 #pragma unroll
                     for (int j = 0; j < TNW; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[tap & 1][i][s], bv[tap & 1][j][s], acc[i][j],
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tap & 1][j][s], av[tap & 1][i][s], acc[i][j],
                                                                           0, 0, 0);
         }
     }
