@@ -103,24 +103,24 @@ __device__ __forceinline__ void fp8_epilogue(const f32x4 (&acc)[TMW][TNW], const
 #pragma unroll
         for (int j = 0; j < TNW; ++j) {
             const int col = cw + j * 16 + 4 * lg;
-            float cs[4], b[4], inv[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int n = min(n0 + col + v, a.n - 1);   // columns beyond n are never stored
-                const int oc = EPI == EPI_CONVT ? n % a.cout : n;
-                cs[v] = a.col_scale[n];
-                b[v] = a.bias[oc];
-                inv[v] = a.out_inv_scale[oc];
-            }
+            // y / a_out = LeakyReLU(acc * s_n / a_out + b / a_out): one FMA per
+            // value with the folded per-column factors (n % 16 == 0, so a
+            // lane's four columns are all valid or all past n)
+            const int nc = min(n0 + col, a.n - 4);
+            const f32x4 fs = *reinterpret_cast<const f32x4*>(a.fold_scale + nc);
+            const f32x4 fb = *reinterpret_cast<const f32x4*>(a.fold_bias + nc);
 #pragma unroll
             for (int i = 0; i < TMW; ++i) {
-                uint32_t w = 0;
+                float y[4];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    float y = acc[i][j][v] * cs[v] + b[v];
-                    if (EPI != EPI_CONVT) y = lrelu(y, a.slope);
-                    w |= (uint32_t)to_e4m3(y * inv[v]) << (8 * v);
+                    float x = fmaf(acc[i][j][v], fs[v], fb[v]);
+                    if (EPI != EPI_CONVT) x = lrelu(x, a.slope);
+                    y[v] = fminf(fmaxf(x, -448.f), 448.f);   // saturate (the conversion maps overflow to NaN)
                 }
+                // two packed conversions: channel 4 lg + v goes to byte v
+                uint32_t w = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(y[0], y[1], 0, false);
+                w = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(y[2], y[3], (int)w, true);
                 *reinterpret_cast<uint32_t*>(ot + (rw + i * 16 + li) * OP + col) = w;
             }
         }
@@ -505,7 +505,7 @@ hipError_t launch_conv_fp8(const ConvArgs& a, int taps, Epi epi, int v, hipStrea
 {
     if (a.cin % KC != 0 || a.m_rows <= 0 || !fp8_variant_ok(v, a.n, a.cin, taps, epi) || !a.col_scale)
         return hipErrorInvalidValue;
-    if (epi != EPI_HEAD && !a.out_inv_scale) return hipErrorInvalidValue;
+    if (epi != EPI_HEAD && (!a.fold_scale || !a.fold_bias || a.n % 16 != 0)) return hipErrorInvalidValue;
     if (epi == EPI_CONVT && a.cout % 16 != 0) return hipErrorInvalidValue;
     if (taps == 5) {
         switch (epi) {

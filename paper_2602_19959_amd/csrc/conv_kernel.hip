@@ -38,8 +38,9 @@ constexpr int KC = 16;         // input channels per LDS stage = 4 chunks of 16 
 // is stored at position q ^ swz(r), swz(r) = 2 * bit 3 of r.  Read-pattern
 // probes on gfx950 show that bits 1..2 of r would make every fragment read
 // conflict-free (with this one only the halo reads of tap 0 are), yet the
-// dominant FP32 layer ran 6% slower with it in repeated A/B runs (same
-// instruction stream apart from the address arithmetic; cause not pinned down).
+// dominant FP32 layer ran slower with it in repeated A/B runs: 6% with the
+// weight rows in (column, tap) order, under 1% with the tap-major rows used
+// now (cause not pinned down).
 __device__ __forceinline__ int swz(int r) { return (r >> 2) & 2; }
 __device__ __forceinline__ int lds_at(int r, int q) { return (r * 4 + (q ^ swz(r))) * 4; }   // in floats
 

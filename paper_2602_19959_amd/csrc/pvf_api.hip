@@ -16,7 +16,7 @@ namespace pvf {
 namespace {
 
 constexpr int kMaxBins = 16384;
-constexpr size_t kMaxScaleFloats = 1 << 15;   // FP8 column / output / tensor scales
+constexpr size_t kMaxScaleFloats = 1 << 16;   // FP8 column / output / tensor scales
 constexpr int kMaxBinsPerInterval = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -385,6 +385,7 @@ struct pvf_engine {
         const WeightLayout::Conv* w = nullptr;
         std::vector<int> in_src;      // launches whose stored outputs form this input, in channel order
         size_t col = 0;               // FP8: offsets (floats) into the scales region
+        size_t fold = 0;              // FP8 stored outputs: [n] s_n / a_out, then [n] bias / a_out
     };
     std::vector<int> out_channels;       // channels of the tensor launch i stores (0: none)
     std::vector<size_t> outinv_off, a_off;   // FP8: 1/a and a of launch i's stored tensor
@@ -564,6 +565,16 @@ pvf_status setup_fp8(pvf_engine* e, const std::vector<float>& f32, const float* 
                 for (int ch = 0; ch < c.cin; ++ch)
                     wq[c.w->w + (size_t)n * per_n + t * c.cin + ch] = to_e4m3_host(row[t * c.cin + ch] * ain[ch] / sn);
         }
+        // stored outputs: the column scale and the bias divided by the output
+        // channel's scale (a positive factor, which LeakyReLU commutes with),
+        // 16-byte aligned so a lane reads its four columns with one load each
+        if (c.epi != EPI_HEAD) {
+            if ((int)a[i].size() != c.cout) return PVF_ERR_INVALID_ARGUMENT;
+            while (sc.size() % 4) sc.push_back(0.f);
+            c.fold = sc.size();
+            for (int n = 0; n < c.n; ++n) sc.push_back(sc[c.col + n] / a[i][n % c.cout]);
+            for (int n = 0; n < c.n; ++n) sc.push_back(f32[c.w->b + n % c.cout] / a[i][n % c.cout]);
+        }
     }
     // the track network: per layer input-channel scales from the calibration,
     // folded into the weights, and one scale per column
@@ -694,6 +705,8 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
         if (scales) {
             a.col_scale = scales + eng->conv[li].col;
             a.out_inv_scale = epi == EPI_HEAD ? nullptr : scales + eng->outinv_off[li];
+            a.fold_scale = epi == EPI_HEAD ? nullptr : scales + eng->conv[li].fold;
+            a.fold_bias = epi == EPI_HEAD ? nullptr : scales + eng->conv[li].fold + eng->conv[li].n;
         }
         const int C = eng->conv[li].cout;
         check(launch_conv(dt, a, taps, epi, var(), s));

@@ -121,6 +121,8 @@ struct ConvArgs {
     int l_out;           // positions per event of the output (EPI_HEAD)
     const float* col_scale;     // FP8: per GEMM column, dequantises the accumulator
     const float* out_inv_scale; // FP8: per output channel, 1 / scale of the stored tensor
+    const float* fold_scale;    // FP8 stored outputs: per GEMM column, col_scale / output scale (16-byte aligned)
+    const float* fold_bias;     // FP8 stored outputs: per GEMM column, bias / output scale (16-byte aligned)
 };
 
 struct TrackArgs {
