@@ -35,9 +35,35 @@ constexpr int HP = kHidden + 1;   // LDS pitch of the hidden activations
 
 __device__ __forceinline__ float lrelu(float x, float s) { return x >= 0.f ? x : s * x; }
 
+// softplus(x) = max(x, 0) + log1p(exp(-|x|)), in about 20 instructions:
+//   * t = exp(-|x|) = 2^(-|x| log2 e) on the hardware exp2, with the product
+//     split into hi + lo (the FMA gives the rounding error of hi exactly) and
+//     2^lo applied to first order; below 2^-120 the library exp2f keeps the
+//     subnormal result;
+//   * log1p(t) = 2 atanh(s), s = t / (2 + t) in (0, 1/3], from the atanh
+//     series s + s^3/3 + ... + s^17/17 (truncation below 2e-9 relative).
+// Relative error about 1e-6 (4e-6 at |x| = 80), against FP32 network
+// errors of the same order and the histogram's 1e-4 bound.
 __device__ __forceinline__ float softplus(float x)
 {
-    return fmaxf(x, 0.f) + log1pf(expf(-fabsf(x)));
+    constexpr float kLog2e = 1.44269504f, kLog2eLo = 1.92596303e-8f, kLn2 = 0.693147181f;
+    const float a = -fabsf(x);
+    const float hi = a * kLog2e;
+    const float lo = fmaf(a, kLog2eLo, fmaf(a, kLog2e, -hi));
+    const float t0 = hi < -120.f ? exp2f(hi) : __builtin_amdgcn_exp2f(hi);
+    const float t = fmaf(t0, lo * kLn2, t0);
+    const float s = t * __builtin_amdgcn_rcpf(2.f + t);
+    const float z = s * s;
+    float p = 1.f / 17.f;
+    p = fmaf(p, z, 1.f / 15.f);
+    p = fmaf(p, z, 1.f / 13.f);
+    p = fmaf(p, z, 1.f / 11.f);
+    p = fmaf(p, z, 1.f / 9.f);
+    p = fmaf(p, z, 1.f / 7.f);
+    p = fmaf(p, z, 1.f / 5.f);
+    p = fmaf(p, z, 1.f / 3.f);
+    p = fmaf(p, z, 1.f);
+    return fmaxf(x, 0.f) + 2.f * s * p;
 }
 
 // Exact (uncontracted) lower edge of interval i, as the binning takes it.
