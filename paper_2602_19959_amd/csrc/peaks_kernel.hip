@@ -8,9 +8,12 @@
 // the window's bin centres.  Window sums and centroids are accumulated in
 // double, in ascending bin order.
 //
-// The row is staged in LDS; thread k owns a contiguous run of bins, counts
-// its vertices, a block-wide exclusive scan gives each thread its first
-// output slot, and the vertices are written in ascending bin order.
+// The row is staged in LDS.  Round k tests bins k * NT + tid (consecutive
+// lanes read consecutive bins, so the LDS reads are conflict-free); a ballot
+// per wave and round counts the vertices, and after one barrier every thread
+// knows how many vertices precede its own in ascending bin order (earlier
+// rounds, then earlier waves, then lower lanes of its round), so they are
+// written in that order.
 #include "pvf_internal.h"
 
 namespace pvf {
@@ -43,12 +46,14 @@ __device__ __forceinline__ Vertex test_bin(const float* ps, int t, int L, const 
     return v;
 }
 
+constexpr int kMaxRounds = 64;   // bins per event <= NT * kMaxRounds (one bit per round)
+
 __global__ __launch_bounds__(NT) void peak_finder(PeakArgs a)
 {
     extern __shared__ float ps[];                 // [L]
-    __shared__ int scan[NT];
+    __shared__ int wcount[NT / 64][kMaxRounds];   // vertices per wave and round
 
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int e = blockIdx.x;
     const int L = a.L;
     const float* p = a.prob + (int64_t)e * L;
@@ -57,43 +62,47 @@ __global__ __launch_bounds__(NT) void peak_finder(PeakArgs a)
     const bool bypass = (flags & (PVF_EV_TOO_MANY_TRACKS | PVF_EV_BAD_INPUT)) != 0;
     __syncthreads();
 
-    const int chunk = (L + NT - 1) / NT;
-    const int t0 = tid * chunk < 1 ? 1 : tid * chunk;
-    const int t1 = (tid + 1) * chunk > L - 1 ? L - 1 : (tid + 1) * chunk;
-    int n = 0;
-    if (!bypass)
-        for (int t = t0; t < t1; ++t) n += test_bin(ps, t, L, a).ok ? 1 : 0;
-
-    // inclusive Hillis-Steele scan of the per-thread counts
-    scan[tid] = n;
-    __syncthreads();
-    for (int off = 1; off < NT; off <<= 1) {
-        const int v = tid >= off ? scan[tid - off] : 0;
-        __syncthreads();
-        scan[tid] += v;
-        __syncthreads();
+    const int rounds = (L + NT - 1) / NT;
+    uint64_t mine = 0;                            // bit k: bin k * NT + tid is a vertex
+    for (int k = 0; k < rounds; ++k) {
+        const int t = k * NT + tid;
+        const bool ok = !bypass && t >= 1 && t <= L - 2 && test_bin(ps, t, L, a).ok;
+        const uint64_t m = __ballot(ok);
+        if (lane == 0) wcount[wave][k] = __popcll(m);
+        mine |= (uint64_t)ok << k;
     }
-    const int total = scan[NT - 1];
-    int k = scan[tid] - n;
+    __syncthreads();
 
     double* zo = a.z + (int64_t)e * a.max_peaks;
     float* po = a.peak_prob + (int64_t)e * a.max_peaks;
     double* so = a.integral + (int64_t)e * a.max_peaks;
     int32_t* bo = a.bin ? a.bin + (int64_t)e * a.max_peaks : nullptr;
-    if (!bypass && n > 0) {
-        for (int t = t0; t < t1 && k < a.max_peaks; ++t) {
-            const Vertex v = test_bin(ps, t, L, a);
-            if (!v.ok) continue;
-            zo[k] = v.M / v.S;
-            po[k] = ps[t];
-            so[k] = v.S;
-            if (bo) bo[k] = t;
-            ++k;
+    const uint64_t below = (1ull << lane) - 1ull;
+    int base = 0;                                 // vertices in earlier rounds
+    for (int k = 0; k < rounds; ++k) {
+        int before = 0, in_round = 0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) {
+            const int c = wcount[w][k];
+            in_round += c;
+            before += w < wave ? c : 0;
         }
+        const bool ok = (mine >> k) & 1ull;
+        const uint64_t m = __ballot(ok);
+        const int slot = base + before + __popcll(m & below);
+        if (ok && slot < a.max_peaks) {
+            const int t = k * NT + tid;
+            const Vertex v = test_bin(ps, t, L, a);
+            zo[slot] = v.M / v.S;
+            po[slot] = ps[t];
+            so[slot] = v.S;
+            if (bo) bo[slot] = t;
+        }
+        base += in_round;
     }
     if (tid == 0) {
-        a.n_vertices[e] = total < a.max_peaks ? total : a.max_peaks;
-        a.status[e] = flags | (total > a.max_peaks ? PVF_EV_PEAKS_TRUNCATED : 0);
+        a.n_vertices[e] = base < a.max_peaks ? base : a.max_peaks;
+        a.status[e] = flags | (base > a.max_peaks ? PVF_EV_PEAKS_TRUNCATED : 0);
     }
 }
 
@@ -101,6 +110,7 @@ __global__ __launch_bounds__(NT) void peak_finder(PeakArgs a)
 
 hipError_t launch_peaks(const PeakArgs& a, int n_events, hipStream_t s)
 {
+    if (a.L < 3 || a.L > NT * kMaxRounds) return hipErrorInvalidValue;
     hipLaunchKernelGGL(peak_finder, dim3(n_events), dim3(NT), sizeof(float) * a.L, s, a);
     return hipGetLastError();
 }
