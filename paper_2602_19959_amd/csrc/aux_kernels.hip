@@ -25,46 +25,41 @@ __device__ __forceinline__ float e4m3_to_f32(uint8_t b)
     return (b & 0x80) ? -v : v;
 }
 
-// enc0.c1: y[c] = LeakyReLU(b[c] + sum_j w[c][j] x[t + j - 2]), one row per
-// thread, all C0 channels written as one contiguous run of float4 stores.
+// enc0.c1: y[c] = LeakyReLU(b[c] + sum_j w[c][j] x[t + j - 2]).  Thread i
+// computes the 16-byte chunk i % CPR of row i / CPR (CPR chunks per row), so
+// the lanes of a wave store consecutive chunks: one contiguous 1 KB per wave
+// store.  Guard rows are not written (they stay zero).
 template <class T>
 __global__ __launch_bounds__(NT) void first_conv(FirstConvArgs a)
 {
+    constexpr int CH = 16 / (int)sizeof(T);       // channels per 16-byte chunk
     __shared__ float w[kMaxC0 * kTaps];
     __shared__ float b[kMaxC0];
     for (int i = threadIdx.x; i < a.c0 * kTaps; i += NT) w[i] = a.w[i];
     for (int i = threadIdx.x; i < a.c0; i += NT) b[i] = a.b[i];
     __syncthreads();
-    const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (r >= a.m_rows) return;
-    const int64_t e = r / a.r0;
-    const int loc = (int)(r - e * a.r0);
+    const int lg_cpr = 31 - __clz(a.c0 / CH);     // chunks per row: a power of two
+    const unsigned i = blockIdx.x * NT + threadIdx.x;    // rows * chunks < 2^31 (checked)
+    const unsigned r = i >> lg_cpr;
+    if (r >= (unsigned)a.m_rows) return;
+    const int c = (int)(i & ((1u << lg_cpr) - 1u)) * CH;   // first channel of the chunk
+    const unsigned e = r / (unsigned)a.r0;
+    const int loc = (int)(r - e * (unsigned)a.r0);
     if (loc < kGuard || loc >= a.r0 - kGuard) return;
     float x[kTaps];
 #pragma unroll
-    for (int j = 0; j < kTaps; ++j) x[j] = a.x0[r + j - kGuard];
-    T* o = static_cast<T*>(a.out) + r * a.c0;
-    for (int c = 0; c < a.c0; c += 8) {
-        T y[8];
+    for (int j = 0; j < kTaps; ++j) x[j] = a.x0[(int64_t)r + j - kGuard];
+    T y[CH];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            float s = b[c + u];
+    for (int u = 0; u < CH; ++u) {
+        float s = b[c + u];
 #pragma unroll
-            for (int j = 0; j < kTaps; ++j) s = fmaf(w[(c + u) * kTaps + j], x[j], s);
-            const float act = s >= 0.f ? s : a.slope * s;
-            if constexpr (sizeof(T) == 1) y[u] = to_e4m3(act * a.out_inv_scale[c + u]);
-            else y[u] = (T)act;
-        }
-        // 8 channels = 32 B (float) or 16 B (16-bit): whole-vector stores
-        if constexpr (sizeof(T) == 4) {
-            reinterpret_cast<f32x4*>(o + c)[0] = *reinterpret_cast<const f32x4*>(y);
-            reinterpret_cast<f32x4*>(o + c)[1] = *reinterpret_cast<const f32x4*>(y + 4);
-        } else if constexpr (sizeof(T) == 1) {
-            *reinterpret_cast<uint2*>(o + c) = *reinterpret_cast<const uint2*>(y);
-        } else {
-            *reinterpret_cast<uint4*>(o + c) = *reinterpret_cast<const uint4*>(y);
-        }
+        for (int j = 0; j < kTaps; ++j) s = fmaf(w[(c + u) * kTaps + j], x[j], s);
+        const float act = s >= 0.f ? s : a.slope * s;
+        if constexpr (sizeof(T) == 1) y[u] = to_e4m3(act * a.out_inv_scale[c + u]);
+        else y[u] = (T)act;
     }
+    *reinterpret_cast<uint4*>(static_cast<T*>(a.out) + (int64_t)r * a.c0 + c) = *reinterpret_cast<const uint4*>(y);
 }
 
 template <class T>
@@ -104,8 +99,12 @@ __global__ __launch_bounds__(NT) void amax_channels(AmaxArgs a)
 
 hipError_t launch_first_conv(const FirstConvArgs& a, int dtype, hipStream_t s)
 {
-    if (a.c0 > kMaxC0 || a.c0 % 8 != 0) return hipErrorInvalidValue;
-    const unsigned blocks = (unsigned)((a.m_rows + NT - 1) / NT);
+    const int bytes = dtype == PVF_FP32 ? 4 : (dtype == PVF_FP8_E4M3 ? 1 : 2);
+    const int cpr = a.c0 * bytes / 16;
+    if (a.c0 > kMaxC0 || (a.c0 * bytes) % 16 != 0 || (cpr & (cpr - 1)) != 0) return hipErrorInvalidValue;
+    const int64_t threads = (int64_t)a.m_rows * cpr;
+    if (threads >= (1ll << 31)) return hipErrorInvalidValue;
+    const unsigned blocks = (unsigned)((threads + NT - 1) / NT);
     if (dtype == PVF_FP32) hipLaunchKernelGGL(first_conv<float>, dim3(blocks), dim3(NT), 0, s, a);
     else if (dtype == PVF_BF16) hipLaunchKernelGGL(first_conv<__bf16>, dim3(blocks), dim3(NT), 0, s, a);
     else if (dtype == PVF_FP16) hipLaunchKernelGGL(first_conv<_Float16>, dim3(blocks), dim3(NT), 0, s, a);
