@@ -35,14 +35,6 @@ __device__ __forceinline__ int at32(int r, int p) { return r * KC + 16 * ((p >> 
 
 __device__ __forceinline__ float lrelu(float x, float s) { return x >= 0.f ? x : s * x; }
 
-// FP32 -> OCP e4m3, saturated to +-448 (the conversion itself turns values
-// beyond the range into NaN), round to nearest even.
-__device__ __forceinline__ uint8_t to_e4m3(float x)
-{
-    x = fminf(fmaxf(x, -448.f), 448.f);
-    return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.f, 0, false) & 0xff);
-}
-
 __device__ __forceinline__ float e4m3_to_f32(uint8_t b)
 {
     const int e = (b >> 3) & 15, m = b & 7;
