@@ -559,6 +559,7 @@ template <class E>
 hipError_t launch_track_typed(const TrackArgs& a, int n_events, int persistent_blocks, int* order_scratch,
                               hipStream_t s)
 {
+    if (a.n_out < 1 || a.n_out > NT) return hipErrorInvalidValue;   // one thread per output column
     const size_t lds = track_stage_lds_bytes(a.n_out, a.n_intervals);
     if (lds > 64 * 1024) {
         hipError_t err = hipFuncSetAttribute((const void*)track_stage<E>,
