@@ -80,6 +80,45 @@ def test_histogram_parity(eng8, out8, ref8):
         assert parity.max_rel(hist[e][nz], ref[nz]) <= parity.P_REL
 
 
+@pytest.fixture(scope="module")
+def eng_seeds():
+    # an engine of its own: the layer tests below read eng8's stored
+    # activations of the seed-0 batch
+    torch_cuda()
+    e = make_engine(8)
+    yield e
+    e.close()
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_parity_other_seeds(eng_seeds, seed):
+    """p, histogram and peaks of three more 8-event batches (other event
+    streams of the same generator) against the oracle, at the same bars."""
+    eng = eng_seeds
+    batch = make_events(8, seed=seed)
+    ref = oracle.run_batch(batch, weights())
+    say(f"execute 8-event batch of seed {seed}")
+    out = run(eng, batch)
+    errs = [parity.max_rel(out["prob"][e], ref[e]["p"]) for e in range(8)]
+    say(f"seed {seed}: max rel err p %.2e" % max(errs))
+    assert max(errs) <= parity.P_REL
+    hist = eng.debug_tensor("hist", 8).cpu().numpy().reshape(8, -1)
+    s_in = weights().s_in
+    geo = geometry(eng)
+    total_amb = 0
+    for e in range(8):
+        h_ref = s_in * ref[e]["H"]
+        nz = h_ref != 0
+        assert np.all(hist[e][~nz] == 0)
+        assert parity.max_rel(hist[e][nz], h_ref[nz]) <= parity.P_REL
+        bins, z, hh, S = event_vertices(out, e)
+        assert out["n_vertices"][e] == len(bins)
+        amb, _ = parity.compare_peaks(bins, z, hh, S, ref[e], geo)
+        total_amb += amb
+    say(f"seed {seed}: ambiguous decisions excluded:", total_amb)
+    assert total_amb < 100
+
+
 LAYERS = ["enc0.c2", "pool0", "enc1.c2", "pool1", "enc2.c2", "pool2", "enc3.c1", "enc3.c2",
           "up2", "dec2.c1", "dec2.c2", "up1", "dec1.c1", "dec1.c2", "up0", "dec0.c1"]
 
