@@ -183,6 +183,82 @@ def serve_bench(args):
     }), flush=True)
 
 
+def gemm_yardstick(args):
+    """Per 5-tap conv layer: this library's launch time (HIP events on the
+    engine's stream) beside the vendor GEMM (torch.mm, i.e. hipBLASLt) on
+    the same layer's plain GEMM, M = positions x events, N = Cout,
+    K = 5 Cin, with A already unfolded in HBM (so the vendor side skips the
+    halo handling a convolution needs).  A yardstick, not part of a step."""
+    import numpy as np
+    import torch
+
+    import paper_2602_19959_amd as pv
+    from synth import make_events, make_weights, weights_to_blob
+
+    if args.dtype == "fp8_e4m3":
+        print("--gemm-yardstick covers fp32, bf16 and fp16", file=sys.stderr)
+        sys.exit(2)
+    E = args.events
+    batch = make_events(E, seed=args.seed, mix=args.mix)
+    T = np.diff(batch.offsets)
+    spec = pv.default_spec(max_events=E, max_tracks_total=int(max(T.sum(), 1)), compute_dtype=args.dtype,
+                           max_tracks_per_event=max(1500, int(T.max())))
+    eng = pv.Engine(weights_to_blob(make_weights(args.seed)), spec)
+    feat, off = pv.upload_events(batch)
+    out = eng.alloc_outputs(E, with_prob=False)
+    eng.profile(True)
+    names, kernels = eng.launch_names(), eng.launch_kernels()
+    runs = []
+    for r in range(args.warmup + args.steps):
+        eng.execute(feat, off, out)
+        eng.synchronize()
+        if r >= args.warmup:
+            runs.append(eng.profile_read())
+    ours = np.median(np.array(runs), axis=0)
+    eng.close()
+    macs = layer_macs(spec)
+    tdt = {"fp32": torch.float32, "bf16": torch.bfloat16, "fp16": torch.float16}[args.dtype]
+    torch.backends.cuda.matmul.allow_tf32 = False
+    c0 = spec.base_channels
+    rows = []
+    for i, nm in enumerate(names):
+        if not (nm.startswith("enc") or nm.startswith("dec")) or nm == "enc0.c1" or nm not in macs:
+            continue
+        lvl = int(nm[3])
+        L, C = spec.n_bins >> lvl, c0 << lvl
+        if nm.startswith("enc"):
+            cin = (c0 << (lvl - 1)) if nm.endswith("c1") else C
+        else:
+            cin = 2 * C if nm.endswith("c1") else C
+        M, N, K = L * E, C, 5 * cin
+        g = torch.Generator(device="cuda").manual_seed(1)
+        a = torch.randn(M, K, device="cuda", dtype=tdt, generator=g)
+        b = torch.randn(K, N, device="cuda", dtype=tdt, generator=g)
+        c = torch.empty(M, N, device="cuda", dtype=tdt)
+        for _ in range(3):
+            torch.mm(a, b, out=c)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            torch.mm(a, b, out=c)
+        e1.record()
+        torch.cuda.synchronize()
+        vend = e0.elapsed_time(e1) / args.steps
+        del a, b, c
+        fl = 2.0 * M * N * K
+        rows.append({"layer": nm, "M": M, "N": N, "K": K, "kernel": kernels[i],
+                     "ours_us": round(float(ours[i]) * 1e3, 1), "vendor_gemm_us": round(vend * 1e3, 1),
+                     "ours_tflops": round(fl / (float(ours[i]) * 1e9), 1),
+                     "vendor_gemm_tflops": round(fl / (vend * 1e9), 1)})
+        print(f"[yardstick] {rows[-1]}", file=sys.stderr, flush=True)
+    tot_o = sum(r["ours_us"] for r in rows)
+    tot_v = sum(r["vendor_gemm_us"] for r in rows)
+    print(json.dumps({"yardstick": "vendor GEMM (torch.mm -> hipBLASLt) on each 5-tap conv layer's GEMM shape",
+                      "dtype": DTYPE_TAG[args.dtype], "events": E, "layers": rows,
+                      "sum_ours_us": round(tot_o, 1), "sum_vendor_gemm_us": round(tot_v, 1)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +296,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-compare-dtypes", dest="compare_dtypes", action="store_false",
                     help="FP32 runs only: skip the BF16 and FP8 passes on the same batch")
+    ap.add_argument("--gemm-yardstick", action="store_true",
+                    help="instead: per 5-tap conv layer, this library's launch time beside the vendor GEMM "
+                         "(torch.mm) of the same GEMM shape; one JSON line")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size kernel "
                          "for scaling hardware byte counters)")
@@ -242,6 +321,9 @@ def main():
         sys.exit(1)
     if args.serve:
         serve_bench(args)
+        return
+    if args.gemm_yardstick:
+        gemm_yardstick(args)
         return
     E = args.events
     from synth import NetShape

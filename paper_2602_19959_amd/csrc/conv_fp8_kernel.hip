@@ -330,10 +330,15 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_fp8_db(ConvArgs a)
 
     // Wave-wide load j fills LDS rows 16 j .. 16 j + 15 of the stage (halo
     // rows first, then the tap-major weight rows tap * BN + column); this
-    // wave issues j = wave + t * NW, from a per-lane source computed once.
+    // wave issues j = wave + t * NW.  Each lane's source is a 32-bit byte
+    // offset, computed once, from one of two block-uniform bases (the halo's
+    // first row and the N tile's first weight row; clamped rows stay at or
+    // after them).
     constexpr int NJ = XI + WI, JT = (NJ + NW - 1) / NW;
     const int lrow = lane >> 2, lpos = lane & 3;
-    const uint8_t* src[JT];
+    const uint8_t* xbase = in + (m0 - RAD) * a.ld_in;
+    const uint8_t* wbase = wt + (int64_t)n0 * kw;
+    unsigned off[JT];
 #pragma unroll
     for (int t = 0; t < JT; ++t) {
         const int j = min(wave + t * NW, NJ - 1);
@@ -343,11 +348,11 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_fp8_db(ConvArgs a)
         if (xj) {
             int64_t gr = m0 - RAD + row;
             gr = gr < 0 ? 0 : (gr >= a.m_rows ? a.m_rows - 1 : gr);
-            src[t] = in + gr * a.ld_in + 16 * c;
+            off[t] = (unsigned)((gr - (m0 - RAD)) * a.ld_in + 16 * c);
         } else {
             const int tap = row / BN, nn = row % BN;
             const int n = n0 + nn < a.n ? n0 + nn : a.n - 1;
-            src[t] = wt + (int64_t)n * kw + tap * a.cin + 16 * c;
+            off[t] = (unsigned)((n - n0) * kw + tap * a.cin + 16 * c);
         }
     }
     auto issue = [&](int buf, int c0) __attribute__((always_inline)) {
@@ -356,7 +361,7 @@ __global__ __launch_bounds__(WM * WN * 64) void conv_mfma_fp8_db(ConvArgs a)
         for (int t = 0; t < JT; ++t) {
             const int j = wave + t * NW;
             if ((t + 1) * NW <= NJ || j < NJ)
-                __builtin_amdgcn_global_load_lds((const void*)(src[t] + c0),
+                __builtin_amdgcn_global_load_lds((const void*)((j < XI ? xbase : wbase) + (off[t] + (unsigned)c0)),
                                                  (__attribute__((address_space(3))) void*)(base + 16 * j * KB), 16, 0, 0);
         }
     };
@@ -424,6 +429,7 @@ constexpr Variant kVariants[] = {
     {4, 1, 4, 4, 1},   // 5: 256 x 64, double-buffered
     {4, 1, 4, 2, 1},   // 6: 256 x 32, double-buffered
     {2, 2, 8, 4, 1},   // 7: 256 x 128, double-buffered, 128 x 64 per wave
+    {8, 2, 4, 4, 1},   // 8: 512 x 128, double-buffered (1024 threads, one block per CU)
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -453,6 +459,7 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_FP8_CASE(5)
             PVF_FP8_CASE(6)
             PVF_FP8_CASE(7)
+            PVF_FP8_CASE(8)
         default: return hipErrorInvalidValue;
         }
     }

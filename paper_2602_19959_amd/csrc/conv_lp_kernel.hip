@@ -373,10 +373,14 @@ void conv_mfma_lp_db(ConvArgs a)
     // Wave-wide load j fills LDS rows 16 j .. 16 j + 15 of the stage (halo
     // rows first, then the tap-major weight rows tap * BN + column); this
     // wave issues j = wave + t * NW.  Each lane's source is fixed apart from
-    // the stage's channel offset, so it is computed once.
+    // the stage's channel offset, so it is computed once, as a 32-bit byte
+    // offset from one of two block-uniform bases (the halo's first row and
+    // the N tile's first weight row; clamped rows stay at or after them).
     constexpr int NJ = XI + WI, JT = (NJ + NW - 1) / NW;
     const int lrow = lane >> 2, lpos = lane & 3;
-    const T* src[JT];
+    const char* xbase = reinterpret_cast<const char*>(in + (m0 - RAD) * a.ld_in);
+    const char* wbase = reinterpret_cast<const char*>(wt + (int64_t)n0 * kw);
+    unsigned off[JT];
 #pragma unroll
     for (int t = 0; t < JT; ++t) {
         const int j = min(wave + t * NW, NJ - 1);
@@ -386,20 +390,21 @@ void conv_mfma_lp_db(ConvArgs a)
         if (xj) {
             int64_t gr = m0 - RAD + row;
             gr = gr < 0 ? 0 : (gr >= a.m_rows ? a.m_rows - 1 : gr);
-            src[t] = in + gr * a.ld_in + 8 * c;
+            off[t] = (unsigned)(((gr - (m0 - RAD)) * a.ld_in + 8 * c) * (int64_t)sizeof(T));
         } else {
             const int tap = row / BN, nn = row % BN;
             const int n = n0 + nn < a.n ? n0 + nn : a.n - 1;
-            src[t] = wt + (int64_t)n * kw + tap * a.cin + 8 * c;
+            off[t] = (unsigned)((int64_t)((n - n0) * kw + tap * a.cin + 8 * c) * (int64_t)sizeof(T));
         }
     }
     auto issue = [&](int buf, int c0) __attribute__((always_inline)) {
         char* base = smem + buf * STAGE;
+        const unsigned cb = (unsigned)(c0 * (int)sizeof(T));
 #pragma unroll
         for (int t = 0; t < JT; ++t) {
             const int j = wave + t * NW;
             if ((t + 1) * NW <= NJ || j < NJ)
-                __builtin_amdgcn_global_load_lds((const void*)(src[t] + c0),
+                __builtin_amdgcn_global_load_lds((const void*)((j < XI ? xbase : wbase) + (off[t] + cb)),
                                                  (__attribute__((address_space(3))) void*)(base + 16 * j * ROWB), 16, 0, 0);
         }
     };
@@ -415,7 +420,10 @@ void conv_mfma_lp_db(ConvArgs a)
         const T* xs = reinterpret_cast<const T*>(smem + (k & 1) * STAGE);
         const T* ws = xs + XR * KC;
         // fragments of tap t + 1 are read while tap t is on the matrix cores
-        V av[2][TMW], bv[2][TNW];
+        // (blocks of 16 waves have no registers to spare for that: there the
+        // other three waves of the SIMD cover the read latency)
+        constexpr int FB = NW < 16 ? 2 : 1;
+        V av[FB][TMW], bv[FB][TNW];
         auto frag = [&](int tap, int f) {
 #pragma unroll
             for (int i = 0; i < TMW; ++i)
@@ -424,14 +432,19 @@ void conv_mfma_lp_db(ConvArgs a)
             for (int j = 0; j < TNW; ++j)
                 bv[f][j] = *reinterpret_cast<const V*>(ws + lds_at<NCH>(tap * BN + wn * TNW * 16 + j * 16 + li, lg));
         };
-        frag(0, 0);
+        if constexpr (FB == 2) frag(0, 0);
 #pragma unroll
         for (int tap = 0; tap < TAPS; ++tap) {
-            if (tap + 1 < TAPS) frag(tap + 1, (tap + 1) & 1);
+            if constexpr (FB == 2) {
+                if (tap + 1 < TAPS) frag(tap + 1, (tap + 1) & 1);
+            } else {
+                frag(tap, 0);
+            }
+            const int f = FB == 2 ? (tap & 1) : 0;
 #pragma unroll
             for (int i = 0; i < TMW; ++i)
 #pragma unroll
-                for (int j = 0; j < TNW; ++j) acc[i][j] = Lp<T>::mfma(bv[tap & 1][j], av[tap & 1][i], acc[i][j]);
+                for (int j = 0; j < TNW; ++j) acc[i][j] = Lp<T>::mfma(bv[f][j], av[f][i], acc[i][j]);
         }
     }
     __syncthreads();   // the epilogue reuses the stage buffers
@@ -475,6 +488,7 @@ constexpr Variant kVariants[] = {
     {2, 1, 4, 2, 32, 2},   // 16: 128 x 32, double-buffered (128 threads)
     {2, 2, 8, 4, 32, 2},   // 17: 256 x 128, double-buffered, 128 x 64 per wave
     {2, 1, 8, 4, 32, 2},   // 18: 256 x 64, double-buffered, 128 x 64 per wave (128 threads)
+    {8, 2, 4, 4, 32, 2},   // 19: 512 x 128, double-buffered (1024 threads, one block per CU)
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -519,6 +533,7 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_LP_CASE(16)
             PVF_LP_CASE(17)
             PVF_LP_CASE(18)
+            PVF_LP_CASE(19)
         default: return hipErrorInvalidValue;
         }
     }
@@ -558,7 +573,8 @@ bool lp_variant_ok(int v, int n, int cin, int taps, Epi epi)
 // Defaults from the autotuner's BF16 picks on MI355X at 1000 events (widths
 // 32 and 64, event and interval layouts).  The small-channel layers take the
 // 128-row or 64-channel-stage tiles, the wide ones the 256 x 128
-// single-buffered tile (two blocks per CU), and the 1x1 transposed convs the
+// single-buffered tile (two blocks per CU) or, from 256 input channels, the
+// double-buffered 512 x 128 tile, and the 1x1 transposed convs the
 // double-buffered 128 x 128 tile.
 int lp_default_variant(int n, int cin, int taps, Epi epi)
 {
@@ -570,7 +586,7 @@ int lp_default_variant(int n, int cin, int taps, Epi epi)
         if (cin <= 32) return 1;
         return cin >= 128 ? 13 : (cin % 64 == 0 ? 8 : 13);
     }
-    return 3;
+    return cin >= 256 ? 19 : 3;
 }
 
 std::string lp_kernel_name(int dtype, int v, int taps, Epi epi)
