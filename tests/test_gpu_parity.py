@@ -200,6 +200,25 @@ def test_edge_events(eng8):
     big.close()
 
 
+@pytest.mark.parametrize("hw,s_min", [(0, 0.2), (3, 3.0), (5, 5.0), (8, 8.0)])
+def test_peaks_other_windows(batch8, ref8, hw, s_min):
+    """Other half-widths and window thresholds (the window test then rejects
+    part of the local maxima); the oracle finds peaks on its own p."""
+    torch_cuda()
+    eng = make_engine(8, half_window=hw, integral_min=s_min)
+    out = run(eng, batch8)
+    geo = geometry(eng)
+    assert geo.half_window == hw and geo.s_min == s_min
+    kept = 0
+    for e in range(8):
+        ref = dict(oracle.peaks(ref8[e]["p"], geo), p=ref8[e]["p"])
+        bins, z, h, S = event_vertices(out, e)
+        parity.compare_peaks(bins, z, h, S, ref, geo)
+        kept += len(bins)
+    say(f"hw {hw} s_min {s_min}: {kept} vertices")
+    eng.close()
+
+
 def test_peak_truncation():
     import paper_2602_19959_amd as pv
     torch_cuda()
