@@ -430,6 +430,9 @@ constexpr Variant kVariants[] = {
     {4, 1, 4, 2, 1},   // 6: 256 x 32, double-buffered
     {2, 2, 8, 4, 1},   // 7: 256 x 128, double-buffered, 128 x 64 per wave
     {8, 2, 4, 4, 1},   // 8: 512 x 128, double-buffered (1024 threads, one block per CU)
+    {8, 1, 4, 2, 0},   // 9: 512 x 32 (the weight tile staged once per 512 rows)
+    {8, 1, 4, 4, 0},   // 10: 512 x 64
+    {8, 1, 4, 4, 1},   // 11: 512 x 64, double-buffered
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -447,6 +450,9 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_FP8_CASE(1)
             PVF_FP8_CASE(5)
             PVF_FP8_CASE(6)
+            PVF_FP8_CASE(9)
+            PVF_FP8_CASE(10)
+            PVF_FP8_CASE(11)
         default: return hipErrorInvalidValue;
         }
     } else {
@@ -460,6 +466,9 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_FP8_CASE(6)
             PVF_FP8_CASE(7)
             PVF_FP8_CASE(8)
+            PVF_FP8_CASE(9)
+            PVF_FP8_CASE(10)
+            PVF_FP8_CASE(11)
         default: return hipErrorInvalidValue;
         }
     }
@@ -476,20 +485,22 @@ bool fp8_variant_ok(int v, int n, int cin, int taps, Epi epi)
     const Variant& x = kVariants[v];
     const int bn = x.wn * x.tnw * 16;
     if (cin % (x.db ? 64 : KC) != 0) return false;
-    if (epi == EPI_HEAD) return (v == 0 || v == 1 || v == 5 || v == 6) && bn == n && x.wn == 1;
+    if (epi == EPI_HEAD) return (v == 0 || v == 1 || v == 5 || v == 6 || v >= 9) && bn == n && x.wn == 1;
     return bn <= (n < 32 ? 32 : n);
 }
 
 // Picks of variant sweeps over 1000 events: the double-buffered 64-channel
 // stages wherever the layer has them (cin a multiple of 64) and enough
-// output channels; the single-buffered tiles for 32-channel inputs.
+// output channels; the single-buffered tiles for 32- and 64-channel inputs,
+// 512 rows tall where the input has 32 channels (the weight tile is then
+// staged once per 512 rows).
 int fp8_default_variant(int n, int cin, int taps, Epi epi)
 {
-    if (epi == EPI_HEAD) return n == 64 ? 1 : 0;
+    if (epi == EPI_HEAD) return n == 64 ? 1 : (cin <= 32 ? 9 : 0);
     if (epi == EPI_CONVT && taps == 1) return n >= 128 ? 4 : 6;
-    if (n <= 32) return 0;
+    if (n <= 32) return cin <= 32 ? 9 : 0;
     if (cin >= 128) return 5;
-    return 1;
+    return cin <= 32 ? 10 : 1;
 }
 
 std::string fp8_kernel_name(int v, int cin, int taps, Epi epi)

@@ -489,6 +489,10 @@ constexpr Variant kVariants[] = {
     {2, 2, 8, 4, 32, 2},   // 17: 256 x 128, double-buffered, 128 x 64 per wave
     {2, 1, 8, 4, 32, 2},   // 18: 256 x 64, double-buffered, 128 x 64 per wave (128 threads)
     {8, 2, 4, 4, 32, 2},   // 19: 512 x 128, double-buffered (1024 threads, one block per CU)
+    {8, 1, 4, 2, 32, 0},   // 20: 512 x 32 (the weight tile staged once per 512 rows)
+    {8, 1, 4, 2, 32, 2},   // 21: 512 x 32, double-buffered
+    {8, 1, 4, 4, 32, 0},   // 22: 512 x 64
+    {8, 1, 4, 4, 32, 2},   // 23: 512 x 64, double-buffered
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -510,6 +514,10 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_LP_CASE(13)
             PVF_LP_CASE(14)
             PVF_LP_CASE(16)
+            PVF_LP_CASE(20)
+            PVF_LP_CASE(21)
+            PVF_LP_CASE(22)
+            PVF_LP_CASE(23)
         default: return hipErrorInvalidValue;
         }
     } else {
@@ -534,6 +542,10 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_LP_CASE(17)
             PVF_LP_CASE(18)
             PVF_LP_CASE(19)
+            PVF_LP_CASE(20)
+            PVF_LP_CASE(21)
+            PVF_LP_CASE(22)
+            PVF_LP_CASE(23)
         default: return hipErrorInvalidValue;
         }
     }
@@ -566,27 +578,28 @@ bool lp_variant_ok(int v, int n, int cin, int taps, Epi epi)
     const int bn = x.wn * x.tnw * 16;
     if (cin % x.kc != 0) return false;
     if (epi == EPI_HEAD)
-        return (v == 0 || v == 1 || v == 4 || v == 5 || v == 11 || v == 13 || v == 14 || v == 16) && bn == n && x.wn == 1;
+        return (v == 0 || v == 1 || v == 4 || v == 5 || v == 11 || v == 13 || v == 14 || v == 16 || v >= 20) &&
+               bn == n && x.wn == 1;
     return bn <= (n < 32 ? 32 : n);
 }
 
 // Defaults from the autotuner's BF16 picks on MI355X at 1000 events (widths
 // 32 and 64, event and interval layouts).  The small-channel layers take the
-// 128-row or 64-channel-stage tiles, the wide ones the 256 x 128
-// single-buffered tile (two blocks per CU) or, from 256 input channels, the
-// double-buffered 512 x 128 tile, and the 1x1 transposed convs the
-// double-buffered 128 x 128 tile.
+// 512-row, 128-row or 64-channel-stage tiles, the wide ones the 256 x 128
+// single-buffered tile (two blocks per CU), the 512 x 64 tile at 128 input
+// channels or, from 256 input channels, the double-buffered 512 x 128 tile,
+// and the 1x1 transposed convs the double-buffered 128 x 128 tile.
 int lp_default_variant(int n, int cin, int taps, Epi epi)
 {
-    if (epi == EPI_HEAD) return n == 64 ? 1 : 5;
+    if (epi == EPI_HEAD) return n == 64 ? 1 : 20;
     if (epi == EPI_CONVT && taps == 1) return n >= 512 ? 17 : (n >= 128 ? 15 : (cin % 64 == 0 ? 8 : 4));
     if (n <= 32) return epi == EPI_POOL ? 5 : (cin % 64 == 0 ? 8 : 14);
     if (n <= 64) {
         if (epi == EPI_POOL) return 4;
-        if (cin <= 32) return 1;
+        if (cin <= 32) return 22;
         return cin >= 128 ? 13 : (cin % 64 == 0 ? 8 : 13);
     }
-    return cin >= 256 ? 19 : 3;
+    return cin >= 256 ? 19 : (cin == 128 ? 22 : 3);
 }
 
 std::string lp_kernel_name(int dtype, int v, int taps, Epi epi)
