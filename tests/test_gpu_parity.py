@@ -219,6 +219,30 @@ def test_peaks_other_windows(batch8, ref8, hw, s_min):
     eng.close()
 
 
+def test_longest_histogram():
+    """The longest histogram the spec takes with the paper's 100-bin
+    intervals: 16000 bins (160 intervals; at most 16384 bins), so the UNet
+    rows, the track stage's LDS histogram and the peak finder's row and
+    candidate list are at their largest.  FP32 p and peaks of two events
+    against the oracle."""
+    torch_cuda()
+    eng = make_engine(2, n_bins=16000, max_peaks_per_event=8000)
+    batch = make_events(2, seed=0)
+    say("16000-bin engine")
+    out = run(eng, batch)
+    geo = geometry(eng)
+    assert geo.n_bins == 16000
+    refs = oracle.run_batch(batch, weights(), geo)
+    for e in range(2):
+        ref = refs[e]
+        assert ref["n"] < 8000
+        assert parity.max_rel(out["prob"][e], ref["p"]) <= parity.P_REL, e
+        bins, z, h, S = event_vertices(out, e)
+        parity.compare_peaks(bins, z, h, S, ref, geo)
+        assert out["status"][e] == 0
+    eng.close()
+
+
 def test_peak_truncation():
     import paper_2602_19959_amd as pv
     torch_cuda()
