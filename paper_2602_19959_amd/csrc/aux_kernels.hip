@@ -11,13 +11,7 @@ constexpr int kMaxC0 = 64;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// OCP e4m3 helpers (saturated conversion: the hardware conversion maps
-// out-of-range values to NaN)
-__device__ __forceinline__ uint8_t to_e4m3(float x)
-{
-    x = fminf(fmaxf(x, -448.f), 448.f);
-    return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.f, 0, false) & 0xff);
-}
+// OCP e4m3 decoding
 __device__ __forceinline__ float e4m3_to_f32(uint8_t b)
 {
     const int e = (b >> 3) & 15, m = b & 7;
@@ -52,11 +46,8 @@ __global__ __launch_bounds__(NT) void first_conv(FirstConvArgs a)
     T y[CH];
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
-        float s = b[c + u];
-#pragma unroll
-        for (int j = 0; j < kTaps; ++j) s = fmaf(w[(c + u) * kTaps + j], x[j], s);
-        const float act = s >= 0.f ? s : a.slope * s;
-        if constexpr (sizeof(T) == 1) y[u] = to_e4m3(act * a.out_inv_scale[c + u]);
+        const float act = first_conv_at(w + (c + u) * kTaps, b[c + u], x, a.slope);
+        if constexpr (sizeof(T) == 1) y[u] = e4m3_sat(act * a.out_inv_scale[c + u]);
         else y[u] = (T)act;
     }
     *reinterpret_cast<uint4*>(static_cast<T*>(a.out) + (int64_t)r * a.c0 + c) = *reinterpret_cast<const uint4*>(y);

@@ -151,10 +151,14 @@ struct F32Occ {
     static constexpr int regs = 512 / F32Regs<TMW, TNW>::v;
     static constexpr int v = PF ? 1 : (lds < regs ? lds : regs);
 };
-template <int WM, int WN, int TMW, int TNW, int PF, int TAPS, int EPI>
-__global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(F32Occ<WM, WN, TMW, TNW, PF, TAPS>::v)))
-void conv_mfma_f32(ConvArgs a)
+// FC: enc0.c2 with the first convolution fused into the staging: each halo
+// chunk is computed from five histogram rows (first_conv_at, the operation
+// order of the standalone kernel, so the bits match) instead of read back;
+// guard rows are zero, as in the stored tensor.
+template <int WM, int WN, int TMW, int TNW, int PF, int TAPS, int EPI, bool FC>
+__device__ __forceinline__ void conv_f32_tile(const ConvArgs& a)
 {
+    static_assert(!FC || (TAPS == kTaps && PF == 0), "the fused first convolution feeds a 5-tap, unprefetched tile");
     constexpr int NT = WM * WN * 64;
     constexpr int BM = WM * TMW * 16;
     constexpr int BN = WN * TNW * 16;
@@ -227,24 +231,58 @@ void conv_mfma_f32(ConvArgs a)
         const int n = n0 + nn < a.n ? n0 + nn : a.n - 1;
         wsrc[u] = wt + (int64_t)n * kw + tap * a.cin + 4 * q;
     }
-    f32x4 xr[XPT], wr[WPT];
+    f32x4 xr[FC ? 1 : XPT], wr[WPT];
     auto fetch = [&](int c0) __attribute__((always_inline)) {
+        if constexpr (!FC) {
 #pragma unroll
-        for (int u = 0; u < XPT; ++u) xr[u] = *reinterpret_cast<const f32x4*>(xsrc[u] + c0);
+            for (int u = 0; u < XPT; ++u) xr[u] = *reinterpret_cast<const f32x4*>(xsrc[u] + c0);
+        }
 #pragma unroll
         for (int u = 0; u < WPT; ++u) wr[u] = *reinterpret_cast<const f32x4*>(wsrc[u] + c0);
     };
-    auto stage = [&]() __attribute__((always_inline)) {
+    // FC: the halo chunks of stage c0 are computed and stored one at a time,
+    // while the stage's weight loads are in flight.
+    auto stage = [&](int c0) __attribute__((always_inline)) {
+        if constexpr (FC) {
+            const int c = c0 + 4 * q;                 // this thread's 4 channels
+            float fw[4][kTaps], fb[4];
 #pragma unroll
-        for (int u = 0; u < XPT; ++u)
-            if (x_has(u)) *reinterpret_cast<f32x4*>(xs + lds0 + u * RS * KC) = xr[u];
+            for (int v = 0; v < 4; ++v) {
+                fb[v] = a.first_b[c + v];
+#pragma unroll
+                for (int j = 0; j < kTaps; ++j) fw[v][j] = a.first_w[(c + v) * kTaps + j];
+            }
+            const RowMap rmap(m0, a.r_in);
+#pragma unroll
+            for (int u = 0; u < XPT; ++u) {
+                if (!x_has(u)) continue;
+                int64_t g = m0 - RAD + row0 + u * RS;
+                g = g < 0 ? 0 : (g >= a.m_rows ? a.m_rows - 1 : g);
+                int64_t e;
+                int loc;
+                rmap.at((int)(g - m0), e, loc);
+                f32x4 y = {0.f, 0.f, 0.f, 0.f};
+                if (loc >= kGuard && loc < a.r_in - kGuard) {
+                    float x[kTaps];
+#pragma unroll
+                    for (int j = 0; j < kTaps; ++j) x[j] = a.first_x0[g + j - kGuard];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) y[v] = first_conv_at(fw[v], fb[v], x, a.slope);
+                }
+                *reinterpret_cast<f32x4*>(xs + lds0 + u * RS * KC) = y;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < XPT; ++u)
+                if (x_has(u)) *reinterpret_cast<f32x4*>(xs + lds0 + u * RS * KC) = xr[u];
+        }
 #pragma unroll
         for (int u = 0; u < WPT; ++u)
             if (w_has(u)) *reinterpret_cast<f32x4*>(ws + lds0 + u * RS * KC) = wr[u];
     };
 
     fetch(0);
-    stage();
+    stage(0);
     __syncthreads();
     for (int c0 = 0; c0 < a.cin; c0 += KC) {
         const bool more = c0 + KC < a.cin;
@@ -269,12 +307,29 @@ void conv_mfma_f32(ConvArgs a)
         __syncthreads();
         if (more) {
             if (!PF) fetch(c0 + KC);
-            stage();
+            stage(c0 + KC);
             __syncthreads();
         }
     }
 
     f32_epilogue<WM, TMW, TNW, EPI>(acc, a, m0, n0, tid);
+}
+
+template <int WM, int WN, int TMW, int TNW, int PF, int TAPS, int EPI>
+__global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(F32Occ<WM, WN, TMW, TNW, PF, TAPS>::v)))
+void conv_mfma_f32(ConvArgs a)
+{
+    conv_f32_tile<WM, WN, TMW, TNW, PF, TAPS, EPI, false>(a);
+}
+
+// enc0.c2 with the first convolution in its staging (max-pool epilogue); the
+// first convolution's weights take registers, so the occupancy target is two
+// waves per SIMD.
+template <int WM, int WN, int TMW, int TNW>
+__global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(2)))
+void conv_mfma_f32_first(ConvArgs a)
+{
+    conv_f32_tile<WM, WN, TMW, TNW, 0, kTaps, EPI_POOL, true>(a);
 }
 
 
@@ -407,6 +462,18 @@ hipError_t run(const ConvArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int WM, int WN, int TMW, int TNW>
+hipError_t run_first(const ConvArgs& a, hipStream_t s)
+{
+    constexpr int BM = WM * TMW * 16;
+    constexpr int BN = WN * TNW * 16;
+    const unsigned m_tiles = (unsigned)((a.m_rows + BM - 1) / BM);
+    const unsigned n_tiles = (unsigned)((a.n + BN - 1) / BN);
+    dim3 grid((m_tiles + kXcds - 1) / kXcds * kXcds * n_tiles);
+    hipLaunchKernelGGL((conv_mfma_f32_first<WM, WN, TMW, TNW>), grid, dim3(WM * WN * 64), 0, s, a);
+    return hipGetLastError();
+}
+
 // Tile-shape variants.  Every variant accumulates each output's k terms in
 // the same order (16-channel chunk, tap, MFMA step), so all of them give
 // bitwise-identical results; they differ only in speed.
@@ -499,6 +566,33 @@ std::string f32_kernel_name(int v, int taps, Epi epi)
     return "conv_mfma_f32<" + std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " + std::to_string(x.tmw) +
            ", " + std::to_string(x.tnw) + ", " + std::to_string(x.pf) + ", " + std::to_string(taps) + ", " +
            std::to_string((int)epi) + ">";
+}
+
+// Variants that can take the fused first convolution: the single-buffered,
+// unprefetched tiles (their halo staging goes through registers).
+bool f32_first_ok(int v)
+{
+    return v == 0 || v == 2 || v == 3 || v == 5;
+}
+
+std::string f32_first_kernel_name(int v)
+{
+    const Variant& x = kVariants[v];
+    return "conv_mfma_f32_first<" + std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " +
+           std::to_string(x.tmw) + ", " + std::to_string(x.tnw) + ">";
+}
+
+hipError_t launch_conv_f32_first(const ConvArgs& a, int v, hipStream_t s)
+{
+    if (a.cin % KC != 0 || a.m_rows <= 0 || !f32_first_ok(v) || !f32_variant_ok(v, a.n, kTaps, EPI_POOL))
+        return hipErrorInvalidValue;
+    switch (v) {
+    case 0: return run_first<kVariants[0].wm, kVariants[0].wn, kVariants[0].tmw, kVariants[0].tnw>(a, s);
+    case 2: return run_first<kVariants[2].wm, kVariants[2].wn, kVariants[2].tmw, kVariants[2].tnw>(a, s);
+    case 3: return run_first<kVariants[3].wm, kVariants[3].wn, kVariants[3].tmw, kVariants[3].tnw>(a, s);
+    case 5: return run_first<kVariants[5].wm, kVariants[5].wn, kVariants[5].tmw, kVariants[5].tnw>(a, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_conv_f32(const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s)

@@ -184,11 +184,14 @@ __device__ __forceinline__ void lp_epilogue(const f32x4 (&acc)[TMW][TNW], const 
 // (32-channel chunk, tap, MFMA), the same as with KC = 32, so KC does not
 // change a bit of the result.  PF = 1: the next stage is fetched into
 // registers while the current one computes.
-template <class T, int WM, int WN, int TMW, int TNW, int KC, int PF, int TAPS, int EPI>
-__global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(PF ? 1 : occupancy_target(
-    LpLds<(int)sizeof(T), WM * TMW * 16, WN * TNW * 16, KC, TAPS, EPI, 1, TAPS - 1>::v, WM * WN))))
-void conv_mfma_lp(ConvArgs a)
+// FC: enc0.c2 with the first convolution fused into the staging: each halo
+// chunk is computed from five histogram rows (first_conv_at, the operation
+// order of the standalone kernel, so the bits match) instead of read back;
+// guard rows are zero, as in the stored tensor.
+template <class T, int WM, int WN, int TMW, int TNW, int KC, int PF, int TAPS, int EPI, bool FC>
+__device__ __forceinline__ void conv_lp_tile(const ConvArgs& a)
 {
+    static_assert(!FC || (TAPS == kTaps && PF == 0), "the fused first convolution feeds a 5-tap, unprefetched tile");
     using V = typename Lp<T>::vec8;
     constexpr int NT = WM * WN * 64;
     constexpr int BM = WM * TMW * 16;
@@ -261,24 +264,67 @@ void conv_mfma_lp(ConvArgs a)
         const int n = n0 + nn < a.n ? n0 + nn : a.n - 1;
         return wt + (int64_t)n * kw + tap * a.cin + 8 * q;
     };
-    u32x4 xr[XPT], wr[WPT];
+    u32x4 xr[FC ? 1 : XPT], wr[WPT];
     auto fetch = [&](int c0) __attribute__((always_inline)) {
+        if constexpr (!FC) {
 #pragma unroll
-        for (int u = 0; u < XPT; ++u) xr[u] = *reinterpret_cast<const u32x4*>(x_src(u) + c0);
+            for (int u = 0; u < XPT; ++u) xr[u] = *reinterpret_cast<const u32x4*>(x_src(u) + c0);
+        }
 #pragma unroll
         for (int u = 0; u < WPT; ++u) wr[u] = *reinterpret_cast<const u32x4*>(w_src(u) + c0);
     };
-    auto stage = [&]() __attribute__((always_inline)) {
+    // FC: the halo chunks of stage c0 are computed and stored one at a time
+    // (while the stage's weight loads are in flight), so only this thread's
+    // eight channels of first-convolution weights stay in registers.
+    auto stage_first = [&](int c0) __attribute__((always_inline)) {
+        const int c = c0 + 8 * q;
+        float fw[8][kTaps], fb[8];
 #pragma unroll
-        for (int u = 0; u < XPT; ++u)
-            if (x_has(u)) *reinterpret_cast<u32x4*>(xs + lds0 + u * RS * KC) = xr[u];
+        for (int v = 0; v < 8; ++v) {
+            fb[v] = a.first_b[c + v];
+#pragma unroll
+            for (int j = 0; j < kTaps; ++j) fw[v][j] = a.first_w[(c + v) * kTaps + j];
+        }
+        const RowMap rmap(m0, a.r_in);
+#pragma unroll
+        for (int u = 0; u < XPT; ++u) {
+            if (!x_has(u)) continue;
+            int64_t g = m0 - RAD + row0 + u * RS;
+            g = g < 0 ? 0 : (g >= a.m_rows ? a.m_rows - 1 : g);
+            int64_t e;
+            int loc;
+            rmap.at((int)(g - m0), e, loc);
+            T y[8];
+            if (loc < kGuard || loc >= a.r_in - kGuard) {
+#pragma unroll
+                for (int v = 0; v < 8; ++v) y[v] = (T)0.f;
+            } else {
+                float x[kTaps];
+#pragma unroll
+                for (int j = 0; j < kTaps; ++j) x[j] = a.first_x0[g + j - kGuard];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) y[v] = (T)first_conv_at(fw[v], fb[v], x, a.slope);
+            }
+            u32x4 yv;
+            __builtin_memcpy(&yv, y, sizeof(y));
+            *reinterpret_cast<u32x4*>(xs + lds0 + u * RS * KC) = yv;
+        }
+    };
+    auto stage = [&](int c0) __attribute__((always_inline)) {
+        if constexpr (FC) {
+            stage_first(c0);
+        } else {
+#pragma unroll
+            for (int u = 0; u < XPT; ++u)
+                if (x_has(u)) *reinterpret_cast<u32x4*>(xs + lds0 + u * RS * KC) = xr[u];
+        }
 #pragma unroll
         for (int u = 0; u < WPT; ++u)
             if (w_has(u)) *reinterpret_cast<u32x4*>(ws + lds0 + u * RS * KC) = wr[u];
     };
 
     fetch(0);
-    stage();
+    stage(0);
     __syncthreads();
     for (int c0 = 0; c0 < a.cin; c0 += KC) {
         const bool more = c0 + KC < a.cin;
@@ -305,13 +351,31 @@ void conv_mfma_lp(ConvArgs a)
         __syncthreads();
         if (more) {
             if constexpr (!PF) fetch(c0 + KC);   // all loads in flight before the first store
-            stage();
+            stage(c0 + KC);
             __syncthreads();
         }
     }
 
     __syncthreads();   // the epilogue reuses the stage buffers
     lp_epilogue<T, NT, BM, BN, WM, TMW, TNW, EPI>(acc, a, smem, m0, n0, tid);
+}
+
+template <class T, int WM, int WN, int TMW, int TNW, int KC, int PF, int TAPS, int EPI>
+__global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(PF ? 1 : occupancy_target(
+    LpLds<(int)sizeof(T), WM * TMW * 16, WN * TNW * 16, KC, TAPS, EPI, 1, TAPS - 1>::v, WM * WN))))
+void conv_mfma_lp(ConvArgs a)
+{
+    conv_lp_tile<T, WM, WN, TMW, TNW, KC, PF, TAPS, EPI, false>(a);
+}
+
+// enc0.c2 with the first convolution in its staging (32-channel stages,
+// max-pool epilogue); the first convolution's weights take registers, so the
+// occupancy target is two waves per SIMD.
+template <class T, int WM, int WN, int TMW, int TNW>
+__global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(2)))
+void conv_mfma_lp_first(ConvArgs a)
+{
+    conv_lp_tile<T, WM, WN, TMW, TNW, 32, 0, kTaps, EPI_POOL, true>(a);
 }
 
 
@@ -466,6 +530,18 @@ hipError_t run(const ConvArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <class T, int WM, int WN, int TMW, int TNW>
+hipError_t run_first(const ConvArgs& a, hipStream_t s)
+{
+    constexpr int BM = WM * TMW * 16;
+    constexpr int BN = WN * TNW * 16;
+    const unsigned m_tiles = (unsigned)((a.m_rows + BM - 1) / BM);
+    const unsigned n_tiles = (unsigned)((a.n + BN - 1) / BN);
+    dim3 grid((m_tiles + kXcds - 1) / kXcds * kXcds * n_tiles);
+    hipLaunchKernelGGL((conv_mfma_lp_first<T, WM, WN, TMW, TNW>), grid, dim3(WM * WN * 64), 0, s, a);
+    return hipGetLastError();
+}
+
 // Tile-shape / staging variants; all give identical bits.
 struct Variant { int wm, wn, tmw, tnw, kc, pf; };
 constexpr Variant kVariants[] = {
@@ -613,6 +689,51 @@ std::string lp_kernel_name(int dtype, int v, int taps, Epi epi)
            std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " + std::to_string(x.tmw) + ", " +
            std::to_string(x.tnw) + ", " + std::to_string(x.kc) + ", " + std::to_string(x.pf) + ", " +
            std::to_string(taps) + ", " + std::to_string((int)epi) + ">";
+}
+
+// Variants that can take the fused first convolution: the single-buffered,
+// unprefetched 32-channel-stage tiles (their halo staging goes through
+// registers; the double-buffered ones load straight into LDS).
+bool lp_first_ok(int v)
+{
+    return v == 0 || v == 1 || v == 5 || v == 20 || v == 22;
+}
+
+std::string lp_first_kernel_name(int dtype, int v)
+{
+    const Variant& x = kVariants[v];
+    return std::string("conv_mfma_lp_first<") + (dtype == PVF_BF16 ? "__bf16" : "_Float16") + ", " +
+           std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " + std::to_string(x.tmw) + ", " +
+           std::to_string(x.tnw) + ">";
+}
+
+hipError_t launch_conv_lp_first(int dtype, const ConvArgs& a, int v, hipStream_t s)
+{
+    if (a.cin % 32 != 0 || a.m_rows <= 0 || !lp_first_ok(v) || !lp_variant_ok(v, a.n, a.cin, kTaps, EPI_POOL))
+        return hipErrorInvalidValue;
+    if (dtype != PVF_BF16 && dtype != PVF_FP16) return hipErrorInvalidValue;
+#define PVF_LP_FIRST(V, TYPE)                                                                                  \
+    case V:                                                                                                \
+        return run_first<TYPE, kVariants[V].wm, kVariants[V].wn, kVariants[V].tmw, kVariants[V].tnw>(a, s);
+    if (dtype == PVF_BF16) {
+        switch (v) {
+            PVF_LP_FIRST(0, __bf16)
+            PVF_LP_FIRST(1, __bf16)
+            PVF_LP_FIRST(5, __bf16)
+            PVF_LP_FIRST(20, __bf16)
+            PVF_LP_FIRST(22, __bf16)
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (v) {
+        PVF_LP_FIRST(0, _Float16)
+        PVF_LP_FIRST(1, _Float16)
+        PVF_LP_FIRST(5, _Float16)
+        PVF_LP_FIRST(20, _Float16)
+        PVF_LP_FIRST(22, _Float16)
+    default: return hipErrorInvalidValue;
+    }
+#undef PVF_LP_FIRST
 }
 
 hipError_t launch_conv_lp(int dtype, const ConvArgs& a, int taps, Epi epi, int v, hipStream_t s)

@@ -98,6 +98,26 @@ struct RowMap {
     }
 };
 
+// One output channel of the first convolution (one input channel, five
+// taps) at one row: bias, then the taps in order as fused multiply-adds, then
+// the LeakyReLU.  The standalone first-convolution kernel and the conv kernels
+// that fuse it into their staging share this, so both give the same bits.
+__device__ __forceinline__ float first_conv_at(const float* w5, float b, const float* x5, float slope)
+{
+    float s = b;
+#pragma unroll
+    for (int j = 0; j < kTaps; ++j) s = fmaf(w5[j], x5[j], s);
+    return s >= 0.f ? s : slope * s;
+}
+
+// OCP e4m3 code of x, saturated at +-448 (the hardware conversion would give
+// NaN beyond).
+__device__ __forceinline__ uint8_t e4m3_sat(float x)
+{
+    x = fminf(fmaxf(x, -448.f), 448.f);
+    return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.f, 0, false) & 0xff);
+}
+
 struct ConvArgs {
     const void* in;      // input rows, channels-last (element type = compute dtype)
     int ld_in;           // floats per input row
@@ -123,6 +143,12 @@ struct ConvArgs {
     const float* out_inv_scale; // FP8: per output channel, 1 / scale of the stored tensor
     const float* fold_scale;    // FP8 stored outputs: per GEMM column, col_scale / output scale (16-byte aligned)
     const float* fold_bias;     // FP8 stored outputs: per GEMM column, bias / output scale (16-byte aligned)
+    // First convolution fused into the staging of enc0.c2 (launch_conv_first
+    // only): the input rows are then computed from the histogram rows instead
+    // of read from `in`
+    const float* first_x0;      // [m_rows] histogram rows, the input level's row layout
+    const float* first_w;       // [cin][taps]
+    const float* first_b;       // [cin]
 };
 
 struct TrackArgs {
@@ -222,6 +248,14 @@ hipError_t launch_first_conv(const FirstConvArgs& a, int dtype, hipStream_t s);
 // Conv launches run one of several tile-shape variants of the kernel for
 // the compute dtype; all variants of a dtype give identical bits.
 hipError_t launch_conv(int dtype, const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s);
+// enc0.c2 (5 taps, max-pool epilogue) with the first convolution computed in
+// its staging (a.first_* set); conv_first_ok tells which variants do this
+// (none in FP8: its 16-channel halo chunks need about 200 registers for the
+// first convolution's weights, and the launch ran slower than the two it
+// replaces).
+hipError_t launch_conv_first(int dtype, const ConvArgs& a, int variant, hipStream_t s);
+bool conv_first_ok(int dtype, int variant);
+std::string conv_first_kernel_name(int dtype, int variant);
 int conv_variant_count(int dtype);
 bool conv_variant_ok(int dtype, int variant, int n, int cin, int taps, Epi epi);
 int conv_default_variant(int dtype, int n, int cin, int taps, Epi epi);
@@ -233,11 +267,17 @@ int f32_variant_count();
 bool f32_variant_ok(int variant, int n, int taps, Epi epi);
 int f32_default_variant(int n, int cin, int taps, Epi epi);
 std::string f32_kernel_name(int variant, int taps, Epi epi);
+hipError_t launch_conv_f32_first(const ConvArgs& a, int variant, hipStream_t s);
+bool f32_first_ok(int variant);
+std::string f32_first_kernel_name(int variant);
 hipError_t launch_conv_lp(int dtype, const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s);
 int lp_variant_count();
 bool lp_variant_ok(int variant, int n, int cin, int taps, Epi epi);
 int lp_default_variant(int n, int cin, int taps, Epi epi);
 std::string lp_kernel_name(int dtype, int variant, int taps, Epi epi);
+hipError_t launch_conv_lp_first(int dtype, const ConvArgs& a, int variant, hipStream_t s);
+bool lp_first_ok(int variant);
+std::string lp_first_kernel_name(int dtype, int variant);
 
 hipError_t launch_conv_fp8(const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s);
 int fp8_variant_count();
