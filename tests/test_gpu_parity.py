@@ -243,6 +243,26 @@ def test_longest_histogram():
     eng.close()
 
 
+def test_first_conv_fused_and_standalone_agree(eng8, batch8, out8):
+    """By default enc0.c2 computes the first convolution in its staging; with
+    a tile variant that cannot (a double-buffered one) the standalone
+    first-convolution kernel runs before it.  Both give the same bits."""
+    names, kernels = eng8.launch_names(), eng8.launch_kernels()
+    i = names.index("enc0.c2")
+    assert names[i - 1] == "enc0.c1"
+    assert kernels[i].startswith("conv_mfma_f32_first<") and kernels[i - 1] == "first_conv (in enc0.c2)"
+    base = eng8.variants()[i]
+    db = next(v for v in range(eng8.variant_count(i)) if eng8.set_variant(i, v) and "_db<" in eng8.launch_kernels()[i])
+    try:
+        assert eng8.launch_kernels()[i - 1] == "first_conv", db
+        got = run(eng8, batch8)
+        for k in ("prob", "z", "integral", "n_vertices", "bin"):
+            assert np.array_equal(got[k], out8[k]), k
+    finally:
+        eng8.set_variant(i, base)
+    assert eng8.launch_kernels()[i].startswith("conv_mfma_f32_first<")
+
+
 def test_peak_truncation():
     import paper_2602_19959_amd as pv
     torch_cuda()
