@@ -226,7 +226,11 @@ pvf_status pvf_graph_launch(pvf_engine *eng);
 
 /* ---- instrumentation (not on the hot path) ---------------------------- */
 
-/* Number of kernel launches one pvf_execute enqueues for this engine. */
+/* Number of launch slots of one pvf_execute for this engine.  One slot,
+ * enc0.c1 (the first convolution), enqueues nothing when enc0.c2's tile
+ * variant computes the first convolution in its own staging (FP32, BF16 and
+ * FP16 by default); its kernel name then reads "first_conv (in enc0.c2)" and
+ * its profiled time is zero. */
 int pvf_launch_count(const pvf_engine *eng);
 
 /* Name of launch i (e.g. "track", "enc0.c2", "up1", "peaks"); NULL if out
@@ -235,7 +239,8 @@ const char *pvf_launch_name(const pvf_engine *eng, int i);
 
 /* Kernel that launch i runs, as it appears in a profiler's kernel name
  * (e.g. "conv_mfma_f32<4, 2, 4, 4, 5, 0>", "track_stage"); NULL if out of
- * range.  Static storage for the engine's life. */
+ * range.  Owned by the engine; valid until the next pvf_set_launch_variant,
+ * pvf_autotune or pvf_set_track_schedule on it. */
 const char *pvf_launch_kernel(const pvf_engine *eng, int i);
 
 /* Tile-shape variants (Section 5 of the paper: launch-geometry tuning).
@@ -251,8 +256,9 @@ pvf_status pvf_set_launch_variant(pvf_engine *eng, int i, int v);
 
 /* Autotuner: runs the batch `tracks` (reps + 1 times per variant) on the
  * engine's stream, timing every launch with HIP events, and keeps the
- * fastest variant of each convolution launch.  A set-up call: it
- * synchronises the stream and overwrites `out`.  Not for the hot path. */
+ * fastest variant of each convolution launch (enc0.c2 is charged the first
+ * convolution too, fused or not).  A set-up call: it synchronises the stream
+ * and overwrites `out`.  Not for the hot path. */
 pvf_status pvf_autotune(pvf_engine *eng, const pvf_tracks *tracks, const pvf_vertices *out, int reps);
 
 /* on != 0: create one HIP event per launch boundary now, and from then on
