@@ -25,6 +25,10 @@
 //   EPI_HEAD   bias + LeakyReLU, then the 1x1 head over all channels and the
 //              sigmoid, writing the per-bin probability
 // Guard rows (the two zero rows before and after each event) are never written.
+//
+// conv_mfma_f32_first runs enc0.c2 with the first convolution (one input
+// channel, five taps) computed in its halo staging from the histogram rows,
+// so that 32-channel tensor never goes through HBM.
 #include "pvf_internal.h"
 
 namespace pvf {

@@ -19,7 +19,10 @@
 //     the tile is staged in LDS and written back as whole 16-byte row chunks
 //     (channels-last rows are contiguous), with the fused max-pool or the
 //     transposed-conv row interleave; the head epilogue works on the FP32
-//     accumulators and writes the FP32 probability.
+//     accumulators and writes the FP32 probability;
+//   * conv_mfma_lp_first runs enc0.c2 with the first convolution (one input
+//     channel, five taps) computed in its halo staging from the histogram
+//     rows, so that 32-channel tensor never goes through HBM.
 #include "pvf_internal.h"
 
 namespace pvf {
