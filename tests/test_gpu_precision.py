@@ -116,3 +116,37 @@ def test_full_batch_sampled(lp):
         say(dt, f"event {e} max |dp| {dp:.3e}")
         assert dp <= parity.P_ABS[dt]
     eng.close()
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp16", "fp8_e4m3"])
+def test_edge_events_reduced_precision(dtype):
+    """Zero tracks, one track, out-of-window and non-finite tracks and an
+    ordinary event in one batch, in each reduced-precision path: p within the
+    dtype's stated bound of the oracle, the same status flags as the FP32
+    path, and events over the track cap bypassed."""
+    import paper_2602_19959_amd as pv
+    from synth.events import pack_events
+    from tests.gpu_util import engine_for
+    torch_cuda()
+    ev = make_events(4, seed=5)
+    t0 = ev.tracks_of(0).copy()
+    t0[0, :3] = [-150.0, 300.0, np.nan]
+    t0[5, 3] = np.inf
+    lists = [np.zeros((9, 0), np.float32), ev.tracks_of(1)[:, :1].copy(), t0, ev.tracks_of(3)]
+    batch = pack_events(lists)
+    w = weights()
+    refs = [oracle.run_event(t, w) for t in lists]
+    say("edge batch", dtype)
+    eng = engine_for(4, dtype)
+    out = run(eng, batch)
+    for e in range(4):
+        dp = float(np.max(np.abs(out["prob"][e] - refs[e]["p"])))
+        assert dp <= parity.P_ABS[dtype], (e, dp)
+    assert out["status"][0] == 0 and out["status"][1] == 0 and out["status"][3] == 0
+    assert out["status"][2] == pv.EV_TRACKS_DROPPED
+    eng.close()
+    capped = engine_for(4, dtype, max_tracks_per_event=50)
+    res = run(capped, batch)
+    assert res["status"][2] & pv.EV_TOO_MANY_TRACKS and res["n_vertices"][2] == 0
+    assert res["status"][0] == 0 and np.array_equal(res["prob"][0], out["prob"][0])
+    capped.close()
