@@ -263,6 +263,40 @@ def test_first_conv_fused_and_standalone_agree(eng8, batch8, out8):
     assert eng8.launch_kernels()[i].startswith("conv_mfma_f32_first<")
 
 
+@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+def test_ragged_shapes(dtype):
+    """A histogram of 3978 bins (39 intervals of 102) and a 2-level UNet: no
+    row count is a multiple of a tile, the bottom level has an odd length
+    (1989), the track network has 102 outputs and the peak finder's row is
+    not a multiple of four floats.  p and peaks of four events against the
+    oracle (FP32 at the FP32 bar, BF16 within its stated bound)."""
+    from synth import NetShape
+    torch_cuda()
+    shape = NetShape(n_out=102, n_levels=2)
+    eng = make_engine(4, shape=shape, n_bins=3978, bins_per_interval=102, compute_dtype=dtype,
+                      max_peaks_per_event=3978)
+    batch = make_events(4, seed=7)
+    say("ragged engine", dtype)
+    out = run(eng, batch)
+    geo = geometry(eng)
+    assert geo.n_bins == 3978 and geo.bins_per_interval == 102
+    refs = oracle.run_batch(batch, weights(0, shape), geo)
+    for e in range(4):
+        if dtype == "fp32":
+            assert parity.max_rel(out["prob"][e], refs[e]["p"]) <= parity.P_REL, e
+            bins, z, h, S = event_vertices(out, e)
+            parity.compare_peaks(bins, z, h, S, refs[e], geo)
+        else:
+            assert float(np.max(np.abs(out["prob"][e] - refs[e]["p"]))) <= parity.P_ABS[dtype], e
+        assert (out["status"][e] & ~pv_dropped()) == 0
+    eng.close()
+
+
+def pv_dropped():
+    import paper_2602_19959_amd as pv
+    return pv.EV_TRACKS_DROPPED
+
+
 def test_peak_truncation():
     import paper_2602_19959_amd as pv
     torch_cuda()
