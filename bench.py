@@ -547,7 +547,8 @@ def main():
                 "value": r["value"], "unit": "events/s", "ms_per_step": r["ms_per_step"],
                 "p50_us_per_event": r["p50_us_per_event"], "p99_us_per_event": r["p99_us_per_event"],
                 "stages_ms": r["stages_ms"], "dtype": r["dtype"],
-                "roofline": {k: r["roofline"][k] for k in ("bound", "kernel", "achieved", "peak", "unit", "frac")},
+                "roofline": {k: r["roofline"][k] for k in ("bound", "kernel", "achieved", "peak", "unit", "frac",
+                                                           "traffic")},
                 "stated_tolerance": STATED_TOL[dt]}
             print(f"[bench] {dt}: {r['value']:.0f} events/s", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
