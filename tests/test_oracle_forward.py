@@ -3,6 +3,7 @@ independent float64 PyTorch restatement of the same network."""
 
 import numpy as np
 import pytest
+import torch
 
 import oracle
 from synth import make_events, make_weights
@@ -23,7 +24,7 @@ def test_forward_vs_torch_restatement(run8):
     for e in range(8):
         np.testing.assert_allclose(res[e]["H"], H[e], rtol=1e-12, atol=0)
         np.testing.assert_allclose(res[e]["logit"], logit[e], rtol=1e-10, atol=1e-11)
-        p = 1.0 / (1.0 + np.exp(-logit[e]))
+        p = torch.sigmoid(torch.from_numpy(logit[e])).numpy()
         np.testing.assert_allclose(res[e]["p"], p, rtol=1e-12)
 
 

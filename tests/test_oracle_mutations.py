@@ -47,7 +47,7 @@ MUTATIONS = [
      "M += p[j] * (z_min + bw * j);", ["test_oracle_peaks.py"]),
     ("input scale dropped", "x0[t] = s_in * H[t];", "x0[t] = H[t];", ["test_oracle_forward.py"]),
     ("sigmoid sign", "return 1.0 / (1.0 + exp(-x));", "return 1.0 / (1.0 + exp(x));",
-     ["test_oracle_forward.py"]),
+     ["test_oracle_ops.py"]),
     ("feature shift sign", "((double)f[k * stride] - (double)shift[k])",
      "((double)f[k * stride] + (double)shift[k])", ["test_oracle_hist.py"]),
     ("height threshold not strict", "if (!(p[t] > p_min)) continue;", "if (!(p[t] >= p_min)) continue;",

@@ -94,6 +94,21 @@ def test_convT2_equals_interleave_then_correlate():
     np.testing.assert_allclose(oracle.convT2(x, W, b), y, rtol=1e-13, atol=1e-13)
 
 
+def test_sigmoid_closed_forms_and_library():
+    """The head's logistic function (Section 2: the UNet ends in a per-bin
+    probability): sigma(ln 3) = 3/4 and sigma(-ln 3) = 1/4 (exp(-ln 3) = 1/3),
+    sigma(0) = 1/2, increasing, and equal to torch.sigmoid in float64."""
+    ln3 = math.log(3.0)
+    assert abs(oracle.sigmoid(ln3) - 0.75) <= 2e-16
+    assert abs(oracle.sigmoid(-ln3) - 0.25) <= 2e-16
+    assert oracle.sigmoid(0.0) == 0.5
+    x = np.linspace(-30.0, 30.0, 601)
+    s = oracle.sigmoid(x)
+    assert np.all(np.diff(s) > 0)
+    ref = torch.sigmoid(torch.from_numpy(x)).numpy()
+    np.testing.assert_allclose(s, ref, rtol=1e-15, atol=0)
+
+
 def test_maxpool2_vs_torch():
     x = rng.normal(size=(5, 20))
     ref = F.max_pool1d(torch.tensor(x)[None], 2)[0].numpy()
