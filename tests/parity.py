@@ -21,14 +21,31 @@ on every robust decision.  Non-robust ("ambiguous") bins are excluded and
 counted.  delta = 1e-5 is ten times the FP32 path's worst absolute error on
 p seen at the 8-event workload and ten times below the tolerance on p.
 Matched vertices: |dz| <= 1e-4 mm, window sum and height within 1e-4 relative.
+Ambiguous decisions are capped: outside the sigmoid's saturated range
+(p_ref > 1 - SAT_EPS, where neighbouring probabilities differ by less than
+FP32 can resolve) at most AMB_MAX_FRAC of an event's decisions may be
+ambiguous; saturated ones are counted and reported.
+
+The peak finder itself is checked without exclusions by exact_peaks: the
+oracle's peak finder run on the GPU's own float32 p (upcast to double, which
+is exact) must give the GPU's vertex list index for index.  Peak finding is
+index work, so the bar there is bit-exact: the same bins, heights and window
+sums (both sides add the same doubles in ascending bin order), the same
+count and truncation flag, and z within 1e-12 relative (the centroid's
+products may be fused on the GPU).
 """
 
 import numpy as np
+
+import oracle
 
 P_REL = 1e-4
 TAP_NORM = 1e-5
 DELTA = 1e-5
 Z_ABS = 1e-4
+SAT_EPS = 1e-3
+AMB_MAX_FRAC = 5e-3
+Z_EXACT_REL = 1e-12
 
 
 def max_rel(a, ref):
@@ -65,9 +82,50 @@ def classify(p, geo):
     return out
 
 
+def ambiguity(ref, geo):
+    """(ambiguous bins, of which saturated, decisions) of one oracle event;
+    asserts the cap on the unsaturated ones."""
+    cls = classify(ref["p"], geo)
+    amb = np.nonzero(cls == 0)[0]
+    sat = int(np.sum(ref["p"][amb] > 1.0 - SAT_EPS))
+    n = max(int(ref["n"]), 1)
+    assert len(amb) - sat <= AMB_MAX_FRAC * n, (len(amb), sat, n)
+    return len(amb), sat, n
+
+
+def exact_peaks(host, e, geo):
+    """The GPU's vertex list of event e against the oracle's peak finder on
+    the GPU's own p: no exclusions, index-exact.  Returns the vertex count."""
+    p = np.asarray(host["prob"][e], np.float32).astype(np.float64)
+    ref = oracle.peaks(p, geo)
+    n = int(host["n_vertices"][e])
+    status = int(host["status"][e])
+    if status & 3:                        # bypassed event: no vertices at all
+        assert n == 0
+        return 0
+    assert n == min(ref["n"], geo.max_peaks), (e, n, ref["n"])
+    assert bool(status & 4) == (ref["n"] > geo.max_peaks), (e, status, ref["n"])
+    bins = host["bin"][e, :n]
+    assert np.array_equal(bins, ref["t"]), e
+    assert np.array_equal(np.asarray(host["integral"][e, :n], np.float64), ref["integral"]), e
+    assert np.array_equal(np.asarray(host["peak_prob"][e, :n], np.float32).astype(np.float64), ref["prob"]), e
+    z = np.asarray(host["z"][e, :n], np.float64)
+    assert np.all(np.abs(z - ref["z"]) <= Z_EXACT_REL * np.maximum(np.abs(ref["z"]), 1.0)), e
+    return n
+
+
+def exact_peaks_all(host, geo, events=None):
+    """exact_peaks over every event (or the given ones); returns the total
+    vertex count."""
+    evs = range(len(host["n_vertices"])) if events is None else events
+    return sum(exact_peaks(host, e, geo) for e in evs)
+
+
 def compare_peaks(gpu_t, gpu_z, gpu_prob, gpu_S, ref, geo):
     """Check the GPU vertex list of one event against the oracle result dict.
-    Returns (n_ambiguous, n_compared); raises AssertionError on a mismatch."""
+    Returns (n_ambiguous, n_compared); raises AssertionError on a mismatch
+    or when the ambiguous decisions outside saturation exceed the cap."""
+    ambiguity(ref, geo)
     cls = classify(ref["p"], geo)
     gset = set(int(t) for t in gpu_t)
     rset = set(int(t) for t in ref["t"])
@@ -89,30 +147,37 @@ def compare_peaks(gpu_t, gpu_z, gpu_prob, gpu_S, ref, geo):
     return len(amb), len(rset | gset)
 
 
-# Reduced-precision paths (BF16/FP16 storage and weights, FP32 accumulation).
-# Bounds frozen from a CPU emulation against the oracle on 16 seed-0 events
-# (BF16: max|dp| 1.4e-2, 99.9% of vertices matched; FP16: 1.6e-3, 99.996%):
-#   max |p - p_ref| <= P_ABS[dtype]; vertices matched one-to-one within
-#   |dz| <= 0.05 mm: at least MATCH_MIN[dtype] of the oracle's, and at most
-#   EXTRA_MAX[dtype] (as a fraction of the oracle's count) unmatched extras.
-# FP8 (e4m3, 3 mantissa bits: unit roundoff 2^-4) with per-channel scales
-# from a calibration batch of other events, for the UNet convolutions and the
-# track network's GEMMs alike: the emulation of that path gives max|dp|
-# 0.23-0.24 and 96.5-97.7% of vertices matched on these 16 events (0.12-0.18
-# with the network in FP32); the bound is 1.25x the emulated maximum.
-# BF16 and FP16 keep their bounds with the network in 16 bits (emulated
-# 1.5e-2 and 1.6e-3).
+# Reduced-precision paths (BF16/FP16 storage and weights, FP32 accumulation;
+# FP8 e4m3 with per-channel calibration scales): max |p - p_ref| <= P_ABS,
+# and vertices matched one-to-one within |dz| <= DZ_MATCH: at least
+# MATCH_MIN of the oracle's, at most EXTRA_MAX (a fraction of the oracle's
+# count) unmatched extras.  Each bound is derived, in
+# tests/test_precision_bounds.py, from the CPU emulation of the rounding in
+# tests/emulate.py against the oracle, and must sit between 1.15x and 4x the
+# emulated maximum.  Emulated on the 16 seed-0 events: max|dp| 1.54e-2 (BF16),
+# 1.58e-3 (FP16), 0.253 (FP8; calibration from 64 events of seed 5); matched
+# 99.86%, 99.98%, 97.8%; extra 0.16%, 0.02%, 2.7%.  FP8's three mantissa bits
+# (unit roundoff 2^-4 per stored value, compounded over 17 layers) set its
+# bound.
 P_ABS = {"bf16": 2e-2, "fp16": 5e-3, "fp8_e4m3": 0.3}
 MATCH_MIN = {"bf16": 0.995, "fp16": 0.999, "fp8_e4m3": 0.95}
 EXTRA_MAX = {"bf16": 0.005, "fp16": 0.001, "fp8_e4m3": 0.05}
 DZ_MATCH = 0.05
 
 # The 64-channel network (the paper's deployed width) sums twice as many
-# rounded products per output and has larger activations; the same
-# emulations on 6 seed-1 events give max|dp| 3.4e-2 (BF16), 4.5e-3 (FP16) and
-# 0.38 (FP8, per-channel scales), with 99.8-100% of vertices matched.
+# rounded products per output and has larger activations; emulated on 6
+# seed-1 events: max|dp| 3.5e-2 (BF16), 3.8e-3 (FP16), 0.40 (FP8), with
+# 99.8-100% of vertices matched.
 P_ABS_WIDE = {"bf16": 5e-2, "fp16": 7e-3, "fp8_e4m3": 0.5}
 MATCH_MIN_WIDE = {"bf16": 0.995, "fp16": 0.999, "fp8_e4m3": 0.97}
+
+# Heavy-tailed batches (log-normal track counts up to 1500): events of
+# 1000-1500 tracks drive the logits beyond 100, and the deep layers' absolute
+# rounding error with them; emulated BF16 over the 176 events of the
+# 4096-event batch with at least 1000 tracks or sampled by the GPU test:
+# max|dp| 0.176 (median 0.033).
+P_ABS_HEAVY = {"bf16": 0.22}
+MATCH_MIN_HEAVY = {"bf16": 0.95}
 
 
 def match_vertices(z_gpu, z_ref, tol=DZ_MATCH):

@@ -11,7 +11,7 @@ import pytest
 import oracle
 from synth import make_events
 from tests import parity
-from tests.gpu_util import torch_cuda, make_engine, run, weights, fp8_calibration
+from tests.gpu_util import torch_cuda, make_engine, run, weights, fp8_calibration, geometry
 
 pytestmark = pytest.mark.gpu
 DT = "fp8_e4m3"
@@ -112,6 +112,7 @@ def test_vertices_agree(fp8, ref16):
     say(f"vertices matched {matched}/{total}, extra {extra}")
     assert matched >= parity.MATCH_MIN[DT] * total
     assert extra <= parity.EXTRA_MAX[DT] * total
+    parity.exact_peaks_all(out, geometry(eng))
 
 
 def test_deterministic_and_batch_invariant(fp8, batch16):
@@ -167,6 +168,7 @@ def test_full_batch_sampled(amax):
         dp = float(np.max(np.abs(out["prob"][e] - ref[k]["p"])))
         say(f"event {e} max |dp| {dp:.3e}")
         assert dp <= parity.P_ABS[DT]
+    parity.exact_peaks_all(out, geometry(eng))
     eng.close()
 
 

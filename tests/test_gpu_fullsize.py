@@ -2,7 +2,9 @@
 times: 1000 events (Poisson(180) tracks) and 4096 heavy-tailed events
 (log-normal track counts, median 180, clipped to [5, 1500]).  The oracle
 checks a sample of events one by one (first, last, largest, random); every
-event's result must also equal, bit for bit, that event run alone."""
+event's vertex list is checked index-exactly against the oracle's peak finder
+on the GPU's own p; every sampled event's result must also equal, bit for
+bit, that event run alone."""
 
 import numpy as np
 import pytest
@@ -36,9 +38,14 @@ def test_full_batch_sampled(n_events, mix):
     for k, e in enumerate(sample):
         err = parity.max_rel(out["prob"][e], ref[k]["p"])
         bins, z, h, S = event_vertices(out, e)
-        amb, n = parity.compare_peaks(bins, z, h, S, ref[k], geo)
-        say(f"event {e} T={T[e]} max rel {err:.2e} peaks {n} ambiguous {amb}")
+        amb, sat, n = parity.ambiguity(ref[k], geo)
+        parity.compare_peaks(bins, z, h, S, ref[k], geo)
+        say(f"event {e} T={T[e]} max|logit| {np.abs(ref[k]['logit']).max():.1f} max rel {err:.2e} "
+            f"vertices {n} ambiguous {amb} ({amb / n:.2%}; saturated {sat}, "
+            f"other {amb - sat} <= {parity.AMB_MAX_FRAC:.1%} of {n})")
         assert err <= parity.P_REL
+    nv = parity.exact_peaks_all(out, geo)
+    say(f"exact peaks on the GPU's p, all {n_events} events: {nv} vertices, no exclusions")
     # batch invariance on the same sample
     alone_eng = make_engine(len(sample))
     alone = run(alone_eng, batch.subset(sample))

@@ -1,12 +1,15 @@
 """The whole path as one HIP graph, and the persistent work-queue track stage
 (one persistent launch for batches with uneven track counts): both must
-reproduce the eager, one-block-per-event results bit for bit."""
+reproduce the eager, one-block-per-event results bit for bit, and the
+heavy-tailed BF16 configuration run that way is checked against the oracle."""
 
 import numpy as np
 import pytest
 
+import oracle
 from synth import make_events
-from tests.gpu_util import torch_cuda, engine_for, run
+from tests import parity
+from tests.gpu_util import torch_cuda, engine_for, run, weights, geometry
 
 pytestmark = pytest.mark.gpu
 
@@ -64,4 +67,59 @@ def test_graph_replays_match_eager(dtype):
     eng.graph_launch()
     eng.synchronize()
     assert np.array_equal(out.to_host()["prob"], ref["prob"][::-1])
+    eng.close()
+
+
+def test_heavy_tailed_bf16_graph_autotuned_vs_oracle():
+    """4096 events with log-normal track counts (median 180, clipped to
+    [5, 1500]) in BF16: work-queue track stage, tile variants picked by the
+    autotuner on this batch, the whole path captured as one HIP graph and
+    replayed twice.  Every replay equals the eager run bit for bit; sampled
+    events (first, last, largest, smallest, four random) are within the
+    heavy-tailed BF16 bounds of the oracle; every event's vertex list is
+    index-exact against the oracle's peak finder on the GPU's own p."""
+    torch = torch_cuda()
+    import paper_2602_19959_amd as pv
+    E = 4096
+    batch = make_events(E, seed=0, mix="lognormal")
+    T = np.diff(batch.offsets)
+    say(f"heavy-tailed bf16: E={E} tracks {T.sum()} max {T.max()}")
+    eng = engine_for(E, "bf16")
+    eng.set_track_schedule(True)
+    feat, off = pv.upload_events(batch)
+    out = eng.alloc_outputs(E)
+    picked = eng.autotune(feat, off, out, reps=1)
+    say("autotuned variants", picked)
+    eng.execute(feat, off, out)
+    eng.synchronize()
+    eager = out.to_host()
+    eng.graph_capture(feat, off, out)
+    for rep in range(2):
+        out.prob.zero_()
+        out.n_vertices.zero_()
+        eng.graph_launch()
+        eng.synchronize()
+        h = out.to_host()
+        for k in ("prob", "z", "integral", "n_vertices", "status", "bin"):
+            assert np.array_equal(h[k], eager[k]), (rep, k)
+        say("replay", rep, "equals eager")
+    assert np.all((h["status"] & 3) == 0)
+    rng = np.random.default_rng(E)
+    sample = sorted(set([0, E - 1, int(np.argmax(T)), int(np.argmin(T))] +
+                        rng.choice(E, 4, replace=False).tolist()))
+    ref = oracle.run_batch(batch.subset(sample), weights())
+    matched = extra = total = 0
+    for k, e in enumerate(sample):
+        dp = float(np.max(np.abs(h["prob"][e] - ref[k]["p"])))
+        n = int(h["n_vertices"][e])
+        m = parity.match_vertices(h["z"][e, :n], ref[k]["z"])
+        matched += m
+        extra += n - m
+        total += len(ref[k]["z"])
+        say(f"event {e} T={T[e]} max|dp| {dp:.3e} matched {m}/{len(ref[k]['z'])}")
+        assert dp <= parity.P_ABS_HEAVY["bf16"], e
+    assert matched >= parity.MATCH_MIN_HEAVY["bf16"] * total
+    assert extra <= parity.EXTRA_MAX["bf16"] * total
+    nv = parity.exact_peaks_all(h, geometry(eng))
+    say(f"exact peaks on the GPU's p, all {E} events: {nv} vertices")
     eng.close()

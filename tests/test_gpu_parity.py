@@ -4,7 +4,8 @@ Workloads (seeded, synthetic, see synth/): the 8-event parity batch
 (Poisson(180) tracks, Poisson(5.6) vertices), the 1000-event production
 batch, and heavy-tailed batches (log-normal track counts up to 1500).
 Bars (tests/parity.py): p within 1e-4 relative, identical peak sets on every
-robust decision, histogram exact where it is zero.
+robust decision, histogram exact where it is zero, and every event's vertex
+list index-exact against the oracle's peak finder run on the GPU's own p.
 """
 
 import numpy as np
@@ -64,6 +65,8 @@ def test_peak_parity(eng8, out8, ref8):
         total_amb += amb
     say("ambiguous decisions excluded:", total_amb)
     assert total_amb < 100
+    nv = parity.exact_peaks_all(out8, geo)
+    say(f"exact peaks on the GPU's p: {nv} vertices, no exclusions")
 
 
 def test_status_ok(out8, ref8):
@@ -117,6 +120,7 @@ def test_parity_other_seeds(eng_seeds, seed):
         total_amb += amb
     say(f"seed {seed}: ambiguous decisions excluded:", total_amb)
     assert total_amb < 100
+    parity.exact_peaks_all(out, geo)
 
 
 LAYERS = ["enc0.c2", "pool0", "enc1.c2", "pool1", "enc2.c2", "pool2", "enc3.c1", "enc3.c2",
@@ -178,6 +182,7 @@ def test_edge_events(eng8):
         assert parity.max_rel(out["prob"][e], refs[e]["p"]) <= parity.P_REL, e
         bins, z, h, S = event_vertices(out, e)
         parity.compare_peaks(bins, z, h, S, refs[e], geo)
+    parity.exact_peaks_all(out, geo)
     assert out["status"][0] == 0 and out["status"][1] == 0 and out["status"][3] == 0
     assert out["status"][2] == pv.EV_TRACKS_DROPPED
     # over the cap: bypassed, neighbours unchanged
@@ -187,6 +192,7 @@ def test_edge_events(eng8):
     assert res["status"][3] & pv.EV_TOO_MANY_TRACKS
     assert res["status"][0] == 0 and np.array_equal(res["prob"][0], out["prob"][0])
     assert np.array_equal(res["prob"][1], out["prob"][1])
+    parity.exact_peaks_all(res, geo)
     # decreasing offsets: bypass that event only
     feat, off = pv.upload_events(batch)
     bad = off.clone()
@@ -215,6 +221,7 @@ def test_peaks_other_windows(batch8, ref8, hw, s_min):
         bins, z, h, S = event_vertices(out, e)
         parity.compare_peaks(bins, z, h, S, ref, geo)
         kept += len(bins)
+    assert parity.exact_peaks_all(out, geo) == kept
     say(f"hw {hw} s_min {s_min}: {kept} vertices")
     eng.close()
 
@@ -240,6 +247,7 @@ def test_longest_histogram():
         bins, z, h, S = event_vertices(out, e)
         parity.compare_peaks(bins, z, h, S, ref, geo)
         assert out["status"][e] == 0
+    parity.exact_peaks_all(out, geo)
     eng.close()
 
 
@@ -289,6 +297,7 @@ def test_ragged_shapes(dtype):
         else:
             assert float(np.max(np.abs(out["prob"][e] - refs[e]["p"]))) <= parity.P_ABS[dtype], e
         assert (out["status"][e] & ~pv_dropped()) == 0
+    parity.exact_peaks_all(out, geo)
     eng.close()
 
 
@@ -307,6 +316,7 @@ def test_peak_truncation():
     ref = oracle.run_event(batch.tracks_of(0), w)
     assert out["n_vertices"][0] == 10 and out["status"][0] & pv.EV_PEAKS_TRUNCATED
     assert np.array_equal(out["bin"][0, :10], ref["t"][:10])
+    parity.exact_peaks_all(out, geometry(e))
     e.close()
 
 

@@ -8,7 +8,7 @@ import pytest
 import oracle
 from synth import make_events
 from tests import parity
-from tests.gpu_util import torch_cuda, make_engine, run, weights
+from tests.gpu_util import torch_cuda, make_engine, run, weights, geometry
 
 pytestmark = pytest.mark.gpu
 
@@ -58,6 +58,8 @@ def test_vertices_agree(lp, ref16):
     say(dt, f"vertices matched {matched}/{total}, extra {extra}")
     assert matched >= parity.MATCH_MIN[dt] * total
     assert extra <= parity.EXTRA_MAX[dt] * total
+    # the peak finder itself is exact whatever the UNet's precision
+    parity.exact_peaks_all(out, geometry(eng))
 
 
 def test_deterministic_and_batch_invariant(lp, batch16):
@@ -115,6 +117,7 @@ def test_full_batch_sampled(lp):
         dp = float(np.max(np.abs(out["prob"][e] - ref[k]["p"])))
         say(dt, f"event {e} max |dp| {dp:.3e}")
         assert dp <= parity.P_ABS[dt]
+    parity.exact_peaks_all(out, geometry(eng))
     eng.close()
 
 
@@ -144,9 +147,11 @@ def test_edge_events_reduced_precision(dtype):
         assert dp <= parity.P_ABS[dtype], (e, dp)
     assert out["status"][0] == 0 and out["status"][1] == 0 and out["status"][3] == 0
     assert out["status"][2] == pv.EV_TRACKS_DROPPED
+    parity.exact_peaks_all(out, geometry(eng))
     eng.close()
     capped = engine_for(4, dtype, max_tracks_per_event=50)
     res = run(capped, batch)
+    parity.exact_peaks_all(res, geometry(capped))
     assert res["status"][2] & pv.EV_TOO_MANY_TRACKS and res["n_vertices"][2] == 0
     assert res["status"][0] == 0 and np.array_equal(res["prob"][0], out["prob"][0])
     capped.close()

@@ -1,13 +1,16 @@
 """Continuous-batching serving: requests admitted into a fixed HBM pool,
 packed event by event into steps on two lanes whose work overlaps, must give
 every event the same bits as the slice run alone (the FP32, BF16 and FP8
-kernels are batch-invariant)."""
+kernels are batch-invariant), and sampled served events must agree with the
+FP64 oracle."""
 
 import numpy as np
 import pytest
 
+import oracle
 from synth import make_events
-from tests.gpu_util import torch_cuda, blob, engine_for, run, fp8_calibration
+from tests import parity
+from tests.gpu_util import torch_cuda, blob, engine_for, run, fp8_calibration, weights, geometry
 
 pytestmark = pytest.mark.gpu
 
@@ -39,8 +42,41 @@ def test_results_same_alone_and_in_the_mix(dtype, realtime):
             n = int(alone["n_vertices"][e])
             for k in ("z", "peak_prob", "integral", "bin"):
                 assert np.array_equal(r.result[k][e, :n], alone[k][e, :n]), (r.rid, e, k)
+    check_served_against_oracle(reqs, dtype, geometry(eng))
     eng.close()
     srv.close()
+
+
+def check_served_against_oracle(reqs, dtype, geo):
+    """Sampled served events against the oracle: the first event of the first
+    four requests, the last event of the last one, and the events with the
+    most and the fewest tracks.  FP32: the same peak set on every robust
+    decision, z within 1e-4 mm, heights and window sums within 1e-4 relative.
+    BF16 and FP8: vertex agreement within the stated floors (the requests cut
+    heavy-tailed events, so BF16 takes its heavy-tailed floor; the served
+    results carry no per-bin p, so FP8 is held to vertex agreement)."""
+    picks = [(r, 0) for r in reqs[:4]] + [(reqs[-1], reqs[-1].n_events - 1)]
+    allev = [(r, e) for r in reqs for e in range(r.n_events)]
+    ntr = [int(np.diff(r.batch.offsets)[e]) for r, e in allev]
+    picks += [allev[int(np.argmax(ntr))], allev[int(np.argmin(ntr))]]
+    w = weights()
+    matched = extra = total = 0
+    for r, e in picks:
+        ref = oracle.run_event(r.batch.tracks_of(e), w, geo)
+        n = int(r.result["n_vertices"][e])
+        bins, z = r.result["bin"][e, :n], r.result["z"][e, :n]
+        h, S = r.result["peak_prob"][e, :n], r.result["integral"][e, :n]
+        if dtype == "fp32":
+            parity.compare_peaks(bins, z, h, S, ref, geo)
+        m = parity.match_vertices(z, ref["z"])
+        matched += m
+        extra += n - m
+        total += len(ref["z"])
+    say(dtype, f"served events vs oracle: {len(picks)} events, vertices matched {matched}/{total}, extra {extra}")
+    if dtype != "fp32":        # FP32 is held to the robust peak set above
+        floor = {"bf16": parity.MATCH_MIN_HEAVY["bf16"], "fp8_e4m3": parity.MATCH_MIN["fp8_e4m3"]}[dtype]
+        assert matched >= floor * total
+        assert extra <= parity.EXTRA_MAX[dtype] * total
 
 
 def test_admission_waits_for_pool_space():

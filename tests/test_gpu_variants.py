@@ -36,6 +36,7 @@ def check_fp32(eng, batch, out, w):
         bins, z, h, S = event_vertices(out, e)
         amb, _ = parity.compare_peaks(bins, z, h, S, refs[e], geo)
         amb_total += amb
+    parity.exact_peaks_all(out, geo)
     return refs, amb_total
 
 
@@ -79,6 +80,7 @@ def test_wide_unet_low_precision(dt):
     say(dt, "max |dp| %.3e, vertices matched %d/%d" % (dp, matched, total))
     assert dp <= parity.P_ABS_WIDE[dt]
     assert matched >= parity.MATCH_MIN_WIDE[dt] * total
+    parity.exact_peaks_all(out, geometry(eng))
     eng.close()
 
 
@@ -169,4 +171,5 @@ def test_interval_layout_bf16():
     dp = max(float(np.max(np.abs(out["prob"][e] - refs[e]["p"]))) for e in range(6))
     say("interval layout bf16 max |dp| %.3e" % dp)
     assert dp <= parity.P_ABS["bf16"]
+    parity.exact_peaks_all(out, geometry(eng))
     eng.close()
