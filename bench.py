@@ -13,8 +13,15 @@ event, times the events of one launch) over its average launch duration,
 measured with HIP events recorded by the library on the stream the kernels
 run on, against the MI355X dense FP32 matrix peak (157.3 TFLOP/s).
 
-CPU baseline: the FP64 oracle (plain C, threads over events) on a bounded
-sample of the same batch, on the host cores this process may use (at most 16).
+CPU baseline: the FP64 oracle (plain C, threads over events; rebuilt for
+this host's CPU when gcc is there) on a bounded sample of the same batch, on
+the host cores this process may use (its affinity set, capped by
+OMP_NUM_THREADS when that names the process's CPU share).
+
+The same line also carries, measured in the same run: the BF16, FP16 and FP8
+paths on the same batch (other_dtypes), the heavy-tailed 4096-event BF16
+batch run as one captured HIP graph with autotuned tiles (heavy_tailed), and
+a short continuous-batching serving pass in FP32 and BF16 (serving).
 """
 
 import argparse
@@ -37,6 +44,8 @@ HBM_PEAK_GBS = 8000.0
 STATED_TOL = {"bf16": {"max_abs_dp": 2e-2, "vertices_matched_min": 0.995, "extra_vertices_max": 0.005},
               "fp16": {"max_abs_dp": 5e-3, "vertices_matched_min": 0.999, "extra_vertices_max": 0.001},
               "fp8_e4m3": {"max_abs_dp": 0.3, "vertices_matched_min": 0.95, "extra_vertices_max": 0.05}}
+# the heavy-tailed batch (log-normal track counts up to 1500) in BF16
+STATED_TOL_HEAVY = {"bf16": {"max_abs_dp": 0.22, "vertices_matched_min": 0.95, "extra_vertices_max": 0.005}}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = {"conv_mfma_f32": "conv_kernel.hip", "conv_mfma_lp": "conv_lp_kernel.hip",
                   "track_stage": "track_kernel.hip", "peak_finder": "peaks_kernel.hip",
@@ -103,16 +112,42 @@ def layer_bytes(spec, eb):
 
 
 def cpu_threads():
+    """(threads to use, affinity size, OMP_NUM_THREADS or None): every core
+    of this process's affinity set, unless OMP_NUM_THREADS names a smaller
+    CPU share for the process."""
     try:
-        n = len(os.sched_getaffinity(0))
+        aff = len(os.sched_getaffinity(0))
     except AttributeError:
-        n = os.cpu_count() or 1
-    return max(1, min(n, 16))
+        aff = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS")
+    share = int(omp) if omp and omp.isdigit() and int(omp) > 0 else None
+    return max(1, min(aff, share) if share else aff), aff, share
+
+
+def native_oracle():
+    """Build the oracle for this host's CPU (-march=native, same source and
+    otherwise the same flags: no fast-math, no contraction, so the same
+    results) into a temporary directory and point the oracle module at it.
+    Returns the flags used; the shipped build stays in use if gcc fails."""
+    import subprocess
+    import tempfile
+    from oracle import build as ob
+    d = tempfile.mkdtemp(prefix="pvf_oracle_native_")
+    lib = os.path.join(d, "libpvf_oracle_native.so")
+    cmd = ["gcc", "-std=c11", "-O2", "-march=native", "-fPIC", "-shared", "-ffp-contract=off",
+           "-fno-fast-math", "-o", lib, ob.SRC, "-lm"]
+    try:
+        subprocess.run(cmd, check=True, capture_output=True, timeout=120)
+    except (OSError, subprocess.SubprocessError):
+        return "shipped build (-O2)"
+    os.environ["PVF_ORACLE_LIB"] = lib
+    return "-O2 -march=native -ffp-contract=off"
 
 
 def cpu_baseline(batch, w, target_s):
+    flags = native_oracle()
     import oracle
-    threads = cpu_threads()
+    threads, aff, share = cpu_threads()
     t0 = time.perf_counter()
     oracle.run_batch(batch.subset([0]), w, threads=1)
     t_one = time.perf_counter() - t0
@@ -131,60 +166,149 @@ def cpu_baseline(batch, w, target_s):
     except OSError:
         pass
     return {"value": n / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} events of the same batch, FP64 C oracle, {threads} threads, "
-                      f"{dt:.1f} s wall on {cpu}"}
+            "cpu_model": cpu, "cpu_count": os.cpu_count(), "affinity_cores": aff, "omp_num_threads": share,
+            "build": flags,
+            "sample": f"first {n} events of the same batch, FP64 C oracle ({flags}), {threads} threads "
+                      f"(affinity {aff} cores, OMP_NUM_THREADS {share}), {dt:.1f} s wall on {cpu}"}
+
+
+def fp8_calibration_table(pv, blob, n_events, seed, mix, variant=None):
+    """Set-up, outside every timed region: per-channel scales for an FP8
+    engine from an FP32 run over other events."""
+    import numpy as np
+    from synth import make_events
+    cb = make_events(n_events, seed=seed, mix=mix)
+    CT = np.diff(cb.offsets)
+    cspec = pv.default_spec(max_events=cb.n_events, max_tracks_total=int(max(CT.sum(), 1)),
+                            max_tracks_per_event=max(1500, int(CT.max())), **(variant or {}))
+    ceng = pv.Engine(blob, cspec)
+    cf, co = pv.upload_events(cb)
+    amax = ceng.calibrate(cf, co)
+    ceng.close()
+    return amax
+
+
+def serve_pass(dtype, blob, pool_events, n_requests, loads, seed, pool_gb=8.0, lanes=2, results="host",
+               warm=False, amax=None):
+    """Continuous-batching serving of one dtype: capacity with every request
+    queued at once, then Poisson arrivals at the given fractions of that
+    capacity.  Requests arrive with their features in page-locked host
+    memory; the consumer callback takes each request's results where the
+    server leaves them (results="host": page-locked host blocks; "device":
+    HBM) and drops them."""
+    import numpy as np
+    from paper_2602_19959_amd.serve import Server, poisson_requests
+
+    srv = Server(blob, pool_bytes=int(pool_gb * (1 << 30)), lanes=lanes, compute_dtype=dtype, fp8_amax=amax,
+                 results=results)
+    print(f"[serve] {dtype} pool {pool_gb} GB, {lanes} lanes x {srv.lane_events} events, results on {results}",
+          file=sys.stderr, flush=True)
+    consume = lambda r: None
+    if warm:
+        # steady state of a long-running server (allocator caches filled)
+        srv.run(poisson_requests(1e9, n_requests, seed + 7, pool_events, pinned=True), realtime=False,
+                on_complete=consume)
+    reqs = poisson_requests(1e9, n_requests, seed + 8, pool_events, pinned=True)
+    cap = srv.run(reqs, realtime=False, on_complete=consume).summary()
+    print(f"[serve] {dtype} capacity {cap['events_per_s']:.0f} events/s", file=sys.stderr, flush=True)
+    mean_size = float(np.mean([r.n_events for r in reqs]))
+    out = {"capacity": cap, "lane_events": srv.lane_events, "results_on": results, "loads": {}}
+    for f in loads:
+        rate = f * cap["events_per_s"] / mean_size
+        rq = poisson_requests(rate, n_requests, seed + 9, pool_events, pinned=True)
+        out["loads"][f"{f:.2f}"] = dict(srv.run(rq, realtime=True, on_complete=consume).summary(),
+                                        offered_requests_per_s=rate)
+        print(f"[serve] {dtype} load {f:.2f}: {out['loads'][f'{f:.2f}']}", file=sys.stderr, flush=True)
+    srv.close()
+    return out
 
 
 def serve_bench(args):
     """Continuous-batching serving: capacity with every request queued at
     once, then Poisson arrivals at fractions of that capacity."""
-    import numpy as np
-    from paper_2602_19959_amd.serve import Server, poisson_requests
+    import paper_2602_19959_amd as pv
     from synth import make_events, make_weights, weights_to_blob
 
     blob = weights_to_blob(make_weights(args.seed))
     pool_events = make_events(8000, seed=args.seed + 1, mix="lognormal")
-    amax = None
-    if args.dtype == "fp8_e4m3":
-        import paper_2602_19959_amd as pv
-        cb = make_events(args.calib_events, seed=args.seed + 5, mix="lognormal")
-        CT = np.diff(cb.offsets)
-        ceng = pv.Engine(blob, pv.default_spec(max_events=cb.n_events, max_tracks_total=int(max(CT.sum(), 1)),
-                                               max_tracks_per_event=max(1500, int(CT.max()))))
-        cf, co = pv.upload_events(cb)
-        amax = ceng.calibrate(cf, co)
-        ceng.close()
-    srv = Server(blob, pool_bytes=int(args.pool_gb * (1 << 30)), lanes=args.lanes, compute_dtype=args.dtype,
-                 fp8_amax=amax)
-    print(f"[serve] {args.dtype} pool {args.pool_gb} GB, {args.lanes} lanes x {srv.lane_events} events",
-          file=sys.stderr, flush=True)
-    # steady state: a first pass of the same size fills the host allocator's
-    # cache of pinned buffers (feature staging and result copies), as a
-    # long-running server's would be; its results are dropped
-    warm = poisson_requests(1e9, args.serve_requests, args.seed + 7, pool_events)
-    srv.run(warm, realtime=False)
-    del warm
-    reqs = poisson_requests(1e9, args.serve_requests, args.seed + 8, pool_events)
-    cap = srv.run(reqs, realtime=False).summary()
-    print(f"[serve] capacity {cap['events_per_s']:.0f} events/s", file=sys.stderr, flush=True)
-    mean_size = float(np.mean([r.n_events for r in reqs]))
-    loads = {}
-    for f in [float(x) for x in args.serve_loads.split(",")]:
-        rate = f * cap["events_per_s"] / mean_size
-        rq = poisson_requests(rate, args.serve_requests, args.seed + 9, pool_events)
-        loads[f"{f:.2f}"] = dict(srv.run(rq, realtime=True).summary(), offered_requests_per_s=rate)
-        print(f"[serve] load {f:.2f}: {loads[f'{f:.2f}']}", file=sys.stderr, flush=True)
-    srv.close()
+    amax = (fp8_calibration_table(pv, blob, args.calib_events, args.seed + 5, "lognormal")
+            if args.dtype == "fp8_e4m3" else None)
+    res = serve_pass(args.dtype, blob, pool_events, args.serve_requests,
+                     [float(x) for x in args.serve_loads.split(",")], args.seed, args.pool_gb, args.lanes,
+                     args.results, warm=args.serve_warm, amax=amax)
+    cap = res["capacity"]
     print(json.dumps({
         "metric": METRIC, "value": cap["events_per_s"], "unit": "events/s", "n_gpus": 1,
         "higher_is_better": True, "dtype": DTYPE_TAG[args.dtype], "data": "synthetic",
         "config": {"workload": f"serving: slices of U{{100..2000}} events (log-normal track counts), "
                                f"Poisson arrivals, {args.pool_gb} GB HBM pool, {args.lanes} lanes of "
-                               f"{srv.lane_events} events, continuous batching",
-                   "requests": args.serve_requests},
-        "capacity": cap, "loads": loads,
+                               f"{res['lane_events']} events, continuous batching, results on {args.results}",
+                   "requests": args.serve_requests, "warm_pass": bool(args.serve_warm)},
+        "capacity": cap, "loads": res["loads"],
         "budget_us_per_event": 400.0,
     }), flush=True)
+
+
+def heavy_tailed_pass(args, blob):
+    """The heavy-tailed batch in BF16 as a batching configuration: 4096 events
+    with log-normal track counts (median 180, clipped to [5, 1500]), the
+    work-queue track stage, tile variants picked by the autotuner on this
+    batch, the whole path captured as one HIP graph; K graph replays timed
+    with HIP events on the engine's stream."""
+    import numpy as np
+    import torch
+    import paper_2602_19959_amd as pv
+    from synth import make_events
+
+    E = 4096
+    batch = make_events(E, seed=args.seed, mix="lognormal")
+    T = np.diff(batch.offsets)
+    spec = pv.default_spec(max_events=E, max_tracks_total=int(T.sum()), compute_dtype="bf16",
+                           max_tracks_per_event=max(1500, int(T.max())))
+    eng = pv.Engine(blob, spec)
+    eng.set_track_schedule(True)
+    feat, off = pv.upload_events(batch)
+    out = eng.alloc_outputs(E, with_prob=False)
+    t_tune = time.perf_counter()
+    eng.autotune(feat, off, out, reps=1)
+    t_tune = time.perf_counter() - t_tune
+    eng.graph_capture(feat, off, out)
+    s = eng.stream
+    for _ in range(3):
+        eng.graph_launch()
+    s.synchronize()
+    steps = max(5, args.steps // 5)
+    ms = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        eng.graph_launch()
+        e1.record(s)
+        s.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    wall = time.perf_counter() - t0
+    eng.profile(True)
+    eng.execute(feat, off, out)
+    s.synchronize()
+    split = eng.profile_read()
+    eng.profile(False)
+    host = out.to_host()
+    eng.close()
+    if np.any(host["status"] & (pv.EV_TOO_MANY_TRACKS | pv.EV_BAD_INPUT)):
+        print("[bench] unexpected bypassed events in the heavy-tailed batch", file=sys.stderr)
+        sys.exit(1)
+    us = sorted(m * 1e3 / E for m in ms)
+    res = {"value": E * steps / wall, "unit": "events/s", "dtype": "bf16", "steps": steps,
+           "ms_per_step": wall / steps * 1e3,
+           "p50_us_per_event": statistics.median(us), "p99_us_per_event": us[min(len(us) - 1, int(round(0.99 * (len(us) - 1))))],
+           "config": {"workload": f"{E} events, log-normal track counts (median 180, clipped to [5, 1500]; "
+                                  f"mean {T.mean():.1f}, max {int(T.max())}), work-queue track stage, autotuned "
+                                  f"tiles ({t_tune:.1f} s set-up), one HIP graph per step"},
+           "stages_ms_eager": {"track": split[0], "unet": sum(split[1:-1]), "peaks": split[-1]},
+           "stated_tolerance": STATED_TOL_HEAVY["bf16"]}
+    print(f"[bench] heavy-tailed bf16 graph: {res['value']:.0f} events/s", file=sys.stderr, flush=True)
+    return res
 
 
 def gemm_yardstick(args):
@@ -294,6 +418,12 @@ def main():
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
     ap.add_argument("--pool-gb", type=float, default=8.0)
     ap.add_argument("--lanes", type=int, default=2)
+    ap.add_argument("--results", default="host", choices=["host", "device"],
+                    help="serving: results back to page-locked host memory, or left in HBM for device consumers")
+    ap.add_argument("--serve-warm", action="store_true",
+                    help="serving: a first, untimed pass of the same size before the measured ones")
+    ap.add_argument("--no-extras", dest="extras", action="store_false",
+                    help="default run: skip the heavy-tailed graph pass and the short serving pass")
     ap.add_argument("--autotune", action="store_true",
                     help="time every tile variant per launch first and keep the fastest (the built-in "
                          "defaults are the picks of such sweeps on this workload)")
@@ -347,16 +477,9 @@ def main():
         if dtype == "fp8_e4m3":
             # set-up, before and outside the timed region: channel scales from an
             # FP32 run over other events
-            cb = make_events(args.calib_events, seed=args.seed + 5, mix=args.mix)
-            CT = np.diff(cb.offsets)
-            cspec = pv.default_spec(max_events=cb.n_events, max_tracks_total=int(max(CT.sum(), 1)),
-                                    max_tracks_per_event=max(1500, int(CT.max())), **variant)
-            ceng = pv.Engine(weights_to_blob(w), cspec)
-            cf, co = pv.upload_events(cb)
-            amax = ceng.calibrate(cf, co)
-            ceng.close()
-            del cf, co
-            print(f"[bench] FP8 calibration over {cb.n_events} events: {amax.size} channel scales",
+            amax = fp8_calibration_table(pv, weights_to_blob(w), args.calib_events, args.seed + 5, args.mix,
+                                         variant)
+            print(f"[bench] FP8 calibration over {args.calib_events} events: {amax.size} channel scales",
                   file=sys.stderr, flush=True)
         eng = pv.Engine(weights_to_blob(w), spec, fp8_amax=amax)
         eng.set_track_schedule(args.schedule == "queue")
@@ -540,7 +663,7 @@ def main():
         # the same batch and timing in the reduced-precision paths, each with
         # the error bound the GPU tests hold it to against the FP64 oracle
         result["other_dtypes"] = {}
-        for dt in ("bf16", "fp8_e4m3"):
+        for dt in ("bf16", "fp16", "fp8_e4m3"):
             r, e2 = measure(dt, 0)
             e2.close()
             result["other_dtypes"][dt] = {
@@ -551,6 +674,20 @@ def main():
                                                            "traffic")},
                 "stated_tolerance": STATED_TOL[dt]}
             print(f"[bench] {dt}: {r['value']:.0f} events/s", file=sys.stderr, flush=True)
+    default_run = (args.dtype == "fp32" and args.width == 32 and args.layout == "event" and levels == 4
+                   and args.boundary_mm == 0 and args.mix == "poisson" and E == 1000)
+    if args.extras and default_run:
+        blob = weights_to_blob(w)
+        result["heavy_tailed"] = heavy_tailed_pass(args, blob)
+        pool_events = make_events(4000, seed=args.seed + 1, mix="lognormal")
+        result["serving"] = {
+            "workload": "slices of U{100..2000} events (log-normal track counts), 40 requests per pass, "
+                        "8 GB HBM pool, 2 lanes, continuous batching, features arriving in page-locked host "
+                        "memory, no warm-up pass; capacity with all requests queued, then Poisson arrivals "
+                        "at 0.8 of it; latency from arrival to results in host memory",
+            "budget_us_per_event": 400.0}
+        for dt in ("fp32", "bf16"):
+            result["serving"][dt] = serve_pass(dt, blob, pool_events, 40, [0.8], args.seed)
     if not args.no_cpu_baseline:
         print("[bench] CPU baseline (FP64 oracle)...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(batch, w, args.cpu_seconds)

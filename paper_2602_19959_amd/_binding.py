@@ -244,8 +244,9 @@ class Engine:
 
     def _views(self, feat, offsets, out: Outputs):
         t = self._torch
-        if feat.dtype != t.float32 or feat.dim() != 2 or feat.shape[0] != N_FEAT or not feat.is_contiguous():
-            raise ValueError("feat must be a contiguous float32 [9][T] device tensor")
+        if feat.dtype != t.float32 or feat.dim() != 2 or feat.shape[0] != N_FEAT or \
+                (feat.shape[1] > 1 and feat.stride(1) != 1):
+            raise ValueError("feat must be a float32 [9][T] device tensor with contiguous rows")
         if offsets.dtype != t.int32 or offsets.dim() != 1 or not offsets.is_contiguous():
             raise ValueError("offsets must be a contiguous int32 [E+1] device tensor")
         if feat.device != self.device or offsets.device != self.device:
@@ -256,8 +257,8 @@ class Engine:
         tr.n_events = n_events
         tr.n_tracks_total = T
         tr.d_event_offsets = offsets.data_ptr()
-        for k in range(N_FEAT):
-            tr.d_feat[k] = feat.data_ptr() + 4 * k * T if T > 0 else None
+        for k in range(N_FEAT):          # one pointer per SoA plane (row)
+            tr.d_feat[k] = feat.data_ptr() + 4 * k * feat.stride(0) if T > 0 else None
         v = Vertices()
         v.d_n_vertices = out.n_vertices.data_ptr()
         v.d_z = out.z.data_ptr()

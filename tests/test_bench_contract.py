@@ -19,6 +19,44 @@ def test_stated_tolerances_are_the_tested_ones():
         assert tol["max_abs_dp"] == parity.P_ABS[dt]
         assert tol["vertices_matched_min"] == parity.MATCH_MIN[dt]
         assert tol["extra_vertices_max"] == parity.EXTRA_MAX[dt]
+    for dt, tol in bench.STATED_TOL_HEAVY.items():
+        assert tol["max_abs_dp"] == parity.P_ABS_HEAVY[dt]
+        assert tol["vertices_matched_min"] == parity.MATCH_MIN_HEAVY[dt]
+        assert tol["extra_vertices_max"] == parity.EXTRA_MAX[dt]
+
+
+def test_cpu_baseline_threads_follow_the_process_share(monkeypatch):
+    """Every core of the affinity set, unless OMP_NUM_THREADS names a smaller
+    share; the count and the share are reported."""
+    aff = len(os.sched_getaffinity(0))
+    monkeypatch.delenv("OMP_NUM_THREADS", raising=False)
+    assert bench.cpu_threads() == (aff, aff, None)
+    monkeypatch.setenv("OMP_NUM_THREADS", "1")
+    assert bench.cpu_threads() == (1, aff, 1)
+    monkeypatch.setenv("OMP_NUM_THREADS", str(aff + 100))
+    assert bench.cpu_threads() == (aff, aff, aff + 100)
+
+
+def test_native_oracle_build_gives_the_same_results(monkeypatch, tmp_path):
+    """The CPU-baseline build for the host CPU (-march=native) computes the
+    same numbers as the shipped build (no fast-math, no contraction)."""
+    import numpy as np
+    import oracle
+    from synth import make_events, make_weights
+    ev = make_events(1, seed=3)
+    w = make_weights(0)
+    ref = oracle.run_event(ev.tracks_of(0), w)
+    monkeypatch.delenv("PVF_ORACLE_LIB", raising=False)
+    flags = bench.native_oracle()
+    assert "native" in flags
+    lib = os.environ["PVF_ORACLE_LIB"]
+    dst = str(tmp_path / "p.npy")
+    code = ("import numpy as np, oracle; from synth import make_events, make_weights; "
+            "r = oracle.run_event(make_events(1, seed=3).tracks_of(0), make_weights(0)); "
+            f"np.save({dst!r}, r['p'])")
+    subprocess.run([sys.executable, "-c", code], env=dict(os.environ, PVF_ORACLE_LIB=lib), cwd=ROOT,
+                   capture_output=True, timeout=120, check=True)
+    assert np.array_equal(np.load(dst), ref["p"])
 
 
 def test_unet_flops_closed_form():

@@ -95,3 +95,43 @@ def test_admission_waits_for_pool_space():
     assert stats.summary()["requests"] == 6
     assert stats.max_pool_used <= budget
     srv.close()
+
+
+def test_device_results_and_oversized_request():
+    """results="device" (outputs left in HBM for consumers on the GPU, the
+    Extract phase of Section 3) gives the same bits as running each slice
+    alone; a request whose state can never fit beside the lanes is rejected
+    with an error while every other request is served."""
+    torch = torch_cuda()
+    from paper_2602_19959_amd.serve import Server, poisson_requests
+    pool = make_events(300, seed=23, mix="lognormal")
+    reqs = poisson_requests(rate_hz=1e5, n=6, seed=5, pool=pool, min_events=10, max_events=60, pinned=True)
+    probe = Server(blob(), pool_bytes=3 << 30, lanes=2, lane_events=32, compute_dtype="bf16")
+    room = int(1.2 * max(probe.request_bytes(r.batch) for r in reqs))
+    budget = probe.arena_total + room
+    probe.close()
+    big = poisson_requests(rate_hz=1e5, n=1, seed=6, pool=pool, min_events=200, max_events=200)[0]
+    big.rid = 99
+    big.arrival = reqs[2].arrival
+    srv = Server(blob(), pool_bytes=budget, lanes=2, lane_events=32, compute_dtype="bf16", results="device")
+    assert srv.request_bytes(big.batch) > room
+    got = {}
+
+    def keep(r):
+        got[r.rid] = {k: v.cpu().numpy() for k, v in r.out.items()}
+
+    stats = srv.run(reqs + [big], realtime=True, on_complete=keep)
+    summ = stats.summary()
+    say("device results", summ)
+    assert summ["requests"] == 6 and summ["rejected"] == 1 and big.error and big.rid not in got
+    assert stats.max_pool_used <= budget
+    eng = engine_for(64, "bf16")
+    for r in reqs:
+        alone = run(eng, r.batch, with_prob=False)
+        for e in range(r.n_events):
+            n = int(alone["n_vertices"][e])
+            assert int(got[r.rid]["n_vertices"][e]) == n
+            for k in ("z", "peak_prob", "integral", "bin"):
+                assert np.array_equal(got[r.rid][k][e, :n], alone[k][e, :n]), (r.rid, e, k)
+    eng.close()
+    srv.close()
