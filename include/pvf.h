@@ -49,7 +49,8 @@ typedef enum {
     PVF_ERR_WEIGHTS = 5,           /* blob malformed or shape != spec          */
     PVF_ERR_UNSUPPORTED_DTYPE = 6, /* compute dtype not built                 */
     PVF_ERR_DEVICE = 7,            /* a HIP runtime call failed               */
-    PVF_ERR_ALIGNMENT = 8          /* a buffer is not aligned as documented   */
+    PVF_ERR_ALIGNMENT = 8,         /* a buffer is not aligned as documented   */
+    PVF_ERR_SCRATCH_TOO_SMALL = 9  /* batch does not fit PVF_SCRATCH_BYTES     */
 } pvf_status;
 
 /* Per-event status bits written to pvf_vertices.d_event_status.  Bypass
@@ -197,6 +198,30 @@ pvf_status pvf_execute(pvf_engine *eng, const pvf_tracks *tracks, const pvf_vert
  * arena). */
 pvf_status pvf_execute_on(pvf_engine *eng, const pvf_tracks *tracks, const pvf_vertices *out,
                           void *stream);
+
+/* Bytes of the library's fixed per-device scratch (64 MiB). */
+#define PVF_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * path and kernels as pvf_execute, with the same results bit for bit, but
+ * every per-batch buffer (histogram rows, activations, the probability rows
+ * when d_prob_hist is NULL, flags, the track work queue) lives in a fixed
+ * scratch array that the library holds on each device until the process
+ * ends, instead of in the engine's arena; of the arena, the call reads only
+ * the weights.  Calls nothing that allocates.
+ * Limit: the batch's per-batch buffers must fit PVF_SCRATCH_BYTES (about
+ * 7.1 MiB per event for the default FP32 network, 3.6 MiB in BF16/FP16,
+ * 1.8 MiB in FP8: 8, 17 and 35 events); a larger batch returns
+ * PVF_ERR_SCRATCH_TOO_SMALL and enqueues nothing.  The other checks are
+ * those of pvf_execute.
+ * Sharing: every engine on a device uses that device's one scratch, and it
+ * keeps the last call's contents (each call clears what it needs zeroed, on
+ * the stream, before its kernels).  Calls that overlap in time on one
+ * device race and corrupt each other's results: order them on one stream,
+ * or with events.  pvf_debug_tensor views only pvf_execute calls.
+ * PVF_ERR_DEVICE if the scratch's device address could not be obtained. */
+pvf_status pvf_execute_scratch(pvf_engine *eng, const pvf_tracks *tracks, const pvf_vertices *out);
 
 /* Release the engine's host state.  The arena is the caller's to free. */
 pvf_status pvf_destroy(pvf_engine *eng);

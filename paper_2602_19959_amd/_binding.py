@@ -21,7 +21,7 @@ N_FEAT = 9
 PVF_OK = 0
 STATUS_NAMES = {0: "PVF_OK", 1: "PVF_ERR_INVALID_ARGUMENT", 2: "PVF_ERR_SHAPE", 3: "PVF_ERR_CAPACITY",
                 4: "PVF_ERR_ARENA_TOO_SMALL", 5: "PVF_ERR_WEIGHTS", 6: "PVF_ERR_UNSUPPORTED_DTYPE",
-                7: "PVF_ERR_DEVICE", 8: "PVF_ERR_ALIGNMENT"}
+                7: "PVF_ERR_DEVICE", 8: "PVF_ERR_ALIGNMENT", 9: "PVF_ERR_SCRATCH_TOO_SMALL"}
 EV_TOO_MANY_TRACKS, EV_BAD_INPUT, EV_PEAKS_TRUNCATED, EV_TRACKS_DROPPED = 1, 2, 4, 8
 DTYPES = {"fp32": 0, "bf16": 1, "fp16": 2, "fp8_e4m3": 3}
 LAYOUTS = {"event": 0, "interval": 1}
@@ -111,6 +111,8 @@ def load_library() -> C.CDLL:
     lib.pvf_execute.restype = C.c_int
     lib.pvf_execute_on.argtypes = [vp, C.POINTER(Tracks), C.POINTER(Vertices), vp]
     lib.pvf_execute_on.restype = C.c_int
+    lib.pvf_execute_scratch.argtypes = [vp, C.POINTER(Tracks), C.POINTER(Vertices)]
+    lib.pvf_execute_scratch.restype = C.c_int
     lib.pvf_destroy.argtypes = [vp]
     lib.pvf_destroy.restype = C.c_int
     lib.pvf_status_string.argtypes = [C.c_int]
@@ -291,6 +293,24 @@ class Engine:
         else:
             st = self.lib.pvf_execute_on(self.handle, C.byref(tr), C.byref(v), C.c_void_p(s.cuda_stream))
         _check("pvf_execute", st)
+        return out
+
+    def execute_scratch(self, feat, offsets, out: Outputs | None = None) -> Outputs:
+        """pvf_execute_scratch: the same path with the per-batch buffers in
+        the library's fixed per-device scratch (no allocation in the call).
+        Same stream ordering as execute(); raises PvfError on a batch too
+        large for the scratch (PVF_ERR_SCRATCH_TOO_SMALL)."""
+        t = self._torch
+        n_events = offsets.shape[0] - 1
+        if out is None:
+            out = self.alloc_outputs(n_events)
+        tr, v = self._views(feat, offsets, out)
+        self.stream.wait_stream(t.cuda.current_stream(self.device))
+        for x in (feat, offsets, out.n_vertices, out.z, out.peak_prob, out.integral, out.status, out.prob,
+                  out.bin):
+            if x is not None:
+                x.record_stream(self.stream)
+        _check("pvf_execute_scratch", self.lib.pvf_execute_scratch(self.handle, C.byref(tr), C.byref(v)))
         return out
 
     def execute_raw(self, tracks: Tracks, vertices: Vertices) -> int:

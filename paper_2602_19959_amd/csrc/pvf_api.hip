@@ -52,28 +52,14 @@ pvf_status validate_spec(const pvf_spec* s)
     return PVF_OK;
 }
 
-void make_plan(const pvf_spec* s, size_t weight_floats, Plan* p)
+// Per-batch working regions (histogram rows, activations, probabilities,
+// flags, the track work queue) for `events` events, laid out from byte
+// offset `off`; returns the end.  The level geometry must already be set.
+size_t layout_work(const pvf_spec* s, int events, size_t off, Plan* p)
 {
     const size_t eb = (size_t)act_bytes(s->compute_dtype);
-    p->n_levels = s->n_levels;
-    p->c0 = s->base_channels;
-    p->max_events = s->max_events;
-    // UNet sequences: one per event, or one per interval
-    p->units = s->unet_layout == PVF_LAYOUT_INTERVAL ? s->n_bins / s->bins_per_interval : 1;
-    const int seq = s->n_bins / p->units;
-    for (int l = 0; l < s->n_levels; ++l) {
-        p->lv[l].L = seq >> l;
-        p->lv[l].R = p->lv[l].L + 2 * kGuard;
-        p->lv[l].C = s->base_channels << l;
-    }
-    const size_t E = (size_t)s->max_events * p->units;     // UNet sequences
-    size_t off = 0;
+    const size_t E = (size_t)events * p->units;           // UNet sequences
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
-    p->weights_bytes = weight_floats * sizeof(float);
-    p->weights = take(p->weights_bytes);
-    // 16-bit copy of the conv weights, same element offsets as the FP32 layout
-    p->weights_lp = s->compute_dtype == PVF_FP32 ? 0 : take(weight_floats * 2);
-    p->mlp_lp = s->compute_dtype == PVF_FP32 ? 0 : take(mlp_lp_elems(kMaxHiddenLayers) * 2);
     p->zero_begin = off;
     p->x0 = take(E * p->lv[0].R * sizeof(float));
     const int n = s->n_levels;
@@ -85,12 +71,36 @@ void make_plan(const pvf_spec* s, size_t weight_floats, Plan* p)
         if (l >= 1) p->d[l] = take(rows * p->lv[l].C * eb);
     }
     p->zero_end = off;
-    p->prob = take((size_t)s->max_events * s->n_bins * sizeof(float));
-    p->flags = take((size_t)s->max_events * sizeof(int32_t));
-    p->order = take((size_t)s->max_events * sizeof(int32_t));
-    p->scales = s->compute_dtype == PVF_FP8_E4M3 ? take(kMaxScaleFloats * sizeof(float)) : 0;
+    p->prob = take((size_t)events * s->n_bins * sizeof(float));
+    p->flags = take((size_t)events * sizeof(int32_t));
+    p->order = take((size_t)events * sizeof(int32_t));
     p->queue = take(((size_t)s->max_tracks_per_event + 3) * sizeof(int32_t));
-    p->total = off;
+    return off;
+}
+
+void make_plan(const pvf_spec* s, size_t weight_floats, Plan* p)
+{
+    p->n_levels = s->n_levels;
+    p->c0 = s->base_channels;
+    p->max_events = s->max_events;
+    // UNet sequences: one per event, or one per interval
+    p->units = s->unet_layout == PVF_LAYOUT_INTERVAL ? s->n_bins / s->bins_per_interval : 1;
+    const int seq = s->n_bins / p->units;
+    for (int l = 0; l < s->n_levels; ++l) {
+        p->lv[l].L = seq >> l;
+        p->lv[l].R = p->lv[l].L + 2 * kGuard;
+        p->lv[l].C = s->base_channels << l;
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    // weights and constants first, then the per-batch regions
+    p->weights_bytes = weight_floats * sizeof(float);
+    p->weights = take(p->weights_bytes);
+    // 16-bit copy of the conv weights, same element offsets as the FP32 layout
+    p->weights_lp = s->compute_dtype == PVF_FP32 ? 0 : take(weight_floats * 2);
+    p->mlp_lp = s->compute_dtype == PVF_FP32 ? 0 : take(mlp_lp_elems(kMaxHiddenLayers) * 2);
+    p->scales = s->compute_dtype == PVF_FP8_E4M3 ? take(kMaxScaleFloats * sizeof(float)) : 0;
+    p->total = layout_work(s, s->max_events, off, p);
 }
 
 // ------------------------------------------------------------------ weights
@@ -375,6 +385,7 @@ struct pvf_engine {
     float leaky = 0.f, s_in = 0.f, head_b = 0.f;
     float shift[kFeat] = {}, scale[kFeat] = {};
     char* arena = nullptr;
+    char* scratch = nullptr;             // the library's scratch on this engine's device
     hipStream_t stream = nullptr;
     std::vector<std::string> names;      // one per launch of pvf_execute
     std::vector<std::string> kernels;    // kernel instance of each launch
@@ -655,19 +666,23 @@ ConvArgs conv_args(pvf_engine* eng, const WeightLayout::Conv& c, const void* in,
     return a;
 }
 
-pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* out, hipStream_t s)
+// Enqueue the whole path.  Weights and constants come from the engine's
+// arena (eng->plan); the per-batch regions of plan P start at `work` (the
+// arena itself, or the library's static scratch).
+pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* out, hipStream_t s, const Plan& P,
+                   char* work)
 {
     const int E = tr->n_events;
     const int EU = E * eng->plan.units;          // UNet sequences
     const int dt = eng->spec.compute_dtype;
     const size_t eb = (size_t)act_bytes(dt);
-    const Plan& P = eng->plan;
-    auto act = [&](size_t off) { return eng->arena + off; };
+    auto act = [&](size_t off) { return work + off; };
+    auto wk = [&](size_t off) { return work + off; };
     const WeightLayout& W = eng->wl;
     const int n = P.n_levels;
-    const float* wbase = at<float>(eng, P.weights);
-    float* prob = out->d_prob_hist ? out->d_prob_hist : at<float>(eng, P.prob);
-    int32_t* flags = at<int32_t>(eng, P.flags);
+    const float* wbase = at<float>(eng, eng->plan.weights);
+    float* prob = out->d_prob_hist ? out->d_prob_hist : reinterpret_cast<float*>(wk(P.prob));
+    int32_t* flags = reinterpret_cast<int32_t*>(wk(P.flags));
     int li = 0;                       // index of the launch about to be enqueued
     hipError_t err = hipSuccess;
     if (eng->profiling) err = hipEventRecord(eng->events[0], s);
@@ -694,21 +709,21 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
     for (int k = 0; k < kFeat; ++k) { ta.shift[k] = eng->shift[k]; ta.scale[k] = eng->scale[k]; }
     ta.slope = eng->leaky;
     ta.s_in = eng->s_in;
-    ta.x0 = at<float>(eng, P.x0);
+    ta.x0 = reinterpret_cast<float*>(wk(P.x0));
     ta.r0 = P.lv[0].R;
     ta.unit_bins = P.lv[0].L;
     ta.boundary_mm = eng->spec.boundary_mm;
     ta.mlp_dtype = dt;
-    ta.mlp_lp = dt == PVF_FP32 ? nullptr : eng->arena + P.mlp_lp;
+    ta.mlp_lp = dt == PVF_FP32 ? nullptr : eng->arena + eng->plan.mlp_lp;
     if (dt == PVF_FP8_E4M3) {
-        ta.mlp_in_inv = at<float>(eng, P.scales) + eng->mlp_in_inv_off;
-        ta.mlp_col = at<float>(eng, P.scales) + eng->mlp_col_off;
+        ta.mlp_in_inv = at<float>(eng, eng->plan.scales) + eng->mlp_in_inv_off;
+        ta.mlp_col = at<float>(eng, eng->plan.scales) + eng->mlp_col_off;
     }
     ta.mlp_calib = eng->calib_table ? eng->calib_table + eng->calib_mlp_off : nullptr;
     ta.flags = flags;
-    ta.order = at<int32_t>(eng, P.order);
-    ta.queue_counter = at<int32_t>(eng, P.queue);
-    check(launch_track(ta, E, eng->track_blocks, at<int32_t>(eng, P.queue) + 1, s));
+    ta.order = reinterpret_cast<int32_t*>(wk(P.order));
+    ta.queue_counter = reinterpret_cast<int32_t*>(wk(P.queue));
+    check(launch_track(ta, E, eng->track_blocks, ta.queue_counter + 1, s));
 
     // Calibration (pvf_calibrate only): per-channel absolute maximum of the
     // tensor the launch just enqueued stored.
@@ -725,7 +740,7 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
         m.out = eng->calib_table + eng->calib_off[li - 1];
         err = launch_amax(m, s);
     };
-    float* scales = dt == PVF_FP8_E4M3 ? at<float>(eng, P.scales) : nullptr;
+    float* scales = dt == PVF_FP8_E4M3 ? at<float>(eng, eng->plan.scales) : nullptr;
     // one UNet convolution: FP8 scales of this launch, launch, then calibration
     auto conv = [&](ConvArgs a, int taps, Epi epi, int store_level, int store_ld, int store_ch_off) {
         if (scales) {
@@ -754,7 +769,7 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
         check(hipSuccess);            // enc0.c2 computes it in its staging
     } else {
         FirstConvArgs fa{};
-        fa.x0 = at<float>(eng, P.x0);
+        fa.x0 = reinterpret_cast<float*>(wk(P.x0));
         fa.m_rows = EU * P.lv[0].R;
         fa.r0 = P.lv[0].R;
         fa.w = wbase + W.first_w;
@@ -780,7 +795,7 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
             a.ld_pool = lv.C;
             a.r_pool = P.lv[l + 1].R;
             if (l == 0 && fused) {
-                a.first_x0 = at<float>(eng, P.x0);
+                a.first_x0 = reinterpret_cast<float*>(wk(P.x0));
                 a.first_w = wbase + W.first_w;
                 a.first_b = wbase + W.first_b;
             }
@@ -907,6 +922,7 @@ static pvf_status init_impl(const pvf_spec* spec, const void* blob, size_t blob_
         return PVF_ERR_DEVICE;
     }
     e->track_blocks = 2 * e->cu_count;   // two 64 KB-LDS blocks per CU
+    e->scratch = scratch_base(dev);      // set-up of pvf_execute_scratch, once per device
     build_names(e);
 
     std::vector<float> packed;
@@ -994,7 +1010,7 @@ pvf_status pvf_execute(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices
 {
     pvf_status st = check_call(eng, tr, out);
     if (st != PVF_OK || tr->n_events == 0) return st;
-    return enqueue(eng, tr, out, eng->stream);
+    return enqueue(eng, tr, out, eng->stream, eng->plan, eng->arena);
 }
 
 pvf_status pvf_execute_on(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* out, void* stream)
@@ -1002,7 +1018,37 @@ pvf_status pvf_execute_on(pvf_engine* eng, const pvf_tracks* tr, const pvf_verti
     if (!stream) return PVF_ERR_INVALID_ARGUMENT;
     pvf_status st = check_call(eng, tr, out);
     if (st != PVF_OK || tr->n_events == 0) return st;
-    return enqueue(eng, tr, out, static_cast<hipStream_t>(stream));
+    return enqueue(eng, tr, out, static_cast<hipStream_t>(stream), eng->plan, eng->arena);
+}
+
+pvf_status pvf_execute_scratch(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* out)
+{
+    pvf_status st = check_call(eng, tr, out);
+    if (st != PVF_OK || tr->n_events == 0) return st;
+    if (!eng->scratch) return PVF_ERR_DEVICE;
+    // the per-batch regions laid out for this batch alone, from the scratch's start
+    Plan P = eng->plan;
+    P.total = layout_work(&eng->spec, tr->n_events, 0, &P);
+    if (P.total > kScratchBytes) return PVF_ERR_SCRATCH_TOO_SMALL;
+    // zero padding: the guard rows of every activation tensor
+    const size_t eb = (size_t)act_bytes(eng->spec.compute_dtype);
+    GuardZeroArgs g{};
+    g.n_seq = (int64_t)tr->n_events * P.units;
+    auto region = [&](size_t off, int level, size_t row_bytes) {
+        g.r[g.n].base = eng->scratch + off;
+        g.r[g.n].row_bytes = (int)row_bytes;
+        g.r[g.n].rows_per_seq = P.lv[level].R;
+        ++g.n;
+    };
+    region(P.x0, 0, sizeof(float));
+    for (int l = 0; l < P.n_levels; ++l) {
+        region(P.a[l], l, P.lv[l].C * eb);
+        if (l < P.n_levels - 1) region(P.cat[l], l, 2 * P.lv[l].C * eb);
+        if (l >= 1) region(P.pool[l], l, P.lv[l - 1].C * eb);
+        if (l >= 1) region(P.d[l], l, P.lv[l].C * eb);
+    }
+    if (launch_zero_guard_rows(g, eng->stream) != hipSuccess) return PVF_ERR_DEVICE;
+    return enqueue(eng, tr, out, eng->stream, P, eng->scratch);
 }
 
 pvf_status pvf_destroy(pvf_engine* eng)
@@ -1027,6 +1073,8 @@ const char* pvf_status_string(pvf_status s)
     case PVF_ERR_UNSUPPORTED_DTYPE: return "compute dtype not supported";
     case PVF_ERR_DEVICE: return "HIP runtime error";
     case PVF_ERR_ALIGNMENT: return "misaligned buffer";
+    case PVF_ERR_SCRATCH_TOO_SMALL:
+        return "batch too large for the library's fixed scratch (PVF_SCRATCH_BYTES = 64 MiB per device)";
     }
     return "unknown status";
 }
@@ -1091,7 +1139,7 @@ pvf_status pvf_autotune(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertice
         }
         if (!any) continue;
         for (int r = 0; r < reps + 1 && st == PVF_OK; ++r) {       // first pass warms up
-            st = enqueue(eng, tr, out, eng->stream);
+            st = enqueue(eng, tr, out, eng->stream, eng->plan, eng->arena);
             if (st == PVF_OK && hipStreamSynchronize(eng->stream) != hipSuccess) st = PVF_ERR_DEVICE;
             if (st == PVF_OK && r > 0) st = pvf_profile_read(eng, ms.data(), nl);
             if (st != PVF_OK || r == 0) continue;
@@ -1132,7 +1180,7 @@ pvf_status pvf_graph_capture(pvf_engine* eng, const pvf_tracks* tr, const pvf_ve
         eng->profiling = was;
         return PVF_ERR_DEVICE;
     }
-    st = enqueue(eng, tr, out, eng->stream);
+    st = enqueue(eng, tr, out, eng->stream, eng->plan, eng->arena);
     hipGraph_t g = nullptr;
     const hipError_t end = hipStreamEndCapture(eng->stream, &g);
     eng->profiling = was;
@@ -1167,7 +1215,7 @@ pvf_status pvf_calibrate(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertic
     if (misaligned(d_amax, 4)) return PVF_ERR_ALIGNMENT;
     if (hipMemsetAsync(d_amax, 0, (size_t)n * sizeof(float), eng->stream) != hipSuccess) return PVF_ERR_DEVICE;
     eng->calib_table = d_amax;
-    st = enqueue(eng, tr, out, eng->stream);
+    st = enqueue(eng, tr, out, eng->stream, eng->plan, eng->arena);
     eng->calib_table = nullptr;
     return st;
 }

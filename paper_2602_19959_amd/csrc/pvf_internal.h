@@ -288,6 +288,25 @@ std::string fp8_kernel_name(int variant, int cin, int taps, Epi epi);
 inline int act_bytes(int dtype) { return dtype == PVF_FP32 ? 4 : (dtype == PVF_FP8_E4M3 ? 1 : 2); }
 
 hipError_t launch_peaks(const PeakArgs& a, int n_events, hipStream_t s);
+
+// The library's fixed per-device scratch (pvf_execute_scratch).
+constexpr size_t kScratchBytes = PVF_SCRATCH_BYTES;
+constexpr int kMaxGuardRegions = 1 + 4 * kMaxLevels;
+struct GuardRegion {
+    char* base;          // first row of the region's first sequence
+    int row_bytes;       // bytes per row (a multiple of 4)
+    int rows_per_seq;    // R = L + 2 kGuard
+};
+struct GuardZeroArgs {
+    GuardRegion r[kMaxGuardRegions];
+    int n;               // regions
+    int64_t n_seq;       // sequences per region
+};
+// Device address of the scratch on `device` (which must be current): looked
+// up once per device and cached; nullptr if the lookup failed.
+char* scratch_base(int device);
+// Clear the kGuard rows at both ends of every sequence of every region.
+hipError_t launch_zero_guard_rows(const GuardZeroArgs& a, hipStream_t s);
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
 
 }  // namespace pvf

@@ -154,15 +154,27 @@ def test_execute_rejects_null_engine():
     lib = pv.load_library()
     tr, v = B.Tracks(), B.Vertices()
     assert lib.pvf_execute(None, C.byref(tr), C.byref(v)) == 1
+    assert lib.pvf_execute_scratch(None, C.byref(tr), C.byref(v)) == 1
     assert lib.pvf_destroy(None) == 1
     assert lib.pvf_launch_count(None) == 0
 
 
 def test_status_strings():
     lib = pv.load_library()
-    for k in range(9):
-        assert lib.pvf_status_string(k)
+    for k in range(10):
+        assert lib.pvf_status_string(k) and lib.pvf_status_string(k) != b"unknown status"
+    assert b"scratch" in lib.pvf_status_string(9)
     assert lib.pvf_status_string(99) == b"unknown status"
+
+
+def test_scratch_size_in_header_matches_library_limit():
+    """PVF_SCRATCH_BYTES (the header's stated limit of pvf_execute_scratch)
+    is 64 MiB, and the status text names the same limit."""
+    import re
+    text = open(os.path.join(ROOT, "include", "pvf.h")).read()
+    m = re.search(r"#define PVF_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == 64 << 20
+    assert b"64 MiB" in pv.load_library().pvf_status_string(9)
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
