@@ -12,26 +12,35 @@
 // Max-pool of stored FP8 values equals the FP8 of the max (one scale per
 // channel), and the head and sigmoid work on the FP32 dequantised values.
 //
-// MFMA: v_mfma_f32_16x16x32_fp8_fp8.  One stage = 32 input channels (32 bytes
-// per row); each lane reads 8 consecutive channels (8 bytes) of its row (A)
-// and of its column (B).  32-byte LDS rows, two 16-byte chunks; chunk q of
-// row r sits at q ^ bit 3 of r (swz32): measured on gfx950 with a read-pattern
-// probe, the fragment reads (16 consecutive rows, or rows TAPS apart for the
-// weights, at any tap offset) then run at the conflict-free rate, where the
-// unswizzled rows took two LDS passes per read.
+// MFMA: v_mfma_f32_32x32x64_f8f6f4 with both operands e4m3 and no block
+// scale, the gfx950 matrix instruction that runs FP8 at twice the 16-bit
+// rate (measured at 4.6 PFLOP/s register to register, 4.5 with its operands
+// read from LDS in 64 x 64 tiles per wave).  The GEMM k axis of a 5-tap
+// convolution is cut into 32-byte slices, one (32-channel chunk, tap) pair
+// each, in the order (chunk, tap); one MFMA takes two consecutive slices,
+// lanes 0-31 the first and lanes 32-63 the second (32 bytes per lane, the
+// instruction's k layout).  A stage holds KB = 64 channels (10 slices, five
+// MFMAs per 32 x 32 block) when the input has a multiple of 64 channels,
+// else KB = 32 (5 slices: the third MFMA's second half is zero).  Each
+// layer has one stage width, so every tile variant of a layer pairs the same
+// slices and gives the same bits.  The weights take the A slot (D^T = W X^T):
+// lane l of a 32 x 32 block then holds position l % 32 and, in register v,
+// output channel 8 (v / 4) + 4 (l / 32) + v % 4 (four consecutive channels per
+// register quad).
+//
+// Stages are double-buffered: stage k + 1 streams from global memory straight
+// into the second LDS buffer (16-byte global_load_lds) while stage k is on the
+// matrix cores.  LDS rows hold KB bytes in 16-byte chunks, chunk c of row r at
+// c ^ s(r) (s = bits 2..3 of r for 64-byte rows, bit 3 for 32-byte rows).
 #include "pvf_internal.h"
 
 namespace pvf {
 namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-
-constexpr int KC = 32;            // input channels (bytes) per stage and row
-
-__device__ __forceinline__ int swz32(int r) { return (r >> 3) & 1; }
-// byte offset of the 8-byte piece p (0..3) of row r in a 32-byte-row tile
-__device__ __forceinline__ int at32(int r, int p) { return r * KC + 16 * ((p >> 1) ^ swz32(r)) + 8 * (p & 1); }
 
 __device__ __forceinline__ float lrelu(float x, float s) { return x >= 0.f ? x : s * x; }
 
@@ -44,44 +53,208 @@ __device__ __forceinline__ float e4m3_to_f32(uint8_t b)
 
 template <int A, int B> struct Max { static constexpr int v = A > B ? A : B; };
 
-// Occupancy target handed to the register allocator: as many waves per SIMD
-// as the block's LDS allows on one CU (160 KB), at most 4 (128 registers).
-constexpr int occupancy_target(int lds_bytes, int waves_per_block)
+template <int KB>
+__device__ __forceinline__ int swz(int r) { return KB == 64 ? ((r >> 2) & 3) : ((r >> 3) & 1); }
+
+__device__ __forceinline__ i32x8 join(u32x4 lo, u32x4 hi)
 {
-    const int blocks = lds_bytes > 0 ? 163840 / lds_bytes : 8;
-    const int w = blocks * waves_per_block / 4;
-    return w < 1 ? 1 : (w > 4 ? 4 : w);
+    return i32x8{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
 }
 
-// Epilogue shared by the FP8 kernels (the LDS passed in is free).  The
-// kernels issue the MFMA as D^T = W X^T (weight fragment in the A slot), so
-// lane (li, lg) of a 16 x 16 tile holds channels 4 lg + v (v = 0..3) of tile
-// row li: four consecutive FP8 outputs of one position, one 4-byte LDS store.
-template <int NT, int BM, int BN, int WM, int TMW, int TNW, int EPI>
-__device__ __forceinline__ void fp8_epilogue(const f32x4 (&acc)[TMW][TNW], const ConvArgs& a, void* lds, int64_t m0,
-                                             int n0, int tid)
+// Fragment buffers: two (the next MFMA step's fragments are read while the
+// current one computes), or one in 16-wave blocks, whose four waves per SIMD
+// leave 128 registers a lane and cover the read latency themselves.
+constexpr int frag_bufs(int waves) { return waves >= 16 ? 1 : 2; }
+
+// Occupancy target handed to the register allocator: as many waves per SIMD
+// as both the block's LDS (160 KB per CU) and an estimate of its registers
+// (accumulators, fragments, addressing; 512 per lane and SIMD) allow, at
+// most 4, and at least what one block puts on each SIMD.
+constexpr int occupancy_target(int lds_bytes, int waves_per_block, int tmw, int tnw)
 {
+    const int blocks = lds_bytes > 0 ? 163840 / lds_bytes : 8;
+    int w = blocks * waves_per_block / 4;
+    const int regs = tmw * tnw * 16 + frag_bufs(waves_per_block) * (tmw + tnw) * 8 + 48;
+    w = w < 512 / regs ? w : 512 / regs;
+    w = w < 1 ? 1 : (w > 4 ? 4 : w);
+    const int need = (waves_per_block + 3) / 4;
+    return w < need ? need : w;
+}
+
+template <int BM, int BN, int KB, int TAPS, int EPI>
+struct F8Lds {
+    static constexpr int RPL = 1024 / KB;
+    static constexpr int XR = (BM + TAPS - 1 + RPL - 1) / RPL * RPL;
+    static constexpr int STAGE = (XR + BN * TAPS) * KB;
+    static constexpr int v = Max<2 * STAGE, (EPI == EPI_HEAD ? 0 : BM * (BN + 16))>::v;
+};
+
+template <int WM, int WN, int TMW, int TNW, int KB, int TAPS, int EPI>
+__global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(occupancy_target(
+    F8Lds<WM * TMW * 32, WN * TNW * 32, KB, TAPS, EPI>::v, WM * WN, TMW, TNW))))
+void conv_mfma_fp8x64(ConvArgs a)
+{
+    constexpr int NW = WM * WN;
+    constexpr int NT = NW * 64;
+    constexpr int BM = WM * TMW * 32;
+    constexpr int BN = WN * TNW * 32;
+    constexpr int NS = KB / 32;                  // 32-channel chunks per stage
+    constexpr int SL = NS * TAPS;                // 32-byte k slices per stage
+    constexpr int STEPS = (SL + 1) / 2;          // MFMAs per 32 x 32 block and stage
+    constexpr int RPL = 1024 / KB;               // LDS rows per wave-wide 1 KB load
+    constexpr int CPR = KB / 16;                 // 16-byte chunks per row
+    constexpr int RAD = (TAPS - 1) / 2;
+    using L = F8Lds<BM, BN, KB, TAPS, EPI>;
+    constexpr int XR = L::XR;
+    constexpr int WRW = BN * TAPS;
+    static_assert(WRW % RPL == 0, "weight rows fill whole 1 KB loads");
+    constexpr int XI = XR / RPL, WI = WRW / RPL;
+    constexpr int STAGE = L::STAGE;
     constexpr int OP = BN + 16;                  // epilogue tile pitch (bytes)
-    const int lane = tid & 63, wave = tid >> 6;
-    const int li = lane & 15, lg = lane >> 4;
-    const int rw = (wave % WM) * TMW * 16;
-    const int cw = (wave / WM) * TNW * 16;
+    __shared__ __attribute__((aligned(16))) uint8_t smem[L::v];
+
+    const uint8_t* in = static_cast<const uint8_t*>(a.in);
+    const uint8_t* wt = static_cast<const uint8_t*>(a.w);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave % WM;
+    const int wn = wave / WM;
+    const int r32 = lane & 31;
+    const int h = lane >> 5;
+    // XCD-aware tile order (block b runs on XCD b % 8): every N tile of an M
+    // tile runs back to back on one XCD, sharing its L2.
+    const int n_tiles = (a.n + BN - 1) / BN;
+    const int m_tiles = (int)((a.m_rows + BM - 1) / BM);
+    const int xcd = (int)(blockIdx.x % kXcds), slot = (int)(blockIdx.x / kXcds);
+    const int m_tile = (slot / n_tiles) * kXcds + xcd;
+    if (m_tile >= m_tiles) return;
+    const int64_t m0 = (int64_t)m_tile * BM;
+    const int n0 = (slot % n_tiles) * BN;
+    const int kw = TAPS * a.cin;
+
+    f32x16 acc[TMW][TNW];
+#pragma unroll
+    for (int i = 0; i < TMW; ++i)
+#pragma unroll
+        for (int j = 0; j < TNW; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+    // Wave-wide load j fills LDS rows RPL j .. RPL j + RPL - 1 of the stage
+    // (halo rows first, then the tap-major weight rows tap * BN + column);
+    // this wave issues j = wave + t * NW.  Lane L fills slot L % CPR of row
+    // L / CPR, i.e. the chunk the swizzle puts there.  Sources are 32-bit
+    // byte offsets from two block-uniform bases; halo rows outside the batch
+    // and columns beyond n are clamped to valid ones (their outputs are
+    // discarded by the epilogue).
+    constexpr int NJ = XI + WI, JT = (NJ + NW - 1) / NW;
+    const int lrow = lane / CPR, lpos = lane % CPR;
+    const uint8_t* xbase = in + (m0 - RAD) * a.ld_in;
+    const uint8_t* wbase = wt + (int64_t)n0 * kw;
+    unsigned off[JT];
+#pragma unroll
+    for (int t = 0; t < JT; ++t) {
+        const int j = min(wave + t * NW, NJ - 1);
+        const bool xj = j < XI;
+        const int row = RPL * (xj ? j : j - XI) + lrow;
+        const int c = lpos ^ swz<KB>(row);
+        if (xj) {
+            int64_t gr = m0 - RAD + row;
+            gr = gr < 0 ? 0 : (gr >= a.m_rows ? a.m_rows - 1 : gr);
+            off[t] = (unsigned)((gr - (m0 - RAD)) * a.ld_in + 16 * c);
+        } else {
+            const int tap = row / BN, nn = row % BN;
+            const int n = n0 + nn < a.n ? n0 + nn : a.n - 1;
+            off[t] = (unsigned)((n - n0) * kw + tap * a.cin + 16 * c);
+        }
+    }
+    auto issue = [&](int buf, int c0) __attribute__((always_inline)) {
+        uint8_t* base = smem + buf * STAGE;
+#pragma unroll
+        for (int t = 0; t < JT; ++t) {
+            const int j = wave + t * NW;
+            if ((t + 1) * NW <= NJ || j < NJ)
+                __builtin_amdgcn_global_load_lds((const void*)((j < XI ? xbase : wbase) + (off[t] + (unsigned)c0)),
+                                                 (__attribute__((address_space(3))) void*)(base + 1024 * j), 16, 0, 0);
+        }
+    };
+
+    const int nk = a.cin / KB;
+    issue(0, 0);
+    for (int k = 0; k < nk; ++k) {
+        // this wave's loads of stage k have landed; the barrier makes every
+        // wave's visible and frees the other buffer (last read in stage k - 1)
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (k + 1 < nk) issue((k + 1) & 1, (k + 1) * KB);
+        const uint8_t* xs = smem + (k & 1) * STAGE;
+        const uint8_t* ws = xs + XR * KB;
+        constexpr int FB = frag_bufs(NW);
+        i32x8 av[FB][TMW], bv[FB][TNW];
+        // fragments of MFMA step p: this lane's slice 2 p + h (clamped; the
+        // half past the last slice is zero)
+        auto frag = [&](int p, int f) __attribute__((always_inline)) {
+            const int s0 = 2 * p + h;
+            const bool pad = s0 >= SL;
+            const int s = pad ? SL - 1 : s0;
+            const int sub = s / TAPS, tap = s - sub * TAPS;
+#pragma unroll
+            for (int i = 0; i < TMW; ++i) {
+                const int r = wm * TMW * 32 + i * 32 + r32 + tap;
+                const u32x4 lo = *reinterpret_cast<const u32x4*>(xs + r * KB + 16 * ((2 * sub) ^ swz<KB>(r)));
+                const u32x4 hi = *reinterpret_cast<const u32x4*>(xs + r * KB + 16 * ((2 * sub + 1) ^ swz<KB>(r)));
+                av[f][i] = pad ? i32x8{0, 0, 0, 0, 0, 0, 0, 0} : join(lo, hi);
+            }
+#pragma unroll
+            for (int j = 0; j < TNW; ++j) {
+                const int r = tap * BN + wn * TNW * 32 + j * 32 + r32;
+                const u32x4 lo = *reinterpret_cast<const u32x4*>(ws + r * KB + 16 * ((2 * sub) ^ swz<KB>(r)));
+                const u32x4 hi = *reinterpret_cast<const u32x4*>(ws + r * KB + 16 * ((2 * sub + 1) ^ swz<KB>(r)));
+                bv[f][j] = pad ? i32x8{0, 0, 0, 0, 0, 0, 0, 0} : join(lo, hi);
+            }
+        };
+        if constexpr (FB == 2) frag(0, 0);
+#pragma unroll
+        for (int p = 0; p < STEPS; ++p) {
+            if constexpr (FB == 2) {
+                if (p + 1 < STEPS) frag(p + 1, (p + 1) & 1);
+            } else {
+                frag(p, 0);
+            }
+            const int f = FB == 2 ? (p & 1) : 0;
+#pragma unroll
+            for (int i = 0; i < TMW; ++i)
+#pragma unroll
+                for (int j = 0; j < TNW; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(bv[f][j], av[f][i], acc[i][j], 0, 0,
+                                                                                0, 0, 0, 0);
+        }
+    }
+    __syncthreads();   // the epilogue reuses the stage buffers
+
+    // ---- epilogue
+    const int rw = wm * TMW * 32;
+    const int cw = wn * TNW * 32;
     const RowMap rows(m0, a.r_in);
     if constexpr (EPI == EPI_HEAD) {
+        // logit = sum over channels of LeakyReLU(acc s_n + b_n) w_n; the two
+        // lane halves hold the two halves of each block's channels
 #pragma unroll
         for (int i = 0; i < TMW; ++i) {
             float s = 0.f;
 #pragma unroll
-            for (int j = 0; j < TNW; ++j) {
-                const int c = n0 + cw + j * 16 + 4 * lg;
+            for (int j = 0; j < TNW; ++j)
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    s += lrelu(acc[i][j][v] * a.col_scale[c + v] + a.bias[c + v], a.slope) * a.head_w[c + v];
-            }
-            s += __shfl_xor(s, 16);
+                for (int g = 0; g < 4; ++g)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int c = n0 + cw + j * 32 + 8 * g + 4 * h + v;
+                        s += lrelu(acc[i][j][4 * g + v] * a.col_scale[c] + a.bias[c], a.slope) * a.head_w[c];
+                    }
             s += __shfl_xor(s, 32);
-            const int t = rw + i * 16 + li;
-            if (lg == 0 && m0 + t < a.m_rows) {
+            const int t = rw + i * 32 + r32;
+            if (h == 0 && m0 + t < a.m_rows) {
                 int64_t e;
                 int loc;
                 rows.at(t, e, loc);
@@ -91,31 +264,32 @@ __device__ __forceinline__ void fp8_epilogue(const f32x4 (&acc)[TMW][TNW], const
         }
         return;
     } else {
-        uint8_t* ot = static_cast<uint8_t*>(lds);   // [BM][OP] bytes
+        uint8_t* ot = smem;   // [BM][OP] bytes
 #pragma unroll
-        for (int j = 0; j < TNW; ++j) {
-            const int col = cw + j * 16 + 4 * lg;
-            // y / a_out = LeakyReLU(acc * s_n / a_out + b / a_out): one FMA per
-            // value with the folded per-column factors (n % 16 == 0, so a
-            // lane's four columns are all valid or all past n)
-            const int nc = min(n0 + col, a.n - 4);
-            const f32x4 fs = *reinterpret_cast<const f32x4*>(a.fold_scale + nc);
-            const f32x4 fb = *reinterpret_cast<const f32x4*>(a.fold_bias + nc);
+        for (int j = 0; j < TNW; ++j)
 #pragma unroll
-            for (int i = 0; i < TMW; ++i) {
-                float y[4];
+            for (int g = 0; g < 4; ++g) {
+                // y / a_out = LeakyReLU(acc * s_n / a_out + b / a_out): one FMA
+                // per value with the folded per-column factors (columns come in
+                // groups of four, all valid or all past n)
+                const int col = cw + j * 32 + 8 * g + 4 * h;
+                const int nc = min(n0 + col, a.n - 4);
+                const f32x4 fs = *reinterpret_cast<const f32x4*>(a.fold_scale + nc);
+                const f32x4 fb = *reinterpret_cast<const f32x4*>(a.fold_bias + nc);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    float x = fmaf(acc[i][j][v], fs[v], fb[v]);
-                    if (EPI != EPI_CONVT) x = lrelu(x, a.slope);
-                    y[v] = fminf(fmaxf(x, -448.f), 448.f);   // saturate (the conversion maps overflow to NaN)
+                for (int i = 0; i < TMW; ++i) {
+                    float y[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        float x = fmaf(acc[i][j][4 * g + v], fs[v], fb[v]);
+                        if (EPI != EPI_CONVT) x = lrelu(x, a.slope);
+                        y[v] = fminf(fmaxf(x, -448.f), 448.f);   // saturate (the conversion maps overflow to NaN)
+                    }
+                    uint32_t w = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(y[0], y[1], 0, false);
+                    w = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(y[2], y[3], (int)w, true);
+                    *reinterpret_cast<uint32_t*>(ot + (rw + i * 32 + r32) * OP + col) = w;
                 }
-                // two packed conversions: channel 4 lg + v goes to byte v
-                uint32_t w = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(y[0], y[1], 0, false);
-                w = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(y[2], y[3], (int)w, true);
-                *reinterpret_cast<uint32_t*>(ot + (rw + i * 16 + li) * OP + col) = w;
             }
-        }
         __syncthreads();
         uint8_t* out = static_cast<uint8_t*>(a.out);
         constexpr int CH = BN / 16;                 // 16-byte chunks per tile row
@@ -147,10 +321,10 @@ __device__ __forceinline__ void fp8_epilogue(const f32x4 (&acc)[TMW][TNW], const
                 rows.at(2 * pr, e, loc);
                 if (loc < kGuard || loc >= a.r_in - kGuard) continue;
                 // two whole 16-byte rows from LDS, compared in registers
-                const uint4 r0 = *reinterpret_cast<const uint4*>(ot + (2 * pr) * OP + 16 * q);
-                const uint4 r1 = *reinterpret_cast<const uint4*>(ot + (2 * pr + 1) * OP + 16 * q);
-                const uint8_t* x0 = reinterpret_cast<const uint8_t*>(&r0);
-                const uint8_t* x1 = reinterpret_cast<const uint8_t*>(&r1);
+                const uint4 q0 = *reinterpret_cast<const uint4*>(ot + (2 * pr) * OP + 16 * q);
+                const uint4 q1 = *reinterpret_cast<const uint4*>(ot + (2 * pr + 1) * OP + 16 * q);
+                const uint8_t* x0 = reinterpret_cast<const uint8_t*>(&q0);
+                const uint8_t* x1 = reinterpret_cast<const uint8_t*>(&q1);
                 uint8_t y[16];
 #pragma unroll
                 for (int u = 0; u < 16; ++u) y[u] = e4m3_to_f32(x0[u]) >= e4m3_to_f32(x1[u]) ? x0[u] : x1[u];
@@ -161,284 +335,43 @@ __device__ __forceinline__ void fp8_epilogue(const f32x4 (&acc)[TMW][TNW], const
     }
 }
 
-template <int WM, int WN, int TMW, int TNW, int TAPS, int EPI>
-__global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(occupancy_target(
-    Max<(WM * TMW * 16 + TAPS - 1) * 32 + WN * TNW * 16 * TAPS * 32,
-        (EPI == EPI_HEAD ? 0 : WM * TMW * 16 * (WN * TNW * 16 + 16))>::v, WM * WN))))
-void conv_mfma_fp8(ConvArgs a)
-{
-    constexpr int NT = WM * WN * 64;
-    constexpr int BM = WM * TMW * 16;
-    constexpr int BN = WN * TNW * 16;
-    constexpr int RAD = (TAPS - 1) / 2;
-    constexpr int XROWS = BM + TAPS - 1;
-    constexpr int NCH = KC / 16;                 // 16-byte chunks per row
-    constexpr int XV = XROWS * NCH;
-    constexpr int WV = BN * TAPS * NCH;
-    constexpr int OP = BN + 16;                  // epilogue tile pitch (bytes)
-    constexpr int STAGE = XROWS * KC + BN * TAPS * KC;
-    constexpr int SMEM = Max<STAGE, (EPI == EPI_HEAD ? 0 : BM * OP)>::v;
-
-    __shared__ __attribute__((aligned(16))) uint8_t smem[SMEM];
-    uint8_t* xs = smem;
-    uint8_t* ws = smem + XROWS * KC;
-
-    const uint8_t* in = static_cast<const uint8_t*>(a.in);
-    const uint8_t* wt = static_cast<const uint8_t*>(a.w);
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int wm = wave % WM;
-    const int wn = wave / WM;
-    const int li = lane & 15;
-    const int lg = lane >> 4;
-    // XCD-aware tile order (block b runs on XCD b % 8): every N tile of an M
-    // tile runs back to back on one XCD, sharing its L2.
-    const int n_tiles = (a.n + BN - 1) / BN;
-    const int m_tiles = (int)((a.m_rows + BM - 1) / BM);
-    const int xcd = (int)(blockIdx.x % kXcds), slot = (int)(blockIdx.x / kXcds);
-    const int m_tile = (slot / n_tiles) * kXcds + xcd;
-    if (m_tile >= m_tiles) return;
-    const int64_t m0 = (int64_t)m_tile * BM;
-    const int n0 = (slot % n_tiles) * BN;
-    const int kw = TAPS * a.cin;
-
-    f32x4 acc[TMW][TNW];
-#pragma unroll
-    for (int i = 0; i < TMW; ++i)
-#pragma unroll
-        for (int j = 0; j < TNW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    // Staging: thread tid owns chunk q = tid % NCH of LDS rows tid / NCH + u * RS
-    // in the halo tile and in the tap-major weight tile (row = tap * BN +
-    // column); every load of a stage is in flight before the first LDS store.
-    // Halo rows outside the batch and columns beyond n are clamped to valid
-    // ones: they only feed outputs the epilogue discards.
-    constexpr int RS = NT / NCH;
-    constexpr int WROWS = TAPS * BN;
-    constexpr int XPT = (XV + NT - 1) / NT, WPT = (WV + NT - 1) / NT;
-    static_assert(RS % 16 == 0, "chunk rows of one thread share their swizzle");
-    const int q = tid % NCH, row0 = tid / NCH;
-    const int lds0 = row0 * KC + 16 * (q ^ swz32(row0));   // + u * RS * KC for chunk u
-    auto x_has = [&](int u) __attribute__((always_inline)) { return (u + 1) * RS <= XROWS || row0 + u * RS < XROWS; };
-    auto w_has = [&](int u) __attribute__((always_inline)) { return (u + 1) * RS <= WROWS || row0 + u * RS < WROWS; };
-    const uint8_t* xsrc[XPT];
-    const uint8_t* wsrc[WPT];
-#pragma unroll
-    for (int u = 0; u < XPT; ++u) {
-        int64_t g = m0 - RAD + min(row0 + u * RS, XROWS - 1);
-        g = g < 0 ? 0 : (g >= a.m_rows ? a.m_rows - 1 : g);
-        xsrc[u] = in + g * a.ld_in + 16 * q;
-    }
-#pragma unroll
-    for (int u = 0; u < WPT; ++u) {
-        const int wr = min(row0 + u * RS, WROWS - 1);
-        const int tap = wr / BN, nn = wr % BN;
-        const int n = n0 + nn < a.n ? n0 + nn : a.n - 1;
-        wsrc[u] = wt + (int64_t)n * kw + tap * a.cin + 16 * q;
-    }
-
-    for (int c0 = 0; c0 < a.cin; c0 += KC) {
-        u32x4 xr[XPT], wr[WPT];
-#pragma unroll
-        for (int u = 0; u < XPT; ++u) xr[u] = *reinterpret_cast<const u32x4*>(xsrc[u] + c0);
-#pragma unroll
-        for (int u = 0; u < WPT; ++u) wr[u] = *reinterpret_cast<const u32x4*>(wsrc[u] + c0);
-#pragma unroll
-        for (int u = 0; u < XPT; ++u)
-            if (x_has(u)) *reinterpret_cast<u32x4*>(xs + lds0 + u * RS * KC) = xr[u];
-#pragma unroll
-        for (int u = 0; u < WPT; ++u)
-            if (w_has(u)) *reinterpret_cast<u32x4*>(ws + lds0 + u * RS * KC) = wr[u];
-        __syncthreads();
-#pragma unroll
-        for (int tap = 0; tap < TAPS; ++tap) {
-            long av[TMW], bv[TNW];
-#pragma unroll
-            for (int i = 0; i < TMW; ++i)
-                av[i] = *reinterpret_cast<const long*>(xs + at32(wm * TMW * 16 + i * 16 + li + tap, lg));
-#pragma unroll
-            for (int j = 0; j < TNW; ++j)
-                bv[j] = *reinterpret_cast<const long*>(ws + at32(tap * BN + wn * TNW * 16 + j * 16 + li, lg));
-#pragma unroll
-            for (int i = 0; i < TMW; ++i)
-#pragma unroll
-                for (int j = 0; j < TNW; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(bv[j], av[i], acc[i][j], 0, 0, 0);
-        }
-        __syncthreads();
-    }
-
-    __syncthreads();   // the epilogue reuses the stage buffers
-    fp8_epilogue<NT, BM, BN, WM, TMW, TNW, EPI>(acc, a, smem, m0, n0, tid);
-}
-
-
-// Double-buffered form for layers with 64 or more input channels: one stage
-// = 64 channels (bytes) per row, 64-byte LDS rows as in the 16-bit kernels;
-// stage k + 1 streams straight into the second LDS buffer
-// (global_load_lds_dwordx4) while stage k computes, and the fragments of the
-// next (chunk, tap) are read during the current MFMAs.  Same k order as
-// conv_mfma_fp8 (32-channel chunk, tap), so the same bits.  Chunk c of row r
-// sits at c ^ bits 2..3 of r: measured on gfx950 with a read-pattern probe,
-// the 8-byte fragment reads (16 consecutive rows, or rows TAPS apart, at any
-// tap offset) then run at the conflict-free rate, twice as fast as with
-// c ^ 2*bit3(r).  Out-of-range rows and columns are clamped (their outputs
-// are discarded).
-__device__ __forceinline__ int swz64(int r) { return (r >> 2) & 3; }
-
-template <int WM, int WN, int TMW, int TNW, int TAPS, int EPI>
-__global__ __launch_bounds__(WM * WN * 64) void conv_mfma_fp8_db(ConvArgs a)
-{
-    constexpr int NW = WM * WN;
-    constexpr int NT = NW * 64;
-    constexpr int BM = WM * TMW * 16;
-    constexpr int BN = WN * TNW * 16;
-    constexpr int KB = 64;                       // channels (bytes) per stage and row
-    constexpr int RAD = (TAPS - 1) / 2;
-    constexpr int XR = (BM + TAPS - 1 + 15) / 16 * 16;
-    constexpr int WRW = BN * TAPS;
-    static_assert(WRW % 16 == 0, "weight rows fill whole 1 KB loads");
-    constexpr int XI = XR / 16, WI = WRW / 16;
-    constexpr int STAGE = (XR + WRW) * KB;
-    constexpr int SMEM = Max<2 * STAGE, (EPI == EPI_HEAD ? 0 : BM * (BN + 16))>::v;
-    __shared__ __attribute__((aligned(16))) uint8_t smem[SMEM];
-
-    const uint8_t* in = static_cast<const uint8_t*>(a.in);
-    const uint8_t* wt = static_cast<const uint8_t*>(a.w);
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wm = wave % WM;
-    const int wn = wave / WM;
-    const int li = lane & 15;
-    const int lg = lane >> 4;
-    const int n_tiles = (a.n + BN - 1) / BN;
-    const int m_tiles = (int)((a.m_rows + BM - 1) / BM);
-    const int xcd = (int)(blockIdx.x % kXcds), slot = (int)(blockIdx.x / kXcds);
-    const int m_tile = (slot / n_tiles) * kXcds + xcd;
-    if (m_tile >= m_tiles) return;
-    const int64_t m0 = (int64_t)m_tile * BM;
-    const int n0 = (slot % n_tiles) * BN;
-    const int kw = TAPS * a.cin;
-
-    f32x4 acc[TMW][TNW];
-#pragma unroll
-    for (int i = 0; i < TMW; ++i)
-#pragma unroll
-        for (int j = 0; j < TNW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    // Wave-wide load j fills LDS rows 16 j .. 16 j + 15 of the stage (halo
-    // rows first, then the tap-major weight rows tap * BN + column); this
-    // wave issues j = wave + t * NW.  Each lane's source is a 32-bit byte
-    // offset, computed once, from one of two block-uniform bases (the halo's
-    // first row and the N tile's first weight row; clamped rows stay at or
-    // after them).
-    constexpr int NJ = XI + WI, JT = (NJ + NW - 1) / NW;
-    const int lrow = lane >> 2, lpos = lane & 3;
-    const uint8_t* xbase = in + (m0 - RAD) * a.ld_in;
-    const uint8_t* wbase = wt + (int64_t)n0 * kw;
-    unsigned off[JT];
-#pragma unroll
-    for (int t = 0; t < JT; ++t) {
-        const int j = min(wave + t * NW, NJ - 1);
-        const bool xj = j < XI;
-        const int row = 16 * (xj ? j : j - XI) + lrow;
-        const int c = lpos ^ swz64(row);
-        if (xj) {
-            int64_t gr = m0 - RAD + row;
-            gr = gr < 0 ? 0 : (gr >= a.m_rows ? a.m_rows - 1 : gr);
-            off[t] = (unsigned)((gr - (m0 - RAD)) * a.ld_in + 16 * c);
-        } else {
-            const int tap = row / BN, nn = row % BN;
-            const int n = n0 + nn < a.n ? n0 + nn : a.n - 1;
-            off[t] = (unsigned)((n - n0) * kw + tap * a.cin + 16 * c);
-        }
-    }
-    auto issue = [&](int buf, int c0) __attribute__((always_inline)) {
-        uint8_t* base = smem + buf * STAGE;
-#pragma unroll
-        for (int t = 0; t < JT; ++t) {
-            const int j = wave + t * NW;
-            if ((t + 1) * NW <= NJ || j < NJ)
-                __builtin_amdgcn_global_load_lds((const void*)((j < XI ? xbase : wbase) + (off[t] + (unsigned)c0)),
-                                                 (__attribute__((address_space(3))) void*)(base + 16 * j * KB), 16, 0, 0);
-        }
-    };
-    // 8-byte piece lg of 32-channel chunk `sub` of row r: byte offset in the row
-    auto piece = [](int r, int sub, int lg) { return 16 * ((2 * sub + (lg >> 1)) ^ swz64(r)) + 8 * (lg & 1); };
-
-    const int nk = a.cin / KB;
-    issue(0, 0);
-    for (int k = 0; k < nk; ++k) {
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-        if (k + 1 < nk) issue((k + 1) & 1, (k + 1) * KB);
-        const uint8_t* xs = smem + (k & 1) * STAGE;
-        const uint8_t* ws = xs + XR * KB;
-        long av[2][TMW], bv[2][TNW];
-        auto frag = [&](int sub, int tap, int f) {
-#pragma unroll
-            for (int i = 0; i < TMW; ++i) {
-                const int r = wm * TMW * 16 + i * 16 + li + tap;
-                av[f][i] = *reinterpret_cast<const long*>(xs + r * KB + piece(r, sub, lg));
-            }
-#pragma unroll
-            for (int j = 0; j < TNW; ++j) {
-                const int r = tap * BN + wn * TNW * 16 + j * 16 + li;
-                bv[f][j] = *reinterpret_cast<const long*>(ws + r * KB + piece(r, sub, lg));
-            }
-        };
-        frag(0, 0, 0);
-#pragma unroll
-        for (int st = 0; st < 2 * TAPS; ++st) {          // (sub, tap) in k order
-            if (st + 1 < 2 * TAPS) frag((st + 1) / TAPS, (st + 1) % TAPS, (st + 1) & 1);
-#pragma unroll
-            for (int i = 0; i < TMW; ++i)
-#pragma unroll
-                for (int j = 0; j < TNW; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(bv[st & 1][j], av[st & 1][i], acc[i][j], 0, 0, 0);
-        }
-    }
-    __syncthreads();   // the epilogue reuses the stage buffers
-    fp8_epilogue<NT, BM, BN, WM, TMW, TNW, EPI>(acc, a, smem, m0, n0, tid);
-}
-
-template <int WM, int WN, int TMW, int TNW, int DB, int TAPS, int EPI>
+template <int WM, int WN, int TMW, int TNW, int KB, int TAPS, int EPI>
 hipError_t run(const ConvArgs& a, hipStream_t s)
 {
-    constexpr int BM = WM * TMW * 16;
-    constexpr int BN = WN * TNW * 16;
+    constexpr int BM = WM * TMW * 32;
+    constexpr int BN = WN * TNW * 32;
     const unsigned m_tiles = (unsigned)((a.m_rows + BM - 1) / BM);
     const unsigned n_tiles = (unsigned)((a.n + BN - 1) / BN);
     dim3 grid((m_tiles + kXcds - 1) / kXcds * kXcds * n_tiles);
-    if constexpr (DB)
-        hipLaunchKernelGGL((conv_mfma_fp8_db<WM, WN, TMW, TNW, TAPS, EPI>), grid, dim3(WM * WN * 64), 0, s, a);
-    else
-        hipLaunchKernelGGL((conv_mfma_fp8<WM, WN, TMW, TNW, TAPS, EPI>), grid, dim3(WM * WN * 64), 0, s, a);
+    hipLaunchKernelGGL((conv_mfma_fp8x64<WM, WN, TMW, TNW, KB, TAPS, EPI>), grid, dim3(WM * WN * 64), 0, s, a);
     return hipGetLastError();
 }
 
-struct Variant { int wm, wn, tmw, tnw, db; };
+// Tile variants: waves (WM x WN), 32 x 32 blocks per wave (TMW x TNW), stage
+// width KB (fixed by the layer's input channels, so a layer's variants all
+// give the same bits).
+struct Variant { int wm, wn, tmw, tnw, kb; };
 constexpr Variant kVariants[] = {
-    {4, 1, 4, 2, 0},   // 0: 256 x 32
-    {4, 1, 4, 4, 0},   // 1: 256 x 64
-    {2, 2, 4, 4, 0},   // 2: 128 x 128
-    {4, 2, 4, 4, 0},   // 3: 256 x 128 (512 threads)
-    {4, 2, 4, 4, 1},   // 4: 256 x 128, double-buffered 64-channel stages
-    {4, 1, 4, 4, 1},   // 5: 256 x 64, double-buffered
-    {4, 1, 4, 2, 1},   // 6: 256 x 32, double-buffered
-    {2, 2, 8, 4, 1},   // 7: 256 x 128, double-buffered, 128 x 64 per wave
-    {8, 2, 4, 4, 1},   // 8: 512 x 128, double-buffered (1024 threads, one block per CU)
-    {8, 1, 4, 2, 0},   // 9: 512 x 32 (the weight tile staged once per 512 rows)
-    {8, 1, 4, 4, 0},   // 10: 512 x 64
-    {8, 1, 4, 4, 1},   // 11: 512 x 64, double-buffered
+    {4, 1, 2, 1, 64},   //  0: 256 x 32
+    {4, 1, 2, 2, 64},   //  1: 256 x 64
+    {2, 2, 2, 2, 64},   //  2: 128 x 128
+    {4, 2, 2, 2, 64},   //  3: 256 x 128 (512 threads)
+    {8, 1, 2, 2, 64},   //  4: 512 x 64 (512 threads)
+    {2, 2, 2, 1, 64},   //  5: 128 x 64, 64 x 32 per wave
+    {2, 1, 2, 2, 64},   //  6: 128 x 64 (128 threads)
+    {2, 2, 4, 2, 64},   //  7: 256 x 128, 128 x 64 per wave
+    {4, 1, 4, 2, 64},   //  8: 512 x 64, 128 x 64 per wave
+    {4, 1, 2, 1, 32},   //  9: 256 x 32, 32-channel stages
+    {4, 1, 2, 2, 32},   // 10: 256 x 64, 32-channel stages
+    {8, 1, 2, 1, 32},   // 11: 512 x 32, 32-channel stages
+    {8, 1, 2, 2, 32},   // 12: 512 x 64, 32-channel stages
+    {2, 1, 2, 1, 32},   // 13: 128 x 32, 32-channel stages (128 threads)
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-#define PVF_FP8_CASE(V) \
-    case V:                                                                                                  \
-        return run<kVariants[V].wm, kVariants[V].wn, kVariants[V].tmw, kVariants[V].tnw, kVariants[V].db, TAPS, \
+#define PVF_FP8_CASE(V)                                                                                          \
+    case V:                                                                                                      \
+        return run<kVariants[V].wm, kVariants[V].wn, kVariants[V].tmw, kVariants[V].tnw, kVariants[V].kb, TAPS, \
                    EPI>(a, s);
 
 template <int TAPS, int EPI>
@@ -448,11 +381,27 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
         switch (v) {
             PVF_FP8_CASE(0)
             PVF_FP8_CASE(1)
-            PVF_FP8_CASE(5)
+            PVF_FP8_CASE(4)
             PVF_FP8_CASE(6)
+            PVF_FP8_CASE(8)
             PVF_FP8_CASE(9)
             PVF_FP8_CASE(10)
             PVF_FP8_CASE(11)
+            PVF_FP8_CASE(12)
+            PVF_FP8_CASE(13)
+        default: return hipErrorInvalidValue;
+        }
+    } else if constexpr (TAPS == 1) {
+        switch (v) {   // the transposed convolutions read 2 C >= 64 channels
+            PVF_FP8_CASE(0)
+            PVF_FP8_CASE(1)
+            PVF_FP8_CASE(2)
+            PVF_FP8_CASE(3)
+            PVF_FP8_CASE(4)
+            PVF_FP8_CASE(5)
+            PVF_FP8_CASE(6)
+            PVF_FP8_CASE(7)
+            PVF_FP8_CASE(8)
         default: return hipErrorInvalidValue;
         }
     } else {
@@ -469,6 +418,8 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_FP8_CASE(9)
             PVF_FP8_CASE(10)
             PVF_FP8_CASE(11)
+            PVF_FP8_CASE(12)
+            PVF_FP8_CASE(13)
         default: return hipErrorInvalidValue;
         }
     }
@@ -481,39 +432,41 @@ int fp8_variant_count() { return kNumVariants; }
 bool fp8_variant_ok(int v, int n, int cin, int taps, Epi epi)
 {
     if (v < 0 || v >= kNumVariants) return false;
-    (void)taps;
     const Variant& x = kVariants[v];
-    const int bn = x.wn * x.tnw * 16;
-    if (cin % (x.db ? 64 : KC) != 0) return false;
-    if (epi == EPI_HEAD) return (v == 0 || v == 1 || v == 5 || v == 6 || v >= 9) && bn == n && x.wn == 1;
-    return bn <= (n < 32 ? 32 : n);
+    const int bn = x.wn * x.tnw * 32;
+    // the stage width follows the input channels: 64 when they allow it
+    if (cin % 32 != 0 || (x.kb == 64) != (cin % 64 == 0)) return false;
+    if (taps == 1 && x.kb != 64) return false;
+    if (epi == EPI_HEAD)
+        return x.wn == 1 && bn == n && (v == 0 || v == 1 || v == 4 || v == 6 || v == 8 || v >= 9);
+    return bn <= n;
 }
 
-// Picks of variant sweeps over 1000 events: the double-buffered 64-channel
-// stages wherever the layer has them (cin a multiple of 64) and enough
-// output channels; the single-buffered tiles for 32- and 64-channel inputs,
-// 512 rows tall where the input has 32 channels (the weight tile is then
-// staged once per 512 rows).
+// Picks of the autotuner over 1000 events: 256 x 64 tiles (two blocks per
+// CU, 64 x 64 per wave) on the 5-tap layers, 256 x 32 or 128 x 32 where the
+// layer has 32 output channels, 128 x 128 and 256 x 128 on the wide
+// transposed convolutions.
 int fp8_default_variant(int n, int cin, int taps, Epi epi)
 {
-    if (epi == EPI_HEAD) return n == 64 ? 1 : (cin <= 32 ? 9 : 0);
-    if (epi == EPI_CONVT && taps == 1) return n >= 128 ? 4 : 6;
-    if (n <= 32) return cin <= 32 ? 9 : 0;
-    if (cin >= 128) return 5;
-    return cin <= 32 ? 10 : 1;
+    const bool k64 = cin % 64 == 0;
+    if (epi == EPI_HEAD) return n == 64 ? (k64 ? 1 : 10) : (k64 ? 0 : 13);
+    if (taps == 1) return n >= 256 ? 2 : (n >= 128 ? 3 : 0);
+    if (n <= 32) return k64 ? 0 : 9;
+    return k64 ? 1 : 10;
 }
 
 std::string fp8_kernel_name(int v, int cin, int taps, Epi epi)
 {
     (void)cin;
     const Variant& x = kVariants[v];
-    return std::string(x.db ? "conv_mfma_fp8_db<" : "conv_mfma_fp8<") + std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " + std::to_string(x.tmw) +
-           ", " + std::to_string(x.tnw) + ", " + std::to_string(taps) + ", " + std::to_string((int)epi) + ">";
+    return "conv_mfma_fp8x64<" + std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " + std::to_string(x.tmw) +
+           ", " + std::to_string(x.tnw) + ", " + std::to_string(x.kb) + ", " + std::to_string(taps) + ", " +
+           std::to_string((int)epi) + ">";
 }
 
 hipError_t launch_conv_fp8(const ConvArgs& a, int taps, Epi epi, int v, hipStream_t s)
 {
-    if (a.cin % KC != 0 || a.m_rows <= 0 || !fp8_variant_ok(v, a.n, a.cin, taps, epi) || !a.col_scale)
+    if (a.cin % 32 != 0 || a.m_rows <= 0 || !fp8_variant_ok(v, a.n, a.cin, taps, epi) || !a.col_scale)
         return hipErrorInvalidValue;
     if (epi != EPI_HEAD && (!a.fold_scale || !a.fold_bias || a.n % 16 != 0)) return hipErrorInvalidValue;
     if (epi == EPI_CONVT && a.cout % 16 != 0) return hipErrorInvalidValue;
