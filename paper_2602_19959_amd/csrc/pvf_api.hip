@@ -74,7 +74,7 @@ size_t layout_work(const pvf_spec* s, int events, size_t off, Plan* p)
     p->prob = take((size_t)events * s->n_bins * sizeof(float));
     p->flags = take((size_t)events * sizeof(int32_t));
     p->order = take((size_t)events * sizeof(int32_t));
-    p->queue = take(((size_t)s->max_tracks_per_event + 3) * sizeof(int32_t));
+    p->queue = take(sizeof(int32_t));
     return off;
 }
 
@@ -723,7 +723,7 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
     ta.flags = flags;
     ta.order = reinterpret_cast<int32_t*>(wk(P.order));
     ta.queue_counter = reinterpret_cast<int32_t*>(wk(P.queue));
-    check(launch_track(ta, E, eng->track_blocks, ta.queue_counter + 1, s));
+    check(launch_track(ta, E, eng->track_blocks, s));
 
     // Calibration (pvf_calibrate only): per-channel absolute maximum of the
     // tensor the launch just enqueued stored.

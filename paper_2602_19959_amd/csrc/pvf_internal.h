@@ -53,7 +53,7 @@ struct Plan {
     size_t flags = 0;              // [E] int32 track-stage status
     size_t order = 0;              // [E] int32 event order of the track work queue
     size_t scales = 0;             // FP8: per-launch column and output scales
-    size_t queue = 0;              // int32 ticket counter + order histogram
+    size_t queue = 0;              // int32 ticket counter of the track work queue
     size_t zero_begin = 0, zero_end = 0;   // region cleared at init
     size_t total = 0;
 };
@@ -241,9 +241,8 @@ struct AmaxArgs {
 hipError_t launch_amax(const AmaxArgs& a, hipStream_t s);
 
 // persistent_blocks > 0: the work-queue form (order kernel + persistent
-// blocks); order_scratch holds max_tracks + 2 ints.  Otherwise one block per event.
-hipError_t launch_track(const TrackArgs& a, int n_events, int persistent_blocks, int* order_scratch,
-                        hipStream_t s);
+// blocks, a.order and a.queue_counter set).  Otherwise one block per event.
+hipError_t launch_track(const TrackArgs& a, int n_events, int persistent_blocks, hipStream_t s);
 hipError_t launch_first_conv(const FirstConvArgs& a, int dtype, hipStream_t s);
 // Conv launches run one of several tile-shape variants of the kernel for
 // the compute dtype; all variants of a dtype give identical bits.

@@ -17,10 +17,12 @@
 //      weights are wave-uniform, so they come through the scalar cache;
 //   B  per sub-chunk of 64 tracks, wave q computes outputs j = q, q+4, ...
 //      of all 64 tracks (softplus, positive), into LDS;
-//   C  thread j adds output j of the sub-chunk's tracks, in track order, to
-//      the LDS histogram.
-// Every bin is therefore a sequential sum in ascending track order: the
-// histogram is deterministic, with no atomics.  The block then writes the
+//   C  the sub-chunk's tracks are grouped by interval (wave ballots, track
+//      order kept inside a group); each (group, output column) pair is summed
+//      in track order in a register by one thread and added to its LDS bin.
+// Every bin is therefore a fixed sequence of sums in ascending track order
+// (sub-chunk by sub-chunk): the histogram is deterministic, with no atomics,
+// and depends only on the event's own tracks.  The block then writes the
 // scaled histogram, once, straight into the UNet's input rows.
 #include <cmath>
 
@@ -291,6 +293,12 @@ __device__ void track_event(const TrackArgs& a, int e, float* smem)
     float* ob = hb + NT * HP;                         // [SUB][n_out + 1]
     int* iv = reinterpret_cast<int*>(ob + SUB * (a.n_out + 1));   // [NT] interval of each item
     int* nbv = iv + NT;                               // [NT] neighbour interval of each track, or -1
+    // a sub-chunk's items grouped by interval: lst [SUB] rows of ob (offsets),
+    // group g = lst[gbeg[g] .. gbeg[g+1]) of interval giv[g]
+    int* lst = nbv + NT;
+    int* giv = lst + SUB;
+    int* gbeg = giv + SUB;                            // [SUB + 1]
+    __shared__ int n_groups;
     // staging list of the chunk's boundary tracks; it shares ob's space: it is
     // written after the own items' last use of ob and read before ob's next
     int* st = reinterpret_cast<int*>(ob);
@@ -365,13 +373,56 @@ __device__ void track_event(const TrackArgs& a, int e, float* smem)
                 outputs_mma<E>(a, xa, sub / SUB, wave, lane, ob);
             }
             __syncthreads();
-            // ---- C: ordered accumulation
-            if (tid < a.n_out) {
-                const int lim = (n - sub) < SUB ? (n - sub) : SUB;
-                for (int l = 0; l < lim; ++l) {
-                    const int i = iv[sub + l];
-                    if (i >= 0) H[i * a.n_out + tid] += ob[l * op + tid];
+            // ---- C: accumulation.  Wave 0 groups the sub-chunk's kept items by
+            // interval (one ballot round per distinct interval, earliest item
+            // first; track order inside a group); then every thread takes
+            // (group, column) pairs, sums the group's outputs in track order in
+            // a register and adds that to the bin once.
+            const int lim = (n - sub) < SUB ? (n - sub) : SUB;
+            if (wave == 0) {
+                const int itv = lane < lim ? iv[sub + lane] : -1;
+                bool pending = itv >= 0;
+                uint64_t rem = __ballot(pending);
+                int ng = 0, pos = 0;
+                while (rem) {
+                    const int v = __shfl(itv, __ffsll((unsigned long long)rem) - 1);
+                    const bool mine = pending && itv == v;
+                    const uint64_t m = __ballot(mine);
+                    if (mine) {
+                        lst[pos + __popcll(m & ((1ull << lane) - 1ull))] = lane * op;   // row offset in ob
+                        pending = false;
+                    }
+                    if (lane == 0) {
+                        giv[ng] = v;
+                        gbeg[ng] = pos;
+                    }
+                    pos += __popcll(m);
+                    ++ng;
+                    rem &= ~m;
                 }
+                if (lane == 0) {
+                    gbeg[ng] = pos;
+                    n_groups = ng;
+                }
+            }
+            __syncthreads();
+            const int ng = n_groups;
+            for (int q = tid; q < ng * a.n_out; q += NT) {
+                const int g = q / a.n_out, j = q - g * a.n_out;
+                const int ue = gbeg[g + 1];
+                int u = gbeg[g];
+                float sum = 0.f;
+                // four items at a time: their LDS reads overlap, the sums stay in order
+                for (; u + 4 <= ue; u += 4) {
+                    const int r0 = lst[u], r1 = lst[u + 1], r2 = lst[u + 2], r3 = lst[u + 3];
+                    const float o0 = ob[r0 + j], o1 = ob[r1 + j], o2 = ob[r2 + j], o3 = ob[r3 + j];
+                    sum += o0;
+                    sum += o1;
+                    sum += o2;
+                    sum += o3;
+                }
+                for (; u < ue; ++u) sum += ob[lst[u] + j];
+                H[giv[g] * a.n_out + j] += sum;
             }
             __syncthreads();
         }
@@ -500,21 +551,25 @@ __global__ __launch_bounds__(NT) void track_stage_queue(TrackArgs a, int n_event
 }
 
 // Queue order: a counting sort of the events by descending track count
-// (counts clamped to [0, max_tracks + 1]; malformed offsets count 0), in one
-// block.  Events of equal count may come out in any order: the order only
-// schedules work, it never changes a result.  The kernel also resets the
-// queue counter for the launch that follows, so no memset is needed (safe
-// under graph capture).  hist: max_tracks + 2 ints of scratch.
+// (counts clamped to [0, min(max_tracks, kOrderBuckets - 2) + 1]; malformed
+// offsets count 0), in one block, with the count histogram and the scatter
+// in LDS.  Events of equal (clamped) count may come out in any order: the
+// order only schedules work, it never changes a result.  The kernel also
+// resets the queue counter for the launch that follows, so no memset is
+// needed (safe under graph capture).
 constexpr int kOrderThreads = 1024;
-__global__ __launch_bounds__(kOrderThreads) void track_order(TrackArgs a, int n_events, int* hist)
+constexpr int kOrderBuckets = 4096;
+__global__ __launch_bounds__(kOrderThreads) void track_order(TrackArgs a, int n_events)
 {
+    __shared__ int hist[kOrderBuckets];
     __shared__ int part[kOrderThreads];
     const int tid = threadIdx.x;
-    const int nb = a.max_tracks + 2;
+    const int cap = a.max_tracks < kOrderBuckets - 2 ? a.max_tracks : kOrderBuckets - 2;
+    const int nb = cap + 2;
     auto bucket = [&](int e) {           // descending count -> ascending bucket
         const int64_t beg = a.offsets[e], end = a.offsets[e + 1];
         const int64_t t = (beg < 0 || end < beg || end > a.n_tracks_total) ? 0 : end - beg;
-        return nb - 1 - (int)(t > a.max_tracks ? a.max_tracks + 1 : t);
+        return nb - 1 - (int)(t > cap ? cap + 1 : t);
     };
     for (int b = tid; b < nb; b += kOrderThreads) hist[b] = 0;
     __syncthreads();
@@ -552,12 +607,12 @@ static_assert(NT * HP * sizeof(float) >= NT * Net<__bf16>::KP * 2 && NT * HP * s
               "the layer-input tile fits the FP32 hidden-activation space");
 static size_t track_stage_lds_bytes(int n_out, int n_intervals)
 {
-    return sizeof(float) * ((size_t)n_out * n_intervals + NT * HP + SUB * (n_out + 1)) + sizeof(int) * 2 * NT;
+    return sizeof(float) * ((size_t)n_out * n_intervals + NT * HP + SUB * (n_out + 1)) +
+           sizeof(int) * (2 * NT + 3 * SUB + 1);
 }
 
 template <class E>
-hipError_t launch_track_typed(const TrackArgs& a, int n_events, int persistent_blocks, int* order_scratch,
-                              hipStream_t s)
+hipError_t launch_track_typed(const TrackArgs& a, int n_events, int persistent_blocks, hipStream_t s)
 {
     if (a.n_out < 1 || a.n_out > NT) return hipErrorInvalidValue;   // one thread per output column
     const size_t lds = track_stage_lds_bytes(a.n_out, a.n_intervals);
@@ -573,7 +628,7 @@ hipError_t launch_track_typed(const TrackArgs& a, int n_events, int persistent_b
         hipLaunchKernelGGL(track_stage<E>, dim3(n_events), dim3(NT), lds, s, a);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(track_order, dim3(1), dim3(kOrderThreads), 0, s, a, n_events, order_scratch);
+    hipLaunchKernelGGL(track_order, dim3(1), dim3(kOrderThreads), 0, s, a, n_events);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     const int blocks = persistent_blocks < n_events ? persistent_blocks : n_events;
@@ -581,17 +636,16 @@ hipError_t launch_track_typed(const TrackArgs& a, int n_events, int persistent_b
     return hipGetLastError();
 }
 
-hipError_t launch_track(const TrackArgs& a, int n_events, int persistent_blocks, int* order_scratch,
-                        hipStream_t s)
+hipError_t launch_track(const TrackArgs& a, int n_events, int persistent_blocks, hipStream_t s)
 {
     if (a.mlp_dtype != PVF_FP32 && (!a.mlp_lp || a.n_out > kMlpOutN ||
                                     (a.mlp_dtype == PVF_FP8_E4M3 && (!a.mlp_in_inv || !a.mlp_col))))
         return hipErrorInvalidValue;
     switch (a.mlp_dtype) {
-    case PVF_FP32: return launch_track_typed<float>(a, n_events, persistent_blocks, order_scratch, s);
-    case PVF_BF16: return launch_track_typed<__bf16>(a, n_events, persistent_blocks, order_scratch, s);
-    case PVF_FP16: return launch_track_typed<_Float16>(a, n_events, persistent_blocks, order_scratch, s);
-    case PVF_FP8_E4M3: return launch_track_typed<uint8_t>(a, n_events, persistent_blocks, order_scratch, s);
+    case PVF_FP32: return launch_track_typed<float>(a, n_events, persistent_blocks, s);
+    case PVF_BF16: return launch_track_typed<__bf16>(a, n_events, persistent_blocks, s);
+    case PVF_FP16: return launch_track_typed<_Float16>(a, n_events, persistent_blocks, s);
+    case PVF_FP8_E4M3: return launch_track_typed<uint8_t>(a, n_events, persistent_blocks, s);
     default: return hipErrorInvalidValue;
     }
 }
