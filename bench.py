@@ -111,6 +111,17 @@ def layer_bytes(spec, eb):
     return {k: (v * U if v is not None else v) for k, v in out.items()}
 
 
+def layer_bytes_between(spec, eb, first):
+    """Bytes per event of the tensor that launch `first` stores for the
+    launch after it (the one a fusion keeps out of HBM)."""
+    n, c0, U = spec.n_levels, spec.base_channels, units(spec)
+    L0 = spec.n_bins // U
+    if first == "enc0.c1":
+        return L0 * c0 * eb * U
+    l = int(first[3])                      # "decL.c2"
+    return (L0 >> l) * (c0 << l) * eb * U
+
+
 def cpu_threads():
     """(threads to use, affinity size, OMP_NUM_THREADS or None): every core
     of this process's affinity set, unless OMP_NUM_THREADS names a smaller
@@ -563,6 +574,20 @@ def main():
         valid_tracks = float(T.sum())
         mean_ms = [statistics.mean(v) for v in per_launch]
         flops_launch = [2.0 * (macs[n] * valid_tracks if n == "track" else macs[n] * E) for n in names]
+        eb = {"fp32": 4, "fp8_e4m3": 1}.get(dtype, 2)
+        lbytes = layer_bytes(spec, eb)
+        lbytes["track"] = (36.0 * valid_tracks + E * spec.n_bins * 4) / E
+        # a launch that ran inside another ("first_conv (in enc0.c2)",
+        # "transposed conv (in dec1.c2)"): its work is the host launch's; the
+        # tensor between the two never goes through HBM
+        for j, k in enumerate(kernels):
+            if " (in " in k:
+                i = names.index(k.split(" (in ")[1].rstrip(")"))
+                flops_launch[i] += flops_launch[j]
+                flops_launch[j] = 0.0
+                inner = layer_bytes_between(spec, eb, names[min(i, j)])
+                lbytes[names[i]] = lbytes[names[i]] + lbytes[names[j]] - 2 * inner
+                lbytes[names[j]] = 0.0
         print(f"[bench] {'launch':14s} {'kernel':36s} {'ms':>8s} {'TFLOP/s':>8s}", file=sys.stderr)
         for n, k, ms, fl in zip(names, kernels, mean_ms, flops_launch):
             print(f"[bench] {n:14s} {k:36s} {ms:8.3f} {fl / ms / 1e9:8.2f}", file=sys.stderr)
@@ -578,9 +603,6 @@ def main():
         dom_name, dom = max(by_kernel.items(), key=lambda kv: kv[1]["ms"])
         avg_dur_s = dom["ms"] / dom["launches"] / 1e3
         flops_per_launch = dom["flops"] / dom["launches"]
-        eb = {"fp32": 4, "fp8_e4m3": 1}.get(dtype, 2)
-        lbytes = layer_bytes(spec, eb)
-        lbytes["track"] = (36.0 * valid_tracks + E * spec.n_bins * 4) / E
         bytes_per_launch = sum(lbytes[n] * E for n in dom["layers"]) / dom["launches"]
         peak = PEAK_TFLOPS[dtype]
         ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)          # flop per byte

@@ -255,7 +255,11 @@ pvf_status pvf_graph_launch(pvf_engine *eng);
  * enc0.c1 (the first convolution), enqueues nothing when enc0.c2's tile
  * variant computes the first convolution in its own staging (FP32, BF16 and
  * FP16 by default); its kernel name then reads "first_conv (in enc0.c2)" and
- * its profiled time is zero. */
+ * its profiled time is zero.  Likewise, in BF16 and FP16, the transposed-conv
+ * slots up0 .. up(n_levels - 3) enqueue nothing when the decoder conv before
+ * each (dec1.c2, dec2.c2, ...) has a tile variant holding all its output
+ * channels (the default): that conv then runs the transposed conv in its
+ * epilogue, and its kernel name reads "transposed conv (in dec1.c2)". */
 int pvf_launch_count(const pvf_engine *eng);
 
 /* Name of launch i (e.g. "track", "enc0.c2", "up1", "peaks"); NULL if out
@@ -299,8 +303,10 @@ pvf_status pvf_profile_read(pvf_engine *eng, float *ms, int n);
  * per-layer parity checks: copies tensor `name` ("hist", "enc0.c1", ...,
  * "dec0.c1", "prob"), for the first n_events events, into d_dst as float32
  * [n_events][C][L] (channels first), on the engine's stream.  Returns
- * PVF_ERR_INVALID_ARGUMENT for an unknown name; *out_count receives the
- * number of floats (C * L * n_events), also when d_dst is NULL. */
+ * PVF_ERR_INVALID_ARGUMENT for an unknown name, and for "decL.c2" when that
+ * conv runs the following transposed conv in its epilogue (its output is
+ * then never stored); *out_count receives the number of floats
+ * (C * L * n_events), also when d_dst is NULL. */
 pvf_status pvf_debug_tensor(pvf_engine *eng, const char *name, int32_t n_events, float *d_dst,
                             int64_t *out_count);
 

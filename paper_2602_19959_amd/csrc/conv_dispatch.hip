@@ -49,6 +49,12 @@ int conv_default_variant(int dtype, int n, int cin, int taps, Epi epi)
     return lp_default_variant(n, cin, taps, epi);
 }
 
+int conv_default_up_variant(int dtype, int n, int cin)
+{
+    if (dtype == PVF_BF16 || dtype == PVF_FP16) return lp_default_up_variant(n, cin);
+    return -1;
+}
+
 std::string conv_kernel_name(int dtype, int variant, int cin, int taps, Epi epi)
 {
     if (dtype == PVF_FP32) return f32_kernel_name(variant, taps, epi);

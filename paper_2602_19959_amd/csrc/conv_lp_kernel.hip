@@ -19,7 +19,9 @@
 //     the tile is staged in LDS and written back as whole 16-byte row chunks
 //     (channels-last rows are contiguous), with the fused max-pool or the
 //     transposed-conv row interleave; the head epilogue works on the FP32
-//     accumulators and writes the FP32 probability;
+//     accumulators and writes the FP32 probability; a decoder conv whose
+//     output only feeds the next transposed conv runs that transposed conv on
+//     its tile in the epilogue (EPI_UP) and stores only the upsampled rows;
 //   * conv_mfma_lp_first runs enc0.c2 with the first convolution (one input
 //     channel, five taps) computed in its halo staging from the histogram
 //     rows, so that 32-channel tensor never goes through HBM.
@@ -140,6 +142,67 @@ __device__ __forceinline__ void lp_epilogue(const f32x4 (&acc)[TMW][TNW], const 
             }
         }
         __syncthreads();
+        if constexpr (EPI == EPI_UP) {
+            // The transposed conv of the tile (BN == n: every channel of its
+            // rows is here): column c2 = tap * up_cout + o of the upsampled
+            // output is sum_c tile[row][c] up_w[c2][c], over 32-channel chunks
+            // in ascending order with the weights in the A slot, as a
+            // transposed-conv launch accumulates it, so the bits are the same.
+            using V = typename Lp<T>::vec8;
+            const T* uw = static_cast<const T*>(a.up_w);
+            f32x4 up[TMW][TNW];
+#pragma unroll
+            for (int i = 0; i < TMW; ++i)
+#pragma unroll
+                for (int j = 0; j < TNW; ++j) up[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+            for (int kk = 0; kk < BN; kk += 32) {
+                V av[TMW], bv[TNW];
+#pragma unroll
+                for (int i = 0; i < TMW; ++i)
+                    av[i] = *reinterpret_cast<const V*>(ot + (rw + i * 16 + li) * OP + kk + 8 * lg);
+#pragma unroll
+                for (int j = 0; j < TNW; ++j)
+                    bv[j] = *reinterpret_cast<const V*>(uw + (size_t)(cw + j * 16 + li) * BN + kk + 8 * lg);
+#pragma unroll
+                for (int i = 0; i < TMW; ++i)
+#pragma unroll
+                    for (int j = 0; j < TNW; ++j) up[i][j] = Lp<T>::mfma(bv[j], av[i], up[i][j]);
+            }
+            __syncthreads();   // every wave is past its reads of the tile
+            // bias, no activation, one rounding; the upsampled tile replaces it
+#pragma unroll
+            for (int j = 0; j < TNW; ++j) {
+                const int col = cw + j * 16 + 4 * lg;
+                float b[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) b[v] = a.up_b[(col + v) % a.up_cout];
+#pragma unroll
+                for (int i = 0; i < TMW; ++i) {
+                    T y[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) y[v] = (T)(up[i][j][v] + b[v]);
+                    *reinterpret_cast<uint2*>(ot + (rw + i * 16 + li) * OP + col) = *reinterpret_cast<const uint2*>(y);
+                }
+            }
+            __syncthreads();
+            // rows 2 t + tap of the destination, as a transposed-conv launch writes them
+            T* uo = static_cast<T*>(a.up_out);
+            constexpr int UCH = BN / 8;
+            for (int idx = tid; idx < BM * UCH; idx += NT) {
+                const int row = idx / UCH, q = idx % UCH;
+                if (m0 + row >= a.m_rows) continue;
+                int64_t e;
+                int loc;
+                rows.at(row, e, loc);
+                if (loc < kGuard || loc >= a.r_in - kGuard) continue;
+                const uint4 v = *reinterpret_cast<const uint4*>(ot + row * OP + 8 * q);
+                const int tj = (8 * q) / a.up_cout, o = 8 * q - tj * a.up_cout;
+                const int64_t ro = e * a.up_r_out + kGuard + 2 * (loc - kGuard) + tj;
+                *reinterpret_cast<uint4*>(uo + ro * a.up_ld + o) = v;
+            }
+            return;
+        }
         T* out = static_cast<T*>(a.out);
         constexpr int CH = BN / 8;                  // 16-byte chunks per tile row
         const int n_valid = a.n - n0 < BN ? a.n - n0 : BN;
@@ -583,7 +646,22 @@ constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 template <class T, int TAPS, int EPI>
 hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
 {
-    if constexpr (EPI == EPI_HEAD) {
+    if constexpr (EPI == EPI_UP) {
+        switch (v) {
+            PVF_LP_CASE(1)
+            PVF_LP_CASE(2)
+            PVF_LP_CASE(3)
+            PVF_LP_CASE(4)
+            PVF_LP_CASE(9)
+            PVF_LP_CASE(12)
+            PVF_LP_CASE(13)
+            PVF_LP_CASE(15)
+            PVF_LP_CASE(19)
+            PVF_LP_CASE(22)
+            PVF_LP_CASE(23)
+        default: return hipErrorInvalidValue;
+        }
+    } else if constexpr (EPI == EPI_HEAD) {
         switch (v) {
             PVF_LP_CASE(0)
             PVF_LP_CASE(1)
@@ -638,6 +716,7 @@ hipError_t launch_typed(const ConvArgs& a, int taps, Epi epi, int v, hipStream_t
         case EPI_STORE: return dispatch<T, 5, EPI_STORE>(v, a, s);
         case EPI_POOL: return dispatch<T, 5, EPI_POOL>(v, a, s);
         case EPI_HEAD: return dispatch<T, 5, EPI_HEAD>(v, a, s);
+        case EPI_UP: return dispatch<T, 5, EPI_UP>(v, a, s);
         default: return hipErrorInvalidValue;
         }
     }
@@ -659,6 +738,9 @@ bool lp_variant_ok(int v, int n, int cin, int taps, Epi epi)
     if (epi == EPI_HEAD)
         return (v == 0 || v == 1 || v == 4 || v == 5 || v == 11 || v == 13 || v == 14 || v == 16 || v >= 20) &&
                bn == n && x.wn == 1;
+    if (epi == EPI_UP)   // the tile must hold every channel of its rows
+        return (v == 1 || v == 2 || v == 3 || v == 4 || v == 9 || v == 12 || v == 13 || v == 15 || v == 19 ||
+                v == 22 || v == 23) && bn == n;
     return bn <= (n < 32 ? 32 : n);
 }
 
@@ -679,6 +761,16 @@ int lp_default_variant(int n, int cin, int taps, Epi epi)
         return cin >= 128 ? 13 : (cin % 64 == 0 ? 8 : 13);
     }
     return cin >= 256 ? 19 : (cin == 128 ? 22 : 3);
+}
+
+// Decoder convs that run the following transposed conv in their epilogue
+// need a tile of all their output channels; the autotuner's BF16 picks at
+// 1000 events: 512 x 64 for 64 channels, 256 x 128 for 128; -1 where no
+// such variant fits.
+int lp_default_up_variant(int n, int cin)
+{
+    const int v = n == 64 ? 22 : (n == 128 ? 3 : -1);
+    return v >= 0 && lp_variant_ok(v, n, cin, kTaps, EPI_UP) ? v : -1;
 }
 
 std::string lp_kernel_name(int dtype, int v, int taps, Epi epi)
@@ -743,6 +835,8 @@ hipError_t launch_conv_lp(int dtype, const ConvArgs& a, int taps, Epi epi, int v
 {
     if (a.cin % 32 != 0 || a.m_rows <= 0 || !lp_variant_ok(v, a.n, a.cin, taps, epi)) return hipErrorInvalidValue;
     if (epi == EPI_CONVT && a.cout % 8 != 0) return hipErrorInvalidValue;
+    if (epi == EPI_UP && (!a.up_w || !a.up_b || !a.up_out || a.up_cout % 8 != 0 || 2 * a.up_cout != a.n))
+        return hipErrorInvalidValue;
     if (dtype == PVF_BF16) return launch_typed<__bf16>(a, taps, epi, v, s);
     if (dtype == PVF_FP16) return launch_typed<_Float16>(a, taps, epi, v, s);
     return hipErrorInvalidValue;

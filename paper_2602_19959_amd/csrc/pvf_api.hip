@@ -398,6 +398,7 @@ struct pvf_engine {
         size_t col = 0;               // FP8: offsets (floats) into the scales region
         size_t fold = 0;              // FP8 stored outputs: [n] s_n / a_out, then [n] bias / a_out
         bool first = false;           // enc0.c2: may compute the first convolution (the launch before it) itself
+        bool up = false;              // dec(l+1).c2: may run the transposed conv (the launch after it) in its epilogue
     };
     std::vector<int> out_channels;       // channels of the tensor launch i stores (0: none)
     std::vector<size_t> outinv_off, a_off;   // FP8: 1/a and a of launch i's stored tensor
@@ -432,6 +433,33 @@ std::string track_kernel_name(bool persistent, int dtype)
 bool fuses_first(const pvf_engine* e, int i)
 {
     return e->conv[i].first && !e->calib_table && conv_first_ok(e->spec.compute_dtype, e->conv[i].variant);
+}
+
+// Whether launch i (a decoder conv2 below the deepest level) runs the
+// transposed conv that follows it in its epilogue: 16-bit engines, a tile
+// variant whose tile holds all its output channels, and no calibration
+// running (the calibration reads the stored output).
+bool fuses_up(const pvf_engine* e, int i)
+{
+    const auto& c = e->conv[i];
+    const int dt = e->spec.compute_dtype;
+    return c.up && !e->calib_table && (dt == PVF_BF16 || dt == PVF_FP16) &&
+           conv_variant_ok(dt, c.variant, c.n, c.cin, c.taps, EPI_UP);
+}
+
+// Kernel names of the launches a fused transposed conv involves.
+void name_up(pvf_engine* e)
+{
+    const int dt = e->spec.compute_dtype;
+    for (size_t i = 0; i + 1 < e->conv.size(); ++i) {
+        const auto& c = e->conv[i];
+        if (!c.up) continue;
+        const auto& u = e->conv[i + 1];
+        const bool f = fuses_up(e, (int)i);
+        e->kernels[i] = conv_kernel_name(dt, c.variant, c.cin, c.taps, f ? EPI_UP : c.epi);
+        e->kernels[i + 1] = f ? "transposed conv (in " + e->names[i] + ")"
+                              : conv_kernel_name(dt, u.variant, u.cin, u.taps, u.epi);
+    }
 }
 
 // Kernel names of enc0.c1 and enc0.c2 for enc0.c2's current variant.
@@ -507,6 +535,17 @@ void build_names(pvf_engine* e)
     // convolution into its staging when it has the max-pool epilogue
     if (n > 1) e->conv[2].first = true;
     name_first(e);
+    // dec(l+1).c2 feeds only up(l) (l + 1 <= n - 2): it may run it itself, and
+    // takes a tile variant that can when there is one
+    for (int l = n - 3; l >= 0; --l) {
+        const int p = find("dec" + std::to_string(l + 1) + ".c2");
+        if (p < 0 || find("up" + std::to_string(l)) != p + 1) continue;
+        auto& c = e->conv[p];
+        c.up = true;
+        const int v = conv_default_up_variant(e->spec.compute_dtype, c.n, c.cin);
+        if (v >= 0) c.variant = v;
+    }
+    name_up(e);
     // calibration table: the stored tensors' channels, in launch order
     e->calib_off.assign(e->names.size(), 0);
     e->calib_total = 0;
@@ -806,20 +845,40 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
         }
     }
     // ---- decoder
+    bool up_done = false;             // the previous launch ran this level's transposed conv
     for (int l = n - 2; l >= 0; --l) {
         const Level& lv = P.lv[l];
         const Level& lo = P.lv[l + 1];
-        ConvArgs u = conv_args(eng, W.up[l], act(P.d[l + 1]), lo.C, lo.R, EU, act(P.cat[l]) + (size_t)lv.C * eb,
-                               2 * lv.C);
-        u.n = 2 * lv.C;
-        u.cout = lv.C;
-        u.r_out = lv.R;
-        conv(u, 1, EPI_CONVT, l, 2 * lv.C, lv.C);
+        if (up_done) {
+            check(hipSuccess);        // it ran in dec(l+1).c2's epilogue
+        } else {
+            ConvArgs u = conv_args(eng, W.up[l], act(P.d[l + 1]), lo.C, lo.R, EU,
+                                   act(P.cat[l]) + (size_t)lv.C * eb, 2 * lv.C);
+            u.n = 2 * lv.C;
+            u.cout = lv.C;
+            u.r_out = lv.R;
+            conv(u, 1, EPI_CONVT, l, 2 * lv.C, lv.C);
+        }
         conv(conv_args(eng, W.dec[l][0], act(P.cat[l]), 2 * lv.C, lv.R, EU, act(P.a[l]), lv.C), kTaps, EPI_STORE, l,
              lv.C, 0);
         if (l > 0) {
-            conv(conv_args(eng, W.dec[l][1], act(P.a[l]), lv.C, lv.R, EU, act(P.d[l]), lv.C), kTaps, EPI_STORE, l,
-                 lv.C, 0);
+            ConvArgs c2 = conv_args(eng, W.dec[l][1], act(P.a[l]), lv.C, lv.R, EU, act(P.d[l]), lv.C);
+            up_done = fuses_up(eng, li);
+            if (up_done) {
+                // up(l - 1) on this launch's output tiles: its weights, bias
+                // and destination (the upsampled half of level l - 1's concat)
+                const Level& lu = P.lv[l - 1];
+                const WeightLayout::Conv& wu = W.up[l - 1];
+                c2.up_w = at<uint16_t>(eng, eng->plan.weights_lp) + wu.w;
+                c2.up_b = wbase + wu.b;
+                c2.up_out = act(P.cat[l - 1]) + (size_t)lu.C * eb;
+                c2.up_ld = 2 * lu.C;
+                c2.up_r_out = lu.R;
+                c2.up_cout = lu.C;
+                conv(c2, kTaps, EPI_UP, l, lv.C, 0);
+            } else {
+                conv(c2, kTaps, EPI_STORE, l, lv.C, 0);
+            }
         } else {
             ConvArgs b = conv_args(eng, W.dec[0][1], act(P.a[0]), lv.C, lv.R, EU, nullptr, 0);
             b.head_w = wbase + W.head_w;
@@ -1113,6 +1172,7 @@ pvf_status pvf_set_launch_variant(pvf_engine* eng, int i, int v)
     c.variant = v;
     eng->kernels[i] = conv_kernel_name(eng->spec.compute_dtype, v, c.cin, c.taps, c.epi);
     name_first(eng);
+    name_up(eng);
     return PVF_OK;
 }
 
@@ -1145,8 +1205,12 @@ pvf_status pvf_autotune(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertice
             if (st != PVF_OK || r == 0) continue;
             for (int i = 0; i < nl; ++i) {
                 // enc0.c2 is charged the first convolution too: it runs either
-                // inside it or as the launch before it
-                const float t = ms[i] + (eng->conv[i].first ? ms[i - 1] : 0.f);
+                // inside it or as the launch before it; a decoder conv2 that can
+                // run the next transposed conv is charged that launch too, and
+                // a transposed conv is not timed in a pass where it ran inside
+                // the launch before it
+                if (i > 0 && eng->conv[i - 1].up && fuses_up(eng, i - 1)) continue;
+                const float t = ms[i] + (eng->conv[i].first ? ms[i - 1] : 0.f) + (eng->conv[i].up ? ms[i + 1] : 0.f);
                 if (eng->conv[i].variant == v && t < best[i]) { best[i] = t; pick[i] = v; }
             }
         }
@@ -1292,6 +1356,9 @@ pvf_status pvf_debug_tensor(pvf_engine* eng, const char* name, int32_t n_events,
         if (l >= 1 && l < n - 1 && s == "dec" + L + ".c2") set(P.d[l], C, l, C, 0, eb);
     }
     if (!found) return PVF_ERR_INVALID_ARGUMENT;
+    // a decoder conv2 that ran its transposed conv in the epilogue never
+    // stores its own output
+    if (producer >= 0 && s.rfind("dec", 0) == 0 && fuses_up(eng, producer)) return PVF_ERR_INVALID_ARGUMENT;
     if (g.src_bytes == 1) {
         if (producer < 0) return PVF_ERR_INVALID_ARGUMENT;
         g.ch_scale = at<float>(eng, P.scales) + eng->a_off[producer];

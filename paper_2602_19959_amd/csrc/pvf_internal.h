@@ -70,7 +70,10 @@ struct WeightLayout {
     size_t total = 0;
 };
 
-enum Epi { EPI_STORE = 0, EPI_POOL = 1, EPI_CONVT = 2, EPI_HEAD = 3 };
+// EPI_UP: a decoder conv whose output is consumed only by the transposed
+// conv that follows it; the epilogue runs that transposed conv on its own
+// output tile (which then never goes to HBM) and stores the upsampled rows.
+enum Epi { EPI_STORE = 0, EPI_POOL = 1, EPI_CONVT = 2, EPI_HEAD = 3, EPI_UP = 4 };
 
 // Row m0 + t of a channels-last batch with R rows per event -> (event, row
 // within the event), for the rows of one output tile (t < 2^20).  The tile's
@@ -149,6 +152,13 @@ struct ConvArgs {
     const float* first_x0;      // [m_rows] histogram rows, the input level's row layout
     const float* first_w;       // [cin][taps]
     const float* first_b;       // [cin]
+    // EPI_UP: the transposed conv applied to this launch's output tile
+    const void* up_w;           // packed [2 up_cout][n] (compute dtype), as a transposed-conv launch reads it
+    const float* up_b;          // [up_cout]
+    void* up_out;               // its destination: row 0, channel 0 of the upsampled half
+    int up_ld;                  // elements per destination row
+    int up_r_out;               // destination rows per event
+    int up_cout;                // transposed-conv output channels
 };
 
 struct TrackArgs {
@@ -258,6 +268,9 @@ std::string conv_first_kernel_name(int dtype, int variant);
 int conv_variant_count(int dtype);
 bool conv_variant_ok(int dtype, int variant, int n, int cin, int taps, Epi epi);
 int conv_default_variant(int dtype, int n, int cin, int taps, Epi epi);
+// Default tile variant of a 5-tap launch that runs the transposed conv after
+// it in its epilogue (EPI_UP), or -1 where no variant of the dtype can.
+int conv_default_up_variant(int dtype, int n, int cin);
 std::string conv_kernel_name(int dtype, int variant, int cin, int taps, Epi epi);
 
 // per-precision implementations behind the functions above
@@ -276,6 +289,7 @@ int lp_default_variant(int n, int cin, int taps, Epi epi);
 std::string lp_kernel_name(int dtype, int variant, int taps, Epi epi);
 hipError_t launch_conv_lp_first(int dtype, const ConvArgs& a, int variant, hipStream_t s);
 bool lp_first_ok(int variant);
+int lp_default_up_variant(int n, int cin);
 std::string lp_first_kernel_name(int dtype, int variant);
 
 hipError_t launch_conv_fp8(const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s);

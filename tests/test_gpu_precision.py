@@ -88,6 +88,42 @@ def test_variants_identical(lp, batch16):
     assert tried >= 4
 
 
+def test_fused_transposed_convs_identical(lp, batch16):
+    """By default dec1.c2 and dec2.c2 run up0 and up1 in their epilogues (the
+    tiles hold all their output channels), so those launch slots enqueue
+    nothing and the decoder conv's own output never reaches HBM.  With the
+    two convs on tiles that cannot (part of their channels), the transposed
+    convs run as launches of their own: every output is the same bit for bit.
+    The unstored outputs are refused by the debug view while fused."""
+    from paper_2602_19959_amd._binding import PvfError
+    dt, eng, out = lp
+    names, kernels = eng.launch_names(), eng.launch_kernels()
+    prods = [names.index(f"dec{l + 1}.c2") for l in (0, 1)]
+    for l, i in zip((0, 1), prods):
+        assert names[i + 1] == f"up{l}" and kernels[i + 1] == f"transposed conv (in dec{l + 1}.c2)"
+    with pytest.raises(PvfError):
+        eng.debug_tensor("dec1.c2", 1)
+    base = eng.variants()
+    try:
+        for i in prods:
+            for v in range(eng.variant_count(i)):
+                if eng.set_variant(i, v) and not eng.launch_kernels()[i + 1].startswith("transposed conv (in"):
+                    break
+            else:
+                pytest.fail(f"no unfused variant for {names[i]}")
+        kernels2 = eng.launch_kernels()
+        say(dt, "unfused:", [kernels2[i] for i in prods], [kernels2[i + 1] for i in prods])
+        got = run(eng, batch16)
+        for k in ("prob", "z", "integral", "n_vertices", "status", "bin"):
+            assert np.array_equal(got[k], out[k]), k
+        assert eng.debug_tensor("dec1.c2", 1).numel() > 0
+    finally:
+        for i, v in enumerate(base):
+            if v >= 0:
+                eng.set_variant(i, v)
+    assert eng.launch_kernels() == kernels
+
+
 def test_layer_taps_close_to_fp32(lp, batch16):
     """Per-layer activations stay within 16-bit rounding of the oracle's
     (normwise 3e-2 for BF16's 8-bit mantissa, 5e-3 for FP16), so a wrong
