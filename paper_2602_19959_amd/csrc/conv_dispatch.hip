@@ -52,6 +52,7 @@ int conv_default_variant(int dtype, int n, int cin, int taps, Epi epi)
 int conv_default_up_variant(int dtype, int n, int cin)
 {
     if (dtype == PVF_BF16 || dtype == PVF_FP16) return lp_default_up_variant(n, cin);
+    if (dtype == PVF_FP8_E4M3) return fp8_default_up_variant(n, cin);
     return -1;
 }
 

@@ -32,6 +32,10 @@
 // into the second LDS buffer (16-byte global_load_lds) while stage k is on the
 // matrix cores.  LDS rows hold KB bytes in 16-byte chunks, chunk c of row r at
 // c ^ s(r) (s = bits 2..3 of r for 64-byte rows, bit 3 for 32-byte rows).
+//
+// A decoder conv whose output only feeds the next transposed conv runs that
+// transposed conv on its FP8 output tile in the epilogue (EPI_UP) and stores
+// only the upsampled rows.
 #include "pvf_internal.h"
 
 namespace pvf {
@@ -291,6 +295,77 @@ void conv_mfma_fp8x64(ConvArgs a)
                 }
             }
         __syncthreads();
+        if constexpr (EPI == EPI_UP) {
+            // The transposed conv of the tile (BN == n: every channel of its
+            // rows is here): per 64 channels one MFMA whose lane halves take
+            // the two 32-channel chunks, weights in the A slot, as a
+            // transposed-conv launch pairs them, so the bits are the same.
+            // The tile holds the stored FP8 values (x / a_out), which the
+            // transposed conv's weights were folded for.
+            const uint8_t* uw = static_cast<const uint8_t*>(a.up_w);
+            f32x16 up[TMW][TNW];
+#pragma unroll
+            for (int i = 0; i < TMW; ++i)
+#pragma unroll
+                for (int j = 0; j < TNW; ++j)
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) up[i][j][v] = 0.f;
+            for (int kk = 0; kk < BN; kk += 64) {
+                i32x8 xv[TMW], wv[TNW];
+#pragma unroll
+                for (int i = 0; i < TMW; ++i) {
+                    const uint8_t* r = ot + (rw + i * 32 + r32) * OP + kk + 32 * h;
+                    xv[i] = join(*reinterpret_cast<const u32x4*>(r), *reinterpret_cast<const u32x4*>(r + 16));
+                }
+#pragma unroll
+                for (int j = 0; j < TNW; ++j) {
+                    const uint8_t* r = uw + (size_t)(cw + j * 32 + r32) * BN + kk + 32 * h;
+                    wv[j] = join(*reinterpret_cast<const u32x4*>(r), *reinterpret_cast<const u32x4*>(r + 16));
+                }
+#pragma unroll
+                for (int i = 0; i < TMW; ++i)
+#pragma unroll
+                    for (int j = 0; j < TNW; ++j)
+                        up[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(wv[j], xv[i], up[i][j], 0, 0, 0, 0,
+                                                                                   0, 0);
+            }
+            __syncthreads();   // every wave is past its reads of the tile
+            // folded scale and bias of the transposed conv, no activation
+#pragma unroll
+            for (int j = 0; j < TNW; ++j)
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int col = cw + j * 32 + 8 * g + 4 * h;
+                    const f32x4 fs = *reinterpret_cast<const f32x4*>(a.up_fold_scale + col);
+                    const f32x4 fb = *reinterpret_cast<const f32x4*>(a.up_fold_bias + col);
+#pragma unroll
+                    for (int i = 0; i < TMW; ++i) {
+                        float y[4];
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) y[v] = fminf(fmaxf(fmaf(up[i][j][4 * g + v], fs[v], fb[v]), -448.f), 448.f);
+                        uint32_t w = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(y[0], y[1], 0, false);
+                        w = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(y[2], y[3], (int)w, true);
+                        *reinterpret_cast<uint32_t*>(ot + (rw + i * 32 + r32) * OP + col) = w;
+                    }
+                }
+            __syncthreads();
+            // rows 2 t + tap of the destination, as a transposed-conv launch writes them
+            uint8_t* uo = static_cast<uint8_t*>(a.up_out);
+            constexpr int UCH = BN / 16;
+            for (int idx = tid; idx < BM * UCH; idx += NT) {
+                const int row = idx / UCH, q = idx % UCH;
+                if (m0 + row >= a.m_rows) continue;
+                int64_t e;
+                int loc;
+                rows.at(row, e, loc);
+                if (loc < kGuard || loc >= a.r_in - kGuard) continue;
+                const uint4 v = *reinterpret_cast<const uint4*>(ot + row * OP + 16 * q);
+                const int tj = (16 * q) / a.up_cout, o = 16 * q - tj * a.up_cout;
+                const int64_t ro = e * a.up_r_out + kGuard + 2 * (loc - kGuard) + tj;
+                *reinterpret_cast<uint4*>(uo + ro * a.up_ld + o) = v;
+            }
+            return;
+        }
         uint8_t* out = static_cast<uint8_t*>(a.out);
         constexpr int CH = BN / 16;                 // 16-byte chunks per tile row
         const int n_valid = a.n - n0 < BN ? a.n - n0 : BN;
@@ -377,7 +452,18 @@ constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 template <int TAPS, int EPI>
 hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
 {
-    if constexpr (EPI == EPI_HEAD) {
+    if constexpr (EPI == EPI_UP) {
+        switch (v) {   // 64-channel stages, tiles of 64 or 128 columns
+            PVF_FP8_CASE(1)
+            PVF_FP8_CASE(2)
+            PVF_FP8_CASE(3)
+            PVF_FP8_CASE(4)
+            PVF_FP8_CASE(6)
+            PVF_FP8_CASE(7)
+            PVF_FP8_CASE(8)
+        default: return hipErrorInvalidValue;
+        }
+    } else if constexpr (EPI == EPI_HEAD) {
         switch (v) {
             PVF_FP8_CASE(0)
             PVF_FP8_CASE(1)
@@ -439,6 +525,8 @@ bool fp8_variant_ok(int v, int n, int cin, int taps, Epi epi)
     if (taps == 1 && x.kb != 64) return false;
     if (epi == EPI_HEAD)
         return x.wn == 1 && bn == n && (v == 0 || v == 1 || v == 4 || v == 6 || v == 8 || v >= 9);
+    if (epi == EPI_UP)   // the tile must hold every channel of its rows
+        return (v == 1 || v == 2 || v == 3 || v == 4 || v == 6 || v == 7 || v == 8) && bn == n && taps == 5;
     return bn <= n;
 }
 
@@ -453,6 +541,15 @@ int fp8_default_variant(int n, int cin, int taps, Epi epi)
     if (taps == 1) return n >= 256 ? 2 : (n >= 128 ? 3 : 0);
     if (n <= 32) return k64 ? 0 : 9;
     return k64 ? 1 : 10;
+}
+
+// A decoder conv that runs the following transposed conv in its epilogue
+// needs a tile of all its output channels: 256 x 64 for 64, 256 x 128 for
+// 128; -1 where no variant fits.
+int fp8_default_up_variant(int n, int cin)
+{
+    const int v = n == 64 ? 1 : (n == 128 ? 3 : -1);
+    return v >= 0 && fp8_variant_ok(v, n, cin, kTaps, EPI_UP) ? v : -1;
 }
 
 std::string fp8_kernel_name(int v, int cin, int taps, Epi epi)
@@ -470,11 +567,15 @@ hipError_t launch_conv_fp8(const ConvArgs& a, int taps, Epi epi, int v, hipStrea
         return hipErrorInvalidValue;
     if (epi != EPI_HEAD && (!a.fold_scale || !a.fold_bias || a.n % 16 != 0)) return hipErrorInvalidValue;
     if (epi == EPI_CONVT && a.cout % 16 != 0) return hipErrorInvalidValue;
+    if (epi == EPI_UP && (!a.up_w || !a.up_fold_scale || !a.up_fold_bias || !a.up_out || a.up_cout % 16 != 0 ||
+                          2 * a.up_cout != a.n))
+        return hipErrorInvalidValue;
     if (taps == 5) {
         switch (epi) {
         case EPI_STORE: return dispatch<5, EPI_STORE>(v, a, s);
         case EPI_POOL: return dispatch<5, EPI_POOL>(v, a, s);
         case EPI_HEAD: return dispatch<5, EPI_HEAD>(v, a, s);
+        case EPI_UP: return dispatch<5, EPI_UP>(v, a, s);
         default: return hipErrorInvalidValue;
         }
     }

@@ -436,15 +436,14 @@ bool fuses_first(const pvf_engine* e, int i)
 }
 
 // Whether launch i (a decoder conv2 below the deepest level) runs the
-// transposed conv that follows it in its epilogue: 16-bit engines, a tile
-// variant whose tile holds all its output channels, and no calibration
-// running (the calibration reads the stored output).
+// transposed conv that follows it in its epilogue: 16-bit and FP8 engines,
+// a tile variant whose tile holds all its output channels, and no
+// calibration running (the calibration reads the stored output).
 bool fuses_up(const pvf_engine* e, int i)
 {
     const auto& c = e->conv[i];
     const int dt = e->spec.compute_dtype;
-    return c.up && !e->calib_table && (dt == PVF_BF16 || dt == PVF_FP16) &&
-           conv_variant_ok(dt, c.variant, c.n, c.cin, c.taps, EPI_UP);
+    return c.up && !e->calib_table && dt != PVF_FP32 && conv_variant_ok(dt, c.variant, c.n, c.cin, c.taps, EPI_UP);
 }
 
 // Kernel names of the launches a fused transposed conv involves.
@@ -869,7 +868,13 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
                 // and destination (the upsampled half of level l - 1's concat)
                 const Level& lu = P.lv[l - 1];
                 const WeightLayout::Conv& wu = W.up[l - 1];
-                c2.up_w = at<uint16_t>(eng, eng->plan.weights_lp) + wu.w;
+                if (dt == PVF_FP8_E4M3) {
+                    c2.up_w = at<uint8_t>(eng, eng->plan.weights_lp) + wu.w;
+                    c2.up_fold_scale = scales + eng->conv[li + 1].fold;
+                    c2.up_fold_bias = scales + eng->conv[li + 1].fold + eng->conv[li + 1].n;
+                } else {
+                    c2.up_w = at<uint16_t>(eng, eng->plan.weights_lp) + wu.w;
+                }
                 c2.up_b = wbase + wu.b;
                 c2.up_out = act(P.cat[l - 1]) + (size_t)lu.C * eb;
                 c2.up_ld = 2 * lu.C;

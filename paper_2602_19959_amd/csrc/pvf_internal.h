@@ -154,11 +154,13 @@ struct ConvArgs {
     const float* first_b;       // [cin]
     // EPI_UP: the transposed conv applied to this launch's output tile
     const void* up_w;           // packed [2 up_cout][n] (compute dtype), as a transposed-conv launch reads it
-    const float* up_b;          // [up_cout]
+    const float* up_b;          // [up_cout] (16-bit engines; FP8 folds it into up_fold_bias)
     void* up_out;               // its destination: row 0, channel 0 of the upsampled half
     int up_ld;                  // elements per destination row
     int up_r_out;               // destination rows per event
     int up_cout;                // transposed-conv output channels
+    const float* up_fold_scale; // FP8: the transposed conv's folded column scales (16-byte aligned)
+    const float* up_fold_bias;  // FP8: its folded bias (16-byte aligned)
 };
 
 struct TrackArgs {
@@ -290,6 +292,7 @@ std::string lp_kernel_name(int dtype, int variant, int taps, Epi epi);
 hipError_t launch_conv_lp_first(int dtype, const ConvArgs& a, int variant, hipStream_t s);
 bool lp_first_ok(int variant);
 int lp_default_up_variant(int n, int cin);
+int fp8_default_up_variant(int n, int cin);
 std::string lp_first_kernel_name(int dtype, int variant);
 
 hipError_t launch_conv_fp8(const ConvArgs& a, int taps, Epi epi, int variant, hipStream_t s);

@@ -140,6 +140,37 @@ def test_variants_identical(fp8, batch16):
     assert tried >= 3
 
 
+def test_fused_transposed_convs_identical(fp8, batch16):
+    """By default dec2.c2 and dec1.c2 run up1 and up0 in their epilogues on
+    their FP8 output tiles; with both convs on tiles that cannot (part of
+    their channels) the transposed convs run as launches of their own and
+    every output is the same bit for bit."""
+    from paper_2602_19959_amd._binding import PvfError
+    eng, out = fp8
+    names, kernels = eng.launch_names(), eng.launch_kernels()
+    prods = [names.index(p) for p in ("dec2.c2", "dec1.c2")]
+    for l, i in zip((1, 0), prods):
+        assert names[i + 1] == f"up{l}" and kernels[i + 1] == f"transposed conv (in {names[i]})"
+        with pytest.raises(PvfError):
+            eng.debug_tensor(names[i], 1)
+    base = eng.variants()
+    try:
+        for i in prods:
+            for v in range(eng.variant_count(i)):
+                if eng.set_variant(i, v) and not eng.launch_kernels()[i + 1].startswith("transposed conv (in"):
+                    break
+            else:
+                pytest.fail(f"no unfused variant for {names[i]}")
+        got = run(eng, batch16)
+        for k in ("prob", "z", "integral", "n_vertices", "status", "bin"):
+            assert np.array_equal(got[k], out[k]), k
+    finally:
+        for i, v in enumerate(base):
+            if v >= 0:
+                eng.set_variant(i, v)
+    assert eng.launch_kernels() == kernels
+
+
 def test_layer_taps_close_to_fp32(fp8, batch16):
     """Per-layer activations (dequantised with their channel scales) stay
     within FP8 rounding of the oracle's, normwise: 3 mantissa bits give a
