@@ -259,7 +259,11 @@ pvf_status pvf_graph_launch(pvf_engine *eng);
  * slots up0 .. up(n_levels - 3) enqueue nothing when the decoder conv before
  * each (dec1.c2, dec2.c2, ...) has a tile variant holding all its output
  * channels (the default): that conv then runs the transposed conv in its
- * epilogue, and its kernel name reads "transposed conv (in dec1.c2)". */
+ * epilogue, and its kernel name reads "transposed conv (in dec1.c2)".  And
+ * in BF16 and FP16 with 32 level-0 channels, the dec0.c1 slot enqueues
+ * nothing when the head launch ("dec0.c2+head") takes a tile variant that
+ * computes dec0.c1 in the same kernel (the default); its name then reads
+ * "conv (in dec0.c2+head)". */
 int pvf_launch_count(const pvf_engine *eng);
 
 /* Name of launch i (e.g. "track", "enc0.c2", "up1", "peaks"); NULL if out
@@ -303,9 +307,10 @@ pvf_status pvf_profile_read(pvf_engine *eng, float *ms, int n);
  * per-layer parity checks: copies tensor `name` ("hist", "enc0.c1", ...,
  * "dec0.c1", "prob"), for the first n_events events, into d_dst as float32
  * [n_events][C][L] (channels first), on the engine's stream.  Returns
- * PVF_ERR_INVALID_ARGUMENT for an unknown name, and for "decL.c2" when that
- * conv runs the following transposed conv in its epilogue (its output is
- * then never stored); *out_count receives the number of floats
+ * PVF_ERR_INVALID_ARGUMENT for an unknown name, for "decL.c2" when that
+ * conv runs the following transposed conv in its epilogue, and for
+ * "dec0.c1" when the head launch computes it (those outputs are then never
+ * stored); *out_count receives the number of floats
  * (C * L * n_events), also when d_dst is NULL. */
 pvf_status pvf_debug_tensor(pvf_engine *eng, const char *name, int32_t n_events, float *d_dst,
                             int64_t *out_count);

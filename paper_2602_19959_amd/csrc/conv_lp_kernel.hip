@@ -581,6 +581,194 @@ void conv_mfma_lp_db(ConvArgs a)
     lp_epilogue<T, NT, BM, BN, WM, TMW, TNW, EPI>(acc, a, smem, m0, n0, tid);
 }
 
+// dec0.c1 and dec0.c2 + head in one launch (level 0 of the decoder, 32
+// output channels each): the intermediate 32-channel tensor stays in LDS.
+// A block of WM waves owns BO = 64 WM - 16 output rows starting at m0:
+//   phase 1 computes dec0.c1's outputs for the BA = 64 WM rows from m0 - 2
+//     (the tile and its halo), from two 32-channel stages of the
+//     concatenated input, in the standalone launch's k order (chunk, tap)
+//     and with its epilogue (bias, LeakyReLU, one rounding); rows that are
+//     guard rows or outside the batch are set to zero, as the stored tensor
+//     holds them; they go to LDS in the swizzled layout of a 32-channel halo
+//     tile;
+//   phase 2 runs dec0.c2 on that tile exactly as the standalone head launch
+//     runs it on its staged halo (same fragments, k order and head
+//     epilogue), so every bit of p is the same as from the two launches.
+// c1: dec0.c1's arguments; c2: dec0.c2 + head's (in and ld_in unused).
+template <class T, int WM>
+__global__ __launch_bounds__(WM * 64) __attribute__((amdgpu_waves_per_eu(WM >= 8 ? 2 : 3)))
+void conv_mfma_lp_dec0(ConvArgs c1, ConvArgs c2)
+{
+    using V = typename Lp<T>::vec8;
+    constexpr int NT = WM * 64;
+    constexpr int BA = WM * 64;                  // phase-1 rows per block
+    constexpr int BO = BA - 16;                  // output rows per block
+    constexpr int KC = 32, NCH = 4;              // one 32-channel stage, 64-byte rows
+    constexpr int XR1 = BA + kTaps - 1;          // phase-1 halo rows
+    constexpr int WR = kTaps * 32;               // weight rows (tap-major) of either conv
+    constexpr int ATR = BA + 16;                 // intermediate tile rows (phase 2 reads up to BA + 3)
+    __shared__ __attribute__((aligned(16))) T xs[(XR1 + WR) * KC];   // phase-1 stage; phase-2 weights
+    __shared__ __attribute__((aligned(16))) T at[ATR * KC];          // dec0.c1's output tile
+    T* ws = xs + XR1 * KC;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int m_tiles = (int)((c2.m_rows + BO - 1) / BO);
+    const int xcd = (int)(blockIdx.x % kXcds), slot = (int)(blockIdx.x / kXcds);
+    const int m_tile = slot * kXcds + xcd;
+    if (m_tile >= m_tiles) return;
+    const int64_t m0 = (int64_t)m_tile * BO;
+    const int64_t a0 = m0 - 2;                   // first phase-1 row
+
+    const T* in1 = static_cast<const T*>(c1.in);
+    const T* w1 = static_cast<const T*>(c1.w);
+    const T* w2 = static_cast<const T*>(c2.w);
+
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // ---- phase 1: dec0.c1 over rows a0 .. a0 + BA - 1, one 32-channel stage
+    // at a time; the next stage's 16-byte loads (and, during the last stage,
+    // dec0.c2's weights) are in flight in registers while the current stage
+    // is on the matrix cores.  Halo rows outside the batch are clamped (they
+    // only feed zeroed or discarded rows).
+    constexpr int NC1 = (XR1 + WR) * NCH, P1 = (NC1 + NT - 1) / NT;
+    constexpr int NC2 = WR * NCH, P2 = (NC2 + NT - 1) / NT;
+    auto fetch1 = [&](int c0, u32x4 (&v)[P1]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < P1; ++u) {
+            const int idx = min(tid + u * NT, NC1 - 1);
+            const int row = idx / NCH, q = idx % NCH;
+            const T* src;
+            if (row < XR1) {
+                int64_t g = a0 - 2 + row;
+                g = g < 0 ? 0 : (g >= c1.m_rows ? c1.m_rows - 1 : g);
+                src = in1 + g * c1.ld_in + c0 + 8 * q;
+            } else {
+                const int wr = row - XR1, tap = wr / 32, n = wr % 32;
+                src = w1 + (int64_t)n * (kTaps * c1.cin) + tap * c1.cin + c0 + 8 * q;
+            }
+            v[u] = *reinterpret_cast<const u32x4*>(src);
+        }
+    };
+    auto store1 = [&](const u32x4 (&v)[P1]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < P1; ++u) {
+            // halo rows in xs, weight rows in ws, each region swizzled by its own row index
+            const int idx = tid + u * NT;
+            const int row = idx / NCH, q = idx % NCH;
+            if ((u + 1) * NT <= NC1 || idx < NC1)
+                *reinterpret_cast<u32x4*>(row < XR1 ? xs + lds_at<NCH>(row, q) : ws + lds_at<NCH>(row - XR1, q)) = v[u];
+        }
+    };
+    auto fetch2 = [&](u32x4 (&v)[P2]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < P2; ++u) {
+            const int idx = min(tid + u * NT, NC2 - 1);
+            const int wr = idx / NCH, q = idx % NCH, tap = wr / 32, n = wr % 32;
+            v[u] = *reinterpret_cast<const u32x4*>(w2 + (int64_t)n * (kTaps * c2.cin) + tap * c2.cin + 8 * q);
+        }
+    };
+    u32x4 cur[P1], nxt[P1], wv2[P2];
+    fetch1(0, cur);
+    for (int c0 = 0; c0 < c1.cin; c0 += KC) {
+        store1(cur);
+        __syncthreads();
+        if (c0 + KC < c1.cin) fetch1(c0 + KC, nxt);
+        else fetch2(wv2);
+#pragma unroll
+        for (int tap = 0; tap < kTaps; ++tap) {
+            V av[4], bv[2];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = *reinterpret_cast<const V*>(xs + lds_at<NCH>(wave * 64 + i * 16 + li + tap, lg));
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                bv[j] = *reinterpret_cast<const V*>(ws + lds_at<NCH>(tap * 32 + j * 16 + li, lg));
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = Lp<T>::mfma(bv[j], av[i], acc[i][j]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < P1; ++u) cur[u] = nxt[u];
+    }
+    // dec0.c1's epilogue into the tile: row r of the tile is row a0 + r
+    {
+        const RowMap rmap(a0 < 0 ? 0 : a0, c1.r_in);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = wave * 64 + i * 16 + li;
+            const int64_t g = a0 + r;
+            bool keep = g >= 0 && g < c1.m_rows;
+            if (keep) {
+                int64_t e;
+                int loc;
+                rmap.at((int)(g - (a0 < 0 ? 0 : a0)), e, loc);
+                keep = loc >= kGuard && loc < c1.r_in - kGuard;
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int col = j * 16 + 4 * lg;
+                T y[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) y[v] = keep ? (T)lrelu(acc[i][j][v] + c1.bias[col + v], c1.slope) : (T)0.f;
+                *reinterpret_cast<uint2*>(at + lds_at<NCH>(r, col / 8) + (col % 8)) = *reinterpret_cast<const uint2*>(y);
+            }
+        }
+    }
+    // ---- phase 2: dec0.c2's weights, already in registers, into the free stage buffer
+#pragma unroll
+    for (int u = 0; u < P2; ++u) {
+        const int idx = tid + u * NT;
+        if ((u + 1) * NT <= NC2 || idx < NC2) *reinterpret_cast<u32x4*>(ws + lds_at<NCH>(idx / NCH, idx % NCH)) = wv2[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < kTaps; ++tap) {
+        V av[4], bv[2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[i] = *reinterpret_cast<const V*>(at + lds_at<NCH>(wave * 64 + i * 16 + li + tap, lg));
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bv[j] = *reinterpret_cast<const V*>(ws + lds_at<NCH>(tap * 32 + j * 16 + li, lg));
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = Lp<T>::mfma(bv[j], av[i], acc[i][j]);
+    }
+    // head epilogue: output rows t < BO of the block
+    const RowMap rows(m0, c2.r_in);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float sum = 0.f;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int c = j * 16 + 4 * lg;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sum += lrelu(acc[i][j][v] + c2.bias[c + v], c2.slope) * c2.head_w[c + v];
+        }
+        sum += __shfl_xor(sum, 16);
+        sum += __shfl_xor(sum, 32);
+        const int t = wave * 64 + i * 16 + li;
+        if (lg == 0 && t < BO && m0 + t < c2.m_rows) {
+            int64_t e;
+            int loc;
+            rows.at(t, e, loc);
+            if (loc >= kGuard && loc < c2.r_in - kGuard)
+                c2.prob[e * c2.l_out + (loc - kGuard)] = 1.f / (1.f + expf(-(sum + c2.head_b)));
+        }
+    }
+}
+
 template <class T, int WM, int WN, int TMW, int TNW, int KC, int PF, int TAPS, int EPI>
 hipError_t run(const ConvArgs& a, hipStream_t s)
 {
@@ -635,6 +823,8 @@ constexpr Variant kVariants[] = {
     {8, 1, 4, 2, 32, 2},   // 21: 512 x 32, double-buffered
     {8, 1, 4, 4, 32, 0},   // 22: 512 x 64
     {8, 1, 4, 4, 32, 2},   // 23: 512 x 64, double-buffered
+    {4, 1, 4, 2, 32, 3},   // 24: head launch with dec0.c1 fused (conv_mfma_lp_dec0, 4 waves, 240 rows)
+    {8, 1, 4, 2, 32, 3},   // 25: the same with 8 waves (496 rows)
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -731,8 +921,8 @@ int lp_variant_count() { return kNumVariants; }
 bool lp_variant_ok(int v, int n, int cin, int taps, Epi epi)
 {
     if (v < 0 || v >= kNumVariants) return false;
-    (void)taps;
     const Variant& x = kVariants[v];
+    if (x.pf == 3) return epi == EPI_HEAD && n == 32 && cin == 32 && taps == kTaps;   // dec0 fused: 32-channel head
     const int bn = x.wn * x.tnw * 16;
     if (cin % x.kc != 0) return false;
     if (epi == EPI_HEAD)
@@ -773,9 +963,35 @@ int lp_default_up_variant(int n, int cin)
     return v >= 0 && lp_variant_ok(v, n, cin, kTaps, EPI_UP) ? v : -1;
 }
 
+bool lp_dec0_ok(int v) { return v >= 0 && v < kNumVariants && kVariants[v].pf == 3; }
+
+hipError_t launch_conv_lp_dec0(int dtype, const ConvArgs& c1, const ConvArgs& c2, int v, hipStream_t s)
+{
+    if (!lp_dec0_ok(v) || c1.cin % 32 != 0 || c1.n != 32 || c2.cin != 32 || c2.n != 32 || c1.m_rows != c2.m_rows ||
+        c1.r_in != c2.r_in || c2.m_rows <= 0 || !c2.prob || !c2.head_w)
+        return hipErrorInvalidValue;
+    const int wm = kVariants[v].wm;
+    const int bo = wm * 64 - 16;
+    const unsigned m_tiles = (unsigned)((c2.m_rows + bo - 1) / bo);
+    dim3 grid((m_tiles + kXcds - 1) / kXcds * kXcds);
+    if (dtype == PVF_BF16) {
+        if (wm == 4) hipLaunchKernelGGL((conv_mfma_lp_dec0<__bf16, 4>), grid, dim3(256), 0, s, c1, c2);
+        else hipLaunchKernelGGL((conv_mfma_lp_dec0<__bf16, 8>), grid, dim3(512), 0, s, c1, c2);
+    } else if (dtype == PVF_FP16) {
+        if (wm == 4) hipLaunchKernelGGL((conv_mfma_lp_dec0<_Float16, 4>), grid, dim3(256), 0, s, c1, c2);
+        else hipLaunchKernelGGL((conv_mfma_lp_dec0<_Float16, 8>), grid, dim3(512), 0, s, c1, c2);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 std::string lp_kernel_name(int dtype, int v, int taps, Epi epi)
 {
     const Variant& x = kVariants[v];
+    if (x.pf == 3)
+        return std::string("conv_mfma_lp_dec0<") + (dtype == PVF_BF16 ? "__bf16" : "_Float16") + ", " +
+               std::to_string(x.wm) + ">";
     if (x.pf == 2)
         return std::string("conv_mfma_lp_db<") + (dtype == PVF_BF16 ? "__bf16" : "_Float16") + ", " +
                std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " + std::to_string(x.tmw) + ", " +

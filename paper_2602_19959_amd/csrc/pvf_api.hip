@@ -399,6 +399,7 @@ struct pvf_engine {
         size_t fold = 0;              // FP8 stored outputs: [n] s_n / a_out, then [n] bias / a_out
         bool first = false;           // enc0.c2: may compute the first convolution (the launch before it) itself
         bool up = false;              // dec(l+1).c2: may run the transposed conv (the launch after it) in its epilogue
+        bool dec0 = false;            // dec0.c2+head: may compute dec0.c1 (the launch before it) in the same kernel
     };
     std::vector<int> out_channels;       // channels of the tensor launch i stores (0: none)
     std::vector<size_t> outinv_off, a_off;   // FP8: 1/a and a of launch i's stored tensor
@@ -444,6 +445,29 @@ bool fuses_up(const pvf_engine* e, int i)
     const auto& c = e->conv[i];
     const int dt = e->spec.compute_dtype;
     return c.up && !e->calib_table && dt != PVF_FP32 && conv_variant_ok(dt, c.variant, c.n, c.cin, c.taps, EPI_UP);
+}
+
+// Whether launch i (dec0.c2 + head) computes dec0.c1 in the same kernel:
+// 16-bit engines, a variant that does, and no calibration running (the
+// calibration reads dec0.c1's stored output).
+bool fuses_dec0(const pvf_engine* e, int i)
+{
+    const int dt = e->spec.compute_dtype;
+    return e->conv[i].dec0 && !e->calib_table && (dt == PVF_BF16 || dt == PVF_FP16) && lp_dec0_ok(e->conv[i].variant);
+}
+
+// Kernel names of dec0.c1 and dec0.c2 + head for the head's current variant.
+void name_dec0(pvf_engine* e)
+{
+    const int dt = e->spec.compute_dtype;
+    for (size_t i = 1; i < e->conv.size(); ++i) {
+        const auto& c = e->conv[i];
+        if (!c.dec0) continue;
+        const auto& p = e->conv[i - 1];
+        const bool f = fuses_dec0(e, (int)i);
+        e->kernels[i] = conv_kernel_name(dt, c.variant, c.cin, c.taps, c.epi);
+        e->kernels[i - 1] = f ? "conv (in " + e->names[i] + ")" : conv_kernel_name(dt, p.variant, p.cin, p.taps, p.epi);
+    }
 }
 
 // Kernel names of the launches a fused transposed conv involves.
@@ -545,6 +569,17 @@ void build_names(pvf_engine* e)
         if (v >= 0) c.variant = v;
     }
     name_up(e);
+    // dec0.c2 + head may compute dec0.c1 (the launch before it) itself
+    {
+        const int h = find("dec0.c2+head");
+        if (h > 0 && find("dec0.c1") == h - 1) {
+            auto& c = e->conv[h];
+            c.dec0 = true;
+            const int v = conv_default_dec0_variant(e->spec.compute_dtype);
+            if (v >= 0 && conv_variant_ok(e->spec.compute_dtype, v, c.n, c.cin, c.taps, c.epi)) c.variant = v;
+        }
+    }
+    name_dec0(e);
     // calibration table: the stored tensors' channels, in launch order
     e->calib_off.assign(e->names.size(), 0);
     e->calib_total = 0;
@@ -858,8 +893,10 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
             u.r_out = lv.R;
             conv(u, 1, EPI_CONVT, l, 2 * lv.C, lv.C);
         }
-        conv(conv_args(eng, W.dec[l][0], act(P.cat[l]), 2 * lv.C, lv.R, EU, act(P.a[l]), lv.C), kTaps, EPI_STORE, l,
-             lv.C, 0);
+        const ConvArgs c1 = conv_args(eng, W.dec[l][0], act(P.cat[l]), 2 * lv.C, lv.R, EU, act(P.a[l]), lv.C);
+        const bool dec0 = l == 0 && fuses_dec0(eng, li + 1);
+        if (dec0) check(hipSuccess);  // computed inside the head launch
+        else conv(c1, kTaps, EPI_STORE, l, lv.C, 0);
         if (l > 0) {
             ConvArgs c2 = conv_args(eng, W.dec[l][1], act(P.a[l]), lv.C, lv.R, EU, act(P.d[l]), lv.C);
             up_done = fuses_up(eng, li);
@@ -890,7 +927,15 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
             b.head_b = eng->head_b;
             b.prob = prob;
             b.l_out = lv.L;
-            conv(b, kTaps, EPI_HEAD, 0, 0, 0);
+            if (dec0) {
+                check(launch_conv_lp_dec0(dt, c1, b, var(), s));
+            } else if (eng->conv[li].dec0 && lp_dec0_ok(var())) {
+                // a fused variant while calibrating: dec0.c1 ran on its own,
+                // and the head takes the default tile
+                check(launch_conv(dt, b, kTaps, EPI_HEAD, conv_default_variant(dt, b.n, b.cin, kTaps, EPI_HEAD), s));
+            } else {
+                conv(b, kTaps, EPI_HEAD, 0, 0, 0);
+            }
         }
     }
     // ---- peaks
@@ -1178,6 +1223,7 @@ pvf_status pvf_set_launch_variant(pvf_engine* eng, int i, int v)
     eng->kernels[i] = conv_kernel_name(eng->spec.compute_dtype, v, c.cin, c.taps, c.epi);
     name_first(eng);
     name_up(eng);
+    name_dec0(eng);
     return PVF_OK;
 }
 
@@ -1215,7 +1261,9 @@ pvf_status pvf_autotune(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertice
                 // a transposed conv is not timed in a pass where it ran inside
                 // the launch before it
                 if (i > 0 && eng->conv[i - 1].up && fuses_up(eng, i - 1)) continue;
-                const float t = ms[i] + (eng->conv[i].first ? ms[i - 1] : 0.f) + (eng->conv[i].up ? ms[i + 1] : 0.f);
+                if (i + 1 < nl && eng->conv[i + 1].dec0 && fuses_dec0(eng, i + 1)) continue;
+                const float t = ms[i] + (eng->conv[i].first || eng->conv[i].dec0 ? ms[i - 1] : 0.f) +
+                                (eng->conv[i].up ? ms[i + 1] : 0.f);
                 if (eng->conv[i].variant == v && t < best[i]) { best[i] = t; pick[i] = v; }
             }
         }
@@ -1364,6 +1412,8 @@ pvf_status pvf_debug_tensor(pvf_engine* eng, const char* name, int32_t n_events,
     // a decoder conv2 that ran its transposed conv in the epilogue never
     // stores its own output
     if (producer >= 0 && s.rfind("dec", 0) == 0 && fuses_up(eng, producer)) return PVF_ERR_INVALID_ARGUMENT;
+    if (producer >= 0 && producer + 1 < (int)eng->conv.size() && fuses_dec0(eng, producer + 1))
+        return PVF_ERR_INVALID_ARGUMENT;
     if (g.src_bytes == 1) {
         if (producer < 0) return PVF_ERR_INVALID_ARGUMENT;
         g.ch_scale = at<float>(eng, P.scales) + eng->a_off[producer];

@@ -273,6 +273,9 @@ int conv_default_variant(int dtype, int n, int cin, int taps, Epi epi);
 // Default tile variant of a 5-tap launch that runs the transposed conv after
 // it in its epilogue (EPI_UP), or -1 where no variant of the dtype can.
 int conv_default_up_variant(int dtype, int n, int cin);
+// Default variant of the head launch that also computes dec0.c1 (the 8-wave
+// fused kernel for BF16/FP16), or -1 for dtypes without one.
+int conv_default_dec0_variant(int dtype);
 std::string conv_kernel_name(int dtype, int variant, int cin, int taps, Epi epi);
 
 // per-precision implementations behind the functions above
@@ -292,6 +295,11 @@ std::string lp_kernel_name(int dtype, int variant, int taps, Epi epi);
 hipError_t launch_conv_lp_first(int dtype, const ConvArgs& a, int variant, hipStream_t s);
 bool lp_first_ok(int variant);
 int lp_default_up_variant(int n, int cin);
+// Head-launch variants that also compute dec0.c1 (32-channel network): the
+// 32-channel tensor between the two convs stays in LDS.  c1: dec0.c1's
+// arguments, c2: dec0.c2 + head's.
+bool lp_dec0_ok(int variant);
+hipError_t launch_conv_lp_dec0(int dtype, const ConvArgs& c1, const ConvArgs& c2, int variant, hipStream_t s);
 int fp8_default_up_variant(int n, int cin);
 std::string lp_first_kernel_name(int dtype, int variant);
 

@@ -124,6 +124,39 @@ def test_fused_transposed_convs_identical(lp, batch16):
     assert eng.launch_kernels() == kernels
 
 
+def test_fused_level0_identical(lp, batch16):
+    """Head-launch variants 24 and 25 compute dec0.c1 in the same kernel, so
+    its 32-channel output stays in LDS and the dec0.c1 slot enqueues nothing:
+    every output equals the two-launch path bit for bit, and the debug view
+    refuses the unstored dec0.c1 while fused."""
+    from paper_2602_19959_amd._binding import PvfError
+    dt, eng, out = lp
+    names = eng.launch_names()
+    h = names.index("dec0.c2+head")
+    base = eng.variants()
+    assert base[h] == 25, "the fused 8-wave head is the default"
+    try:
+        assert eng.set_variant(h, 20)   # the two-launch path as the reference
+        want = run(eng, batch16)
+        assert eng.launch_kernels()[h - 1] != "conv (in dec0.c2+head)"
+        for k in ("prob", "z", "integral", "n_vertices", "status", "bin"):
+            assert np.array_equal(want[k], out[k]), k
+        for v in (24, 25):
+            assert eng.set_variant(h, v)
+            k = eng.launch_kernels()
+            assert k[h - 1] == "conv (in dec0.c2+head)" and k[h].startswith("conv_mfma_lp_dec0<"), k[h - 1:h + 1]
+            got = run(eng, batch16)
+            for key in ("prob", "z", "integral", "n_vertices", "status", "bin"):
+                assert np.array_equal(got[key], out[key]), (v, key)
+            with pytest.raises(PvfError):
+                eng.debug_tensor("dec0.c1", 1)
+            say(dt, "fused level 0, variant", v, "identical")
+    finally:
+        for i, v in enumerate(base):
+            if v >= 0:
+                eng.set_variant(i, v)
+
+
 def test_layer_taps_close_to_fp32(lp, batch16):
     """Per-layer activations stay within 16-bit rounding of the oracle's
     (normwise 3e-2 for BF16's 8-bit mantissa, 5e-3 for FP16), so a wrong
@@ -132,13 +165,20 @@ def test_layer_taps_close_to_fp32(lp, batch16):
     w = weights()
     taps = oracle.unet_taps(w.s_in * oracle.histogram(batch16.tracks_of(0), w)[0], w)
     bound = {"bf16": 3e-2, "fp16": 5e-3}[dt]
-    # re-run event 0 alone so the debug buffers hold it
-    run(eng, batch16.subset([0]))
-    for name in ("enc0.c2", "pool1", "enc3.c2", "up2", "dec1.c1", "dec0.c1"):
-        got = eng.debug_tensor(name, 1).cpu().numpy().reshape(taps[name].shape)
-        err = parity.tap_err(got, taps[name])
-        say(dt, name, "normwise %.2e" % err)
-        assert err <= bound, name
+    # re-run event 0 alone so the debug buffers hold it, with the head on a
+    # tile that leaves dec0.c1 to its own launch (the fused head keeps it in LDS)
+    h = eng.launch_names().index("dec0.c2+head")
+    vh = eng.variants()[h]
+    assert eng.set_variant(h, 20)
+    try:
+        run(eng, batch16.subset([0]))
+        for name in ("enc0.c2", "pool1", "enc3.c2", "up2", "dec1.c1", "dec0.c1"):
+            got = eng.debug_tensor(name, 1).cpu().numpy().reshape(taps[name].shape)
+            err = parity.tap_err(got, taps[name])
+            say(dt, name, "normwise %.2e" % err)
+            assert err <= bound, name
+    finally:
+        eng.set_variant(h, vh)
 
 
 def test_full_batch_sampled(lp):
