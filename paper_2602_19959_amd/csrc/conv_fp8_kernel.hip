@@ -28,10 +28,14 @@
 // output channel 8 (v / 4) + 4 (l / 32) + v % 4 (four consecutive channels per
 // register quad).
 //
-// Stages are double-buffered: stage k + 1 streams from global memory straight
-// into the second LDS buffer (16-byte global_load_lds) while stage k is on the
-// matrix cores.  LDS rows hold KB bytes in 16-byte chunks, chunk c of row r at
-// c ^ s(r) (s = bits 2..3 of r for 64-byte rows, bit 3 for 32-byte rows).
+// Stages are double-buffered (NB = 2): stage k + 1 streams from global memory
+// straight into the second LDS buffer (16-byte global_load_lds) while stage k
+// is on the matrix cores.  Single-buffered variants (NB = 1) load a stage only
+// after every wave is done with the previous one; they take half the LDS, so
+// more blocks share a CU, which is what hides the load latency in layers of
+// one or two stages (at most 128 input channels).  LDS rows hold KB bytes in
+// 16-byte chunks, chunk c of row r at c ^ s(r) (s = bits 2..3 of r for 64-byte
+// rows, bit 3 for 32-byte rows).
 //
 // A decoder conv whose output only feeds the next transposed conv runs that
 // transposed conv on its FP8 output tile in the epilogue (EPI_UP) and stores
@@ -67,35 +71,36 @@ __device__ __forceinline__ i32x8 join(u32x4 lo, u32x4 hi)
 
 // Fragment buffers: two (the next MFMA step's fragments are read while the
 // current one computes), or one in 16-wave blocks, whose four waves per SIMD
-// leave 128 registers a lane and cover the read latency themselves.
-constexpr int frag_bufs(int waves) { return waves >= 16 ? 1 : 2; }
+// leave 128 registers a lane and cover the read latency themselves, and in
+// the single-buffered variants, which aim at more waves per SIMD.
+constexpr int frag_bufs(int waves, int nb) { return waves >= 16 || nb == 1 ? 1 : 2; }
 
 // Occupancy target handed to the register allocator: as many waves per SIMD
 // as both the block's LDS (160 KB per CU) and an estimate of its registers
 // (accumulators, fragments, addressing; 512 per lane and SIMD) allow, at
 // most 4, and at least what one block puts on each SIMD.
-constexpr int occupancy_target(int lds_bytes, int waves_per_block, int tmw, int tnw)
+constexpr int occupancy_target(int lds_bytes, int waves_per_block, int tmw, int tnw, int nb)
 {
     const int blocks = lds_bytes > 0 ? 163840 / lds_bytes : 8;
     int w = blocks * waves_per_block / 4;
-    const int regs = tmw * tnw * 16 + frag_bufs(waves_per_block) * (tmw + tnw) * 8 + 48;
+    const int regs = tmw * tnw * 16 + frag_bufs(waves_per_block, nb) * (tmw + tnw) * 8 + 48;
     w = w < 512 / regs ? w : 512 / regs;
     w = w < 1 ? 1 : (w > 4 ? 4 : w);
     const int need = (waves_per_block + 3) / 4;
     return w < need ? need : w;
 }
 
-template <int BM, int BN, int KB, int TAPS, int EPI>
+template <int BM, int BN, int KB, int TAPS, int EPI, int NB>
 struct F8Lds {
     static constexpr int RPL = 1024 / KB;
     static constexpr int XR = (BM + TAPS - 1 + RPL - 1) / RPL * RPL;
     static constexpr int STAGE = (XR + BN * TAPS) * KB;
-    static constexpr int v = Max<2 * STAGE, (EPI == EPI_HEAD ? 0 : BM * (BN + 16))>::v;
+    static constexpr int v = Max<NB * STAGE, (EPI == EPI_HEAD ? 0 : BM * (BN + 16))>::v;
 };
 
-template <int WM, int WN, int TMW, int TNW, int KB, int TAPS, int EPI>
+template <int WM, int WN, int TMW, int TNW, int KB, int TAPS, int EPI, int NB>
 __global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(occupancy_target(
-    F8Lds<WM * TMW * 32, WN * TNW * 32, KB, TAPS, EPI>::v, WM * WN, TMW, TNW))))
+    F8Lds<WM * TMW * 32, WN * TNW * 32, KB, TAPS, EPI, NB>::v, WM * WN, TMW, TNW, NB))))
 void conv_mfma_fp8x64(ConvArgs a)
 {
     constexpr int NW = WM * WN;
@@ -108,7 +113,7 @@ void conv_mfma_fp8x64(ConvArgs a)
     constexpr int RPL = 1024 / KB;               // LDS rows per wave-wide 1 KB load
     constexpr int CPR = KB / 16;                 // 16-byte chunks per row
     constexpr int RAD = (TAPS - 1) / 2;
-    using L = F8Lds<BM, BN, KB, TAPS, EPI>;
+    using L = F8Lds<BM, BN, KB, TAPS, EPI, NB>;
     constexpr int XR = L::XR;
     constexpr int WRW = BN * TAPS;
     static_assert(WRW % RPL == 0, "weight rows fill whole 1 KB loads");
@@ -188,13 +193,14 @@ void conv_mfma_fp8x64(ConvArgs a)
     issue(0, 0);
     for (int k = 0; k < nk; ++k) {
         // this wave's loads of stage k have landed; the barrier makes every
-        // wave's visible and frees the other buffer (last read in stage k - 1)
+        // wave's visible and (NB = 2) frees the other buffer (last read in
+        // stage k - 1)
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
-        if (k + 1 < nk) issue((k + 1) & 1, (k + 1) * KB);
-        const uint8_t* xs = smem + (k & 1) * STAGE;
+        if (NB == 2 && k + 1 < nk) issue((k + 1) & 1, (k + 1) * KB);
+        const uint8_t* xs = smem + (NB == 2 ? (k & 1) : 0) * STAGE;
         const uint8_t* ws = xs + XR * KB;
-        constexpr int FB = frag_bufs(NW);
+        constexpr int FB = frag_bufs(NW, NB);
         i32x8 av[FB][TMW], bv[FB][TNW];
         // fragments of MFMA step p: this lane's slice 2 p + h (clamped; the
         // half past the last slice is zero)
@@ -233,6 +239,10 @@ void conv_mfma_fp8x64(ConvArgs a)
                 for (int j = 0; j < TNW; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(bv[f][j], av[f][i], acc[i][j], 0, 0,
                                                                                 0, 0, 0, 0);
+        }
+        if (NB == 1 && k + 1 < nk) {
+            __syncthreads();   // every wave is past its reads of the buffer
+            issue(0, (k + 1) * KB);
         }
     }
     __syncthreads();   // the epilogue reuses the stage buffers
@@ -410,7 +420,7 @@ void conv_mfma_fp8x64(ConvArgs a)
     }
 }
 
-template <int WM, int WN, int TMW, int TNW, int KB, int TAPS, int EPI>
+template <int WM, int WN, int TMW, int TNW, int KB, int NB, int TAPS, int EPI>
 hipError_t run(const ConvArgs& a, hipStream_t s)
 {
     constexpr int BM = WM * TMW * 32;
@@ -418,36 +428,42 @@ hipError_t run(const ConvArgs& a, hipStream_t s)
     const unsigned m_tiles = (unsigned)((a.m_rows + BM - 1) / BM);
     const unsigned n_tiles = (unsigned)((a.n + BN - 1) / BN);
     dim3 grid((m_tiles + kXcds - 1) / kXcds * kXcds * n_tiles);
-    hipLaunchKernelGGL((conv_mfma_fp8x64<WM, WN, TMW, TNW, KB, TAPS, EPI>), grid, dim3(WM * WN * 64), 0, s, a);
+    hipLaunchKernelGGL((conv_mfma_fp8x64<WM, WN, TMW, TNW, KB, TAPS, EPI, NB>), grid, dim3(WM * WN * 64), 0, s, a);
     return hipGetLastError();
 }
 
 // Tile variants: waves (WM x WN), 32 x 32 blocks per wave (TMW x TNW), stage
 // width KB (fixed by the layer's input channels, so a layer's variants all
-// give the same bits).
-struct Variant { int wm, wn, tmw, tnw, kb; };
+// give the same bits), LDS stage buffers NB.
+struct Variant { int wm, wn, tmw, tnw, kb, nb; };
 constexpr Variant kVariants[] = {
-    {4, 1, 2, 1, 64},   //  0: 256 x 32
-    {4, 1, 2, 2, 64},   //  1: 256 x 64
-    {2, 2, 2, 2, 64},   //  2: 128 x 128
-    {4, 2, 2, 2, 64},   //  3: 256 x 128 (512 threads)
-    {8, 1, 2, 2, 64},   //  4: 512 x 64 (512 threads)
-    {2, 2, 2, 1, 64},   //  5: 128 x 64, 64 x 32 per wave
-    {2, 1, 2, 2, 64},   //  6: 128 x 64 (128 threads)
-    {2, 2, 4, 2, 64},   //  7: 256 x 128, 128 x 64 per wave
-    {4, 1, 4, 2, 64},   //  8: 512 x 64, 128 x 64 per wave
-    {4, 1, 2, 1, 32},   //  9: 256 x 32, 32-channel stages
-    {4, 1, 2, 2, 32},   // 10: 256 x 64, 32-channel stages
-    {8, 1, 2, 1, 32},   // 11: 512 x 32, 32-channel stages
-    {8, 1, 2, 2, 32},   // 12: 512 x 64, 32-channel stages
-    {2, 1, 2, 1, 32},   // 13: 128 x 32, 32-channel stages (128 threads)
+    {4, 1, 2, 1, 64, 2},   //  0: 256 x 32
+    {4, 1, 2, 2, 64, 2},   //  1: 256 x 64
+    {2, 2, 2, 2, 64, 2},   //  2: 128 x 128
+    {4, 2, 2, 2, 64, 2},   //  3: 256 x 128 (512 threads)
+    {8, 1, 2, 2, 64, 2},   //  4: 512 x 64 (512 threads)
+    {2, 2, 2, 1, 64, 2},   //  5: 128 x 64, 64 x 32 per wave
+    {2, 1, 2, 2, 64, 2},   //  6: 128 x 64 (128 threads)
+    {2, 2, 4, 2, 64, 2},   //  7: 256 x 128, 128 x 64 per wave
+    {4, 1, 4, 2, 64, 2},   //  8: 512 x 64, 128 x 64 per wave
+    {4, 1, 2, 1, 32, 2},   //  9: 256 x 32, 32-channel stages
+    {4, 1, 2, 2, 32, 2},   // 10: 256 x 64, 32-channel stages
+    {8, 1, 2, 1, 32, 2},   // 11: 512 x 32, 32-channel stages
+    {8, 1, 2, 2, 32, 2},   // 12: 512 x 64, 32-channel stages
+    {2, 1, 2, 1, 32, 2},   // 13: 128 x 32, 32-channel stages (128 threads)
+    {4, 1, 2, 2, 64, 1},   // 14: 256 x 64, single-buffered
+    {4, 1, 2, 1, 64, 1},   // 15: 256 x 32, single-buffered
+    {2, 2, 2, 2, 64, 1},   // 16: 128 x 128, single-buffered
+    {4, 1, 2, 2, 32, 1},   // 17: 256 x 64, 32-channel stages, single-buffered
+    {4, 1, 2, 1, 32, 1},   // 18: 256 x 32, 32-channel stages, single-buffered
+    {2, 1, 2, 2, 64, 1},   // 19: 128 x 64, single-buffered (128 threads)
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 #define PVF_FP8_CASE(V)                                                                                          \
     case V:                                                                                                      \
-        return run<kVariants[V].wm, kVariants[V].wn, kVariants[V].tmw, kVariants[V].tnw, kVariants[V].kb, TAPS, \
-                   EPI>(a, s);
+        return run<kVariants[V].wm, kVariants[V].wn, kVariants[V].tmw, kVariants[V].tnw, kVariants[V].kb,      \
+                   kVariants[V].nb, TAPS, EPI>(a, s);
 
 template <int TAPS, int EPI>
 hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
@@ -461,6 +477,9 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_FP8_CASE(6)
             PVF_FP8_CASE(7)
             PVF_FP8_CASE(8)
+            PVF_FP8_CASE(14)
+            PVF_FP8_CASE(16)
+            PVF_FP8_CASE(19)
         default: return hipErrorInvalidValue;
         }
     } else if constexpr (EPI == EPI_HEAD) {
@@ -475,6 +494,11 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_FP8_CASE(11)
             PVF_FP8_CASE(12)
             PVF_FP8_CASE(13)
+            PVF_FP8_CASE(14)
+            PVF_FP8_CASE(15)
+            PVF_FP8_CASE(17)
+            PVF_FP8_CASE(18)
+            PVF_FP8_CASE(19)
         default: return hipErrorInvalidValue;
         }
     } else if constexpr (TAPS == 1) {
@@ -488,6 +512,10 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_FP8_CASE(6)
             PVF_FP8_CASE(7)
             PVF_FP8_CASE(8)
+            PVF_FP8_CASE(14)
+            PVF_FP8_CASE(15)
+            PVF_FP8_CASE(16)
+            PVF_FP8_CASE(19)
         default: return hipErrorInvalidValue;
         }
     } else {
@@ -506,6 +534,12 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_FP8_CASE(11)
             PVF_FP8_CASE(12)
             PVF_FP8_CASE(13)
+            PVF_FP8_CASE(14)
+            PVF_FP8_CASE(15)
+            PVF_FP8_CASE(16)
+            PVF_FP8_CASE(17)
+            PVF_FP8_CASE(18)
+            PVF_FP8_CASE(19)
         default: return hipErrorInvalidValue;
         }
     }
@@ -526,29 +560,30 @@ bool fp8_variant_ok(int v, int n, int cin, int taps, Epi epi)
     if (epi == EPI_HEAD)
         return x.wn == 1 && bn == n && (v == 0 || v == 1 || v == 4 || v == 6 || v == 8 || v >= 9);
     if (epi == EPI_UP)   // the tile must hold every channel of its rows
-        return (v == 1 || v == 2 || v == 3 || v == 4 || v == 6 || v == 7 || v == 8) && bn == n && taps == 5;
+        return (v == 1 || v == 2 || v == 3 || v == 4 || v == 6 || v == 7 || v == 8 || v == 14 || v == 16 ||
+                v == 19) &&
+               bn == n && taps == 5;
     return bn <= n;
 }
 
-// Picks of the autotuner over 1000 events: 256 x 64 tiles (two blocks per
-// CU, 64 x 64 per wave) on the 5-tap layers, 256 x 32 or 128 x 32 where the
-// layer has 32 output channels, 128 x 128 and 256 x 128 on the wide
-// transposed convolutions.
+// Picks of the autotuner over 1000 events: the single-buffered tiles (more
+// blocks per CU) on the 5-tap layers but the 32-channel head, 256 x 64 (64 x 64 per wave) where the
+// layer has 64 or more output channels, 256 x 32 or 128 x 32 where it has 32,
+// 128 x 128 and 256 x 128 on the wide transposed convolutions; a decoder conv
+// that runs the following transposed conv in its epilogue needs a tile of all
+// its output channels: 256 x 64 for 64, 128 x 128 for 128.
 int fp8_default_variant(int n, int cin, int taps, Epi epi)
 {
     const bool k64 = cin % 64 == 0;
-    if (epi == EPI_HEAD) return n == 64 ? (k64 ? 1 : 10) : (k64 ? 0 : 13);
+    if (epi == EPI_HEAD) return n == 64 ? (k64 ? 14 : 10) : (k64 ? 0 : 13);
     if (taps == 1) return n >= 256 ? 2 : (n >= 128 ? 3 : 0);
-    if (n <= 32) return k64 ? 0 : 9;
-    return k64 ? 1 : 10;
+    if (n <= 32) return k64 ? 15 : 9;
+    return k64 ? 14 : 17;
 }
 
-// A decoder conv that runs the following transposed conv in its epilogue
-// needs a tile of all its output channels: 256 x 64 for 64, 256 x 128 for
-// 128; -1 where no variant fits.
 int fp8_default_up_variant(int n, int cin)
 {
-    const int v = n == 64 ? 1 : (n == 128 ? 3 : -1);
+    const int v = n == 64 ? 14 : (n == 128 ? 16 : -1);
     return v >= 0 && fp8_variant_ok(v, n, cin, kTaps, EPI_UP) ? v : -1;
 }
 
@@ -558,7 +593,7 @@ std::string fp8_kernel_name(int v, int cin, int taps, Epi epi)
     const Variant& x = kVariants[v];
     return "conv_mfma_fp8x64<" + std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " + std::to_string(x.tmw) +
            ", " + std::to_string(x.tnw) + ", " + std::to_string(x.kb) + ", " + std::to_string(taps) + ", " +
-           std::to_string((int)epi) + ">";
+           std::to_string((int)epi) + ", " + std::to_string(x.nb) + ">";
 }
 
 hipError_t launch_conv_fp8(const ConvArgs& a, int taps, Epi epi, int v, hipStream_t s)

@@ -454,9 +454,12 @@ void conv_mfma_lp_first(ConvArgs a)
 // the batch (first and last tile) and columns beyond n (last N tile) are
 // clamped to valid addresses: they only feed outputs the epilogue discards.
 // Same k order as every other variant (32-channel stage, tap, MFMA).
-template <class T, int WM, int WN, int TMW, int TNW, int TAPS, int EPI>
+// NB = 1: one stage buffer, loaded (still straight into LDS) only after every
+// wave is done with the previous stage; half the LDS, so more blocks share a
+// CU and cover each other's load latency, and one fragment buffer per wave.
+template <class T, int WM, int WN, int TMW, int TNW, int TAPS, int EPI, int NB>
 __global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(occupancy_target(
-    LpLds<(int)sizeof(T), WM * TMW * 16, WN * TNW * 16, 32, TAPS, EPI, 2, 16>::v, WM * WN))))
+    LpLds<(int)sizeof(T), WM * TMW * 16, WN * TNW * 16, 32, TAPS, EPI, NB, 16>::v, WM * WN))))
 void conv_mfma_lp_db(ConvArgs a)
 {
     using V = typename Lp<T>::vec8;
@@ -473,7 +476,7 @@ void conv_mfma_lp_db(ConvArgs a)
     constexpr int XI = XR / 16, WI = WRW / 16;      // wave-wide loads per stage
     constexpr int STAGE = (XR + WRW) * ROWB;         // bytes
     constexpr int OP = BN + 8;
-    constexpr int SMEM = Max<2 * STAGE, (EPI == EPI_HEAD ? 0 : BM * OP * (int)sizeof(T))>::v;
+    constexpr int SMEM = Max<NB * STAGE, (EPI == EPI_HEAD ? 0 : BM * OP * (int)sizeof(T))>::v;
     __shared__ __attribute__((aligned(16))) char smem[SMEM];
 
     const T* in = static_cast<const T*>(a.in);
@@ -546,13 +549,13 @@ void conv_mfma_lp_db(ConvArgs a)
         // wave's visible and frees the other buffer (its last reads were stage k - 1)
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
-        if (k + 1 < nk) issue((k + 1) & 1, (k + 1) * KC);
-        const T* xs = reinterpret_cast<const T*>(smem + (k & 1) * STAGE);
+        if (NB == 2 && k + 1 < nk) issue((k + 1) & 1, (k + 1) * KC);
+        const T* xs = reinterpret_cast<const T*>(smem + (NB == 2 ? (k & 1) : 0) * STAGE);
         const T* ws = xs + XR * KC;
         // fragments of tap t + 1 are read while tap t is on the matrix cores
         // (blocks of 16 waves have no registers to spare for that: there the
         // other three waves of the SIMD cover the read latency)
-        constexpr int FB = NW < 16 ? 2 : 1;
+        constexpr int FB = NW < 16 && NB == 2 ? 2 : 1;
         V av[FB][TMW], bv[FB][TNW];
         auto frag = [&](int tap, int f) {
 #pragma unroll
@@ -575,6 +578,10 @@ void conv_mfma_lp_db(ConvArgs a)
             for (int i = 0; i < TMW; ++i)
 #pragma unroll
                 for (int j = 0; j < TNW; ++j) acc[i][j] = Lp<T>::mfma(bv[f][j], av[f][i], acc[i][j]);
+        }
+        if (NB == 1 && k + 1 < nk) {
+            __syncthreads();   // every wave is past its reads of the buffer
+            issue(0, (k + 1) * KC);
         }
     }
     __syncthreads();   // the epilogue reuses the stage buffers
@@ -777,8 +784,9 @@ hipError_t run(const ConvArgs& a, hipStream_t s)
     const unsigned m_tiles = (unsigned)((a.m_rows + BM - 1) / BM);
     const unsigned n_tiles = (unsigned)((a.n + BN - 1) / BN);
     dim3 grid((m_tiles + kXcds - 1) / kXcds * kXcds * n_tiles);
-    if constexpr (PF == 2)
-        hipLaunchKernelGGL((conv_mfma_lp_db<T, WM, WN, TMW, TNW, TAPS, EPI>), grid, dim3(WM * WN * 64), 0, s, a);
+    if constexpr (PF == 2 || PF == 4)
+        hipLaunchKernelGGL((conv_mfma_lp_db<T, WM, WN, TMW, TNW, TAPS, EPI, PF == 2 ? 2 : 1>), grid,
+                           dim3(WM * WN * 64), 0, s, a);
     else
         hipLaunchKernelGGL((conv_mfma_lp<T, WM, WN, TMW, TNW, KC, PF, TAPS, EPI>), grid, dim3(WM * WN * 64), 0, s, a);
     return hipGetLastError();
@@ -825,6 +833,11 @@ constexpr Variant kVariants[] = {
     {8, 1, 4, 4, 32, 2},   // 23: 512 x 64, double-buffered
     {4, 1, 4, 2, 32, 3},   // 24: head launch with dec0.c1 fused (conv_mfma_lp_dec0, 4 waves, 240 rows)
     {8, 1, 4, 2, 32, 3},   // 25: the same with 8 waves (496 rows)
+    {4, 2, 4, 4, 32, 4},   // 26: 256 x 128, single-buffered direct-to-LDS stages
+    {8, 1, 4, 4, 32, 4},   // 27: 512 x 64, single-buffered direct-to-LDS
+    {4, 1, 4, 4, 32, 4},   // 28: 256 x 64, single-buffered direct-to-LDS
+    {4, 1, 4, 2, 32, 4},   // 29: 256 x 32, single-buffered direct-to-LDS
+    {2, 2, 4, 4, 32, 4},   // 30: 128 x 128, single-buffered direct-to-LDS
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -849,6 +862,10 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_LP_CASE(19)
             PVF_LP_CASE(22)
             PVF_LP_CASE(23)
+            PVF_LP_CASE(26)
+            PVF_LP_CASE(27)
+            PVF_LP_CASE(28)
+            PVF_LP_CASE(30)
         default: return hipErrorInvalidValue;
         }
     } else if constexpr (EPI == EPI_HEAD) {
@@ -865,6 +882,9 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_LP_CASE(21)
             PVF_LP_CASE(22)
             PVF_LP_CASE(23)
+            PVF_LP_CASE(27)
+            PVF_LP_CASE(28)
+            PVF_LP_CASE(29)
         default: return hipErrorInvalidValue;
         }
     } else {
@@ -893,6 +913,11 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_LP_CASE(21)
             PVF_LP_CASE(22)
             PVF_LP_CASE(23)
+            PVF_LP_CASE(26)
+            PVF_LP_CASE(27)
+            PVF_LP_CASE(28)
+            PVF_LP_CASE(29)
+            PVF_LP_CASE(30)
         default: return hipErrorInvalidValue;
         }
     }
@@ -930,36 +955,34 @@ bool lp_variant_ok(int v, int n, int cin, int taps, Epi epi)
                bn == n && x.wn == 1;
     if (epi == EPI_UP)   // the tile must hold every channel of its rows
         return (v == 1 || v == 2 || v == 3 || v == 4 || v == 9 || v == 12 || v == 13 || v == 15 || v == 19 ||
-                v == 22 || v == 23) && bn == n;
+                v == 22 || v == 23 || v == 26 || v == 27 || v == 28 || v == 30) && bn == n;
     return bn <= (n < 32 ? 32 : n);
 }
 
-// Defaults from the autotuner's BF16 picks on MI355X at 1000 events (widths
-// 32 and 64, event and interval layouts).  The small-channel layers take the
-// 512-row, 128-row or 64-channel-stage tiles, the wide ones the 256 x 128
-// single-buffered tile (two blocks per CU), the 512 x 64 tile at 128 input
-// channels or, from 256 input channels, the double-buffered 512 x 128 tile,
-// and the 1x1 transposed convs the double-buffered 128 x 128 tile.
+// Defaults from the autotuner's BF16 picks on MI355X at 1000 events.  The
+// small-channel layers take the 512-row, 128-row or 64-channel-stage tiles;
+// from 64 output channels and 64 input channels on, the single-buffered
+// direct-to-LDS 256 x 64 tile (four blocks per CU; also the 64-channel head),
+// except the 128-channel layer over 64 input channels (256 x 128, single
+// stage, register-staged); the 1x1 transposed convs the double-buffered
+// 128 x 128 tile.
 int lp_default_variant(int n, int cin, int taps, Epi epi)
 {
-    if (epi == EPI_HEAD) return n == 64 ? 1 : 20;
+    if (epi == EPI_HEAD) return n == 64 ? 28 : 20;
     if (epi == EPI_CONVT && taps == 1) return n >= 512 ? 17 : (n >= 128 ? 15 : (cin % 64 == 0 ? 8 : 4));
     if (n <= 32) return epi == EPI_POOL ? 5 : (cin % 64 == 0 ? 8 : 14);
-    if (n <= 64) {
-        if (epi == EPI_POOL) return 4;
-        if (cin <= 32) return 22;
-        return cin >= 128 ? 13 : (cin % 64 == 0 ? 8 : 13);
-    }
-    return cin >= 256 ? 19 : (cin == 128 ? 22 : 3);
+    if (cin <= 32) return 22;
+    if (n > 64 && cin < 128) return 3;
+    return 28;
 }
 
 // Decoder convs that run the following transposed conv in their epilogue
 // need a tile of all their output channels; the autotuner's BF16 picks at
-// 1000 events: 512 x 64 for 64 channels, 256 x 128 for 128; -1 where no
-// such variant fits.
+// 1000 events: 512 x 64 for 64 channels, the single-buffered direct-to-LDS
+// 256 x 128 for 128; -1 where no such variant fits.
 int lp_default_up_variant(int n, int cin)
 {
-    const int v = n == 64 ? 22 : (n == 128 ? 3 : -1);
+    const int v = n == 64 ? 22 : (n == 128 ? 26 : -1);
     return v >= 0 && lp_variant_ok(v, n, cin, kTaps, EPI_UP) ? v : -1;
 }
 
@@ -992,10 +1015,11 @@ std::string lp_kernel_name(int dtype, int v, int taps, Epi epi)
     if (x.pf == 3)
         return std::string("conv_mfma_lp_dec0<") + (dtype == PVF_BF16 ? "__bf16" : "_Float16") + ", " +
                std::to_string(x.wm) + ">";
-    if (x.pf == 2)
+    if (x.pf == 2 || x.pf == 4)
         return std::string("conv_mfma_lp_db<") + (dtype == PVF_BF16 ? "__bf16" : "_Float16") + ", " +
                std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " + std::to_string(x.tmw) + ", " +
-               std::to_string(x.tnw) + ", " + std::to_string(taps) + ", " + std::to_string((int)epi) + ">";
+               std::to_string(x.tnw) + ", " + std::to_string(taps) + ", " + std::to_string((int)epi) + ", " +
+               (x.pf == 2 ? "2" : "1") + ">";
     return std::string("conv_mfma_lp<") + (dtype == PVF_BF16 ? "__bf16" : "_Float16") + ", " +
            std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " + std::to_string(x.tmw) + ", " +
            std::to_string(x.tnw) + ", " + std::to_string(x.kc) + ", " + std::to_string(x.pf) + ", " +
