@@ -58,7 +58,7 @@ int conv_default_up_variant(int dtype, int n, int cin)
 
 int conv_default_dec0_variant(int dtype)
 {
-    return dtype == PVF_BF16 || dtype == PVF_FP16 ? 25 : -1;   // the autotuner's pick at 1000 events
+    return dtype == PVF_BF16 || dtype == PVF_FP16 ? 32 : -1;   // the autotuner's pick at 1000 events
 }
 
 std::string conv_kernel_name(int dtype, int variant, int cin, int taps, Epi epi)

@@ -776,6 +776,190 @@ void conv_mfma_lp_dec0(ConvArgs c1, ConvArgs c2)
     }
 }
 
+// The same fused level 0 with its stages loaded straight into LDS
+// (global_load_lds_dwordx4, as the direct-to-LDS conv tiles load theirs) and
+// one buffer: no staging registers, and dec0.c1's output tile takes the place
+// of phase 1's halo tile (both are swizzled 32-channel tiles of the same
+// rows), so a block needs 27 KB (4 waves) or 46 KB (8 waves) of LDS and more
+// blocks share a CU.  Same fragments, k order and epilogues as
+// conv_mfma_lp_dec0, hence the same bits.
+template <class T, int WM>
+__global__ __launch_bounds__(WM * 64) __attribute__((amdgpu_waves_per_eu(4)))
+void conv_mfma_lp_dec0d(ConvArgs c1, ConvArgs c2)
+{
+    using V = typename Lp<T>::vec8;
+    constexpr int NW = WM;
+    constexpr int BA = WM * 64;                  // phase-1 rows per block
+    constexpr int BO = BA - 16;                  // output rows per block
+    constexpr int KC = 32, NCH = 4;              // 32-channel stages, 64-byte rows
+    constexpr int ROWB = KC * (int)sizeof(T);
+    constexpr int XRA = (BA + kTaps - 1 + 15) / 16 * 16;   // halo rows, whole 1 KB loads
+    constexpr int WR = kTaps * 32;               // weight rows (tap-major) of either conv
+    constexpr int XI = XRA / 16, WI = WR / 16;   // wave-wide loads of the halo and of a weight tile
+    __shared__ __attribute__((aligned(16))) char smem[(XRA + WR) * ROWB];
+    T* const xs = reinterpret_cast<T*>(smem);    // phase 1: halo tile; phase 2: dec0.c1's output tile
+    T* const ws = xs + XRA * KC;                 // weights of the current conv
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int li = lane & 15, lg = lane >> 4;
+    const int m_tiles = (int)((c2.m_rows + BO - 1) / BO);
+    const int xcd = (int)(blockIdx.x % kXcds), slot = (int)(blockIdx.x / kXcds);
+    const int m_tile = slot * kXcds + xcd;
+    if (m_tile >= m_tiles) return;
+    const int64_t m0 = (int64_t)m_tile * BO;
+    const int64_t a0 = m0 - 2;                   // first phase-1 row
+
+    // Wave-wide load j fills LDS rows 16 j .. 16 j + 15 (halo rows, then the
+    // weight rows tap * 32 + column); lane L fills slot L % 4 of row L / 4 with
+    // the chunk the swizzle puts there.  Sources: 32-bit byte offsets from the
+    // halo's first row and from the weights; halo rows outside the batch are
+    // clamped (they only feed zeroed or discarded rows).
+    constexpr int NJ = XI + WI, JT = (NJ + NW - 1) / NW;
+    const int lrow = lane >> 2, lpos = lane & 3;
+    const char* xbase = reinterpret_cast<const char*>(static_cast<const T*>(c1.in) + (a0 - 2) * c1.ld_in);
+    const char* w1 = static_cast<const char*>(c1.w);
+    const char* w2 = static_cast<const char*>(c2.w);
+    unsigned off[JT];
+#pragma unroll
+    for (int t = 0; t < JT; ++t) {
+        const int j = min(wave + t * NW, NJ - 1);
+        const bool xj = j < XI;
+        const int row = 16 * (xj ? j : j - XI) + lrow;
+        const int c = lpos ^ swz<NCH>(row);
+        if (xj) {
+            int64_t g = a0 - 2 + row;
+            g = g < 0 ? 0 : (g >= c1.m_rows ? c1.m_rows - 1 : g);
+            off[t] = (unsigned)(((g - (a0 - 2)) * c1.ld_in + 8 * c) * (int64_t)sizeof(T));
+        } else {
+            const int tap = row / 32, n = row % 32;
+            off[t] = (unsigned)((n * (kTaps * c1.cin) + tap * c1.cin + 8 * c) * (int)sizeof(T));
+        }
+    }
+    auto issue1 = [&](int c0) __attribute__((always_inline)) {
+        const unsigned cb = (unsigned)(c0 * (int)sizeof(T));
+#pragma unroll
+        for (int t = 0; t < JT; ++t) {
+            const int j = wave + t * NW;
+            if ((t + 1) * NW <= NJ || j < NJ)
+                __builtin_amdgcn_global_load_lds((const void*)((j < XI ? xbase : w1) + (off[t] + cb)),
+                                                 (__attribute__((address_space(3))) void*)(smem + 16 * j * ROWB), 16,
+                                                 0, 0);
+        }
+    };
+    // dec0.c2's weights (32 input channels: one stage) into the weight rows
+    auto issue2 = [&]() __attribute__((always_inline)) {
+        constexpr int J2 = (WI + NW - 1) / NW;
+#pragma unroll
+        for (int t = 0; t < J2; ++t) {
+            const int j = wave + t * NW;
+            if ((t + 1) * NW <= WI || j < WI) {
+                const int row = 16 * j + lrow, tap = row / 32, n = row % 32;
+                const int c = lpos ^ swz<NCH>(row);
+                __builtin_amdgcn_global_load_lds(
+                    (const void*)(w2 + (n * (kTaps * c2.cin) + tap * c2.cin + 8 * c) * (int)sizeof(T)),
+                    (__attribute__((address_space(3))) void*)(smem + (XI + j) * 16 * ROWB), 16, 0, 0);
+            }
+        }
+    };
+
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // ---- phase 1: dec0.c1 over rows a0 .. a0 + BA - 1
+    issue1(0);
+    for (int c0 = 0; c0 < c1.cin; c0 += KC) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+#pragma unroll
+        for (int tap = 0; tap < kTaps; ++tap) {
+            V av[4], bv[2];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = *reinterpret_cast<const V*>(xs + lds_at<NCH>(wave * 64 + i * 16 + li + tap, lg));
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                bv[j] = *reinterpret_cast<const V*>(ws + lds_at<NCH>(tap * 32 + j * 16 + li, lg));
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = Lp<T>::mfma(bv[j], av[i], acc[i][j]);
+        }
+        __syncthreads();   // every wave is past its reads of the stage
+        if (c0 + KC < c1.cin) issue1(c0 + KC);
+    }
+    issue2();
+    // dec0.c1's epilogue into the tile (the halo's place): row r is row a0 + r
+    {
+        const RowMap rmap(a0 < 0 ? 0 : a0, c1.r_in);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = wave * 64 + i * 16 + li;
+            const int64_t g = a0 + r;
+            bool keep = g >= 0 && g < c1.m_rows;
+            if (keep) {
+                int64_t e;
+                int loc;
+                rmap.at((int)(g - (a0 < 0 ? 0 : a0)), e, loc);
+                keep = loc >= kGuard && loc < c1.r_in - kGuard;
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int col = j * 16 + 4 * lg;
+                T y[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) y[v] = keep ? (T)lrelu(acc[i][j][v] + c1.bias[col + v], c1.slope) : (T)0.f;
+                *reinterpret_cast<uint2*>(xs + lds_at<NCH>(r, col / 8) + (col % 8)) = *reinterpret_cast<const uint2*>(y);
+            }
+        }
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    // ---- phase 2: dec0.c2 on the tile (rows BA .. BA + 3 of it are stale
+    // halo rows: they only feed outputs t >= BO, which are not stored)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < kTaps; ++tap) {
+        V av[4], bv[2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[i] = *reinterpret_cast<const V*>(xs + lds_at<NCH>(wave * 64 + i * 16 + li + tap, lg));
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bv[j] = *reinterpret_cast<const V*>(ws + lds_at<NCH>(tap * 32 + j * 16 + li, lg));
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = Lp<T>::mfma(bv[j], av[i], acc[i][j]);
+    }
+    // head epilogue: output rows t < BO of the block
+    const RowMap rows(m0, c2.r_in);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float sum = 0.f;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int c = j * 16 + 4 * lg;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sum += lrelu(acc[i][j][v] + c2.bias[c + v], c2.slope) * c2.head_w[c + v];
+        }
+        sum += __shfl_xor(sum, 16);
+        sum += __shfl_xor(sum, 32);
+        const int t = wave * 64 + i * 16 + li;
+        if (lg == 0 && t < BO && m0 + t < c2.m_rows) {
+            int64_t e;
+            int loc;
+            rows.at(t, e, loc);
+            if (loc >= kGuard && loc < c2.r_in - kGuard)
+                c2.prob[e * c2.l_out + (loc - kGuard)] = 1.f / (1.f + expf(-(sum + c2.head_b)));
+        }
+    }
+}
+
 template <class T, int WM, int WN, int TMW, int TNW, int KC, int PF, int TAPS, int EPI>
 hipError_t run(const ConvArgs& a, hipStream_t s)
 {
@@ -838,6 +1022,8 @@ constexpr Variant kVariants[] = {
     {4, 1, 4, 4, 32, 4},   // 28: 256 x 64, single-buffered direct-to-LDS
     {4, 1, 4, 2, 32, 4},   // 29: 256 x 32, single-buffered direct-to-LDS
     {2, 2, 4, 4, 32, 4},   // 30: 128 x 128, single-buffered direct-to-LDS
+    {4, 1, 4, 2, 32, 5},   // 31: head launch with dec0.c1 fused, stages straight into LDS (4 waves, 240 rows)
+    {8, 1, 4, 2, 32, 5},   // 32: the same with 8 waves (496 rows)
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -947,7 +1133,7 @@ bool lp_variant_ok(int v, int n, int cin, int taps, Epi epi)
 {
     if (v < 0 || v >= kNumVariants) return false;
     const Variant& x = kVariants[v];
-    if (x.pf == 3) return epi == EPI_HEAD && n == 32 && cin == 32 && taps == kTaps;   // dec0 fused: 32-channel head
+    if (x.pf == 3 || x.pf == 5) return epi == EPI_HEAD && n == 32 && cin == 32 && taps == kTaps;   // dec0 fused: 32-channel head
     const int bn = x.wn * x.tnw * 16;
     if (cin % x.kc != 0) return false;
     if (epi == EPI_HEAD)
@@ -986,7 +1172,7 @@ int lp_default_up_variant(int n, int cin)
     return v >= 0 && lp_variant_ok(v, n, cin, kTaps, EPI_UP) ? v : -1;
 }
 
-bool lp_dec0_ok(int v) { return v >= 0 && v < kNumVariants && kVariants[v].pf == 3; }
+bool lp_dec0_ok(int v) { return v >= 0 && v < kNumVariants && (kVariants[v].pf == 3 || kVariants[v].pf == 5); }
 
 hipError_t launch_conv_lp_dec0(int dtype, const ConvArgs& c1, const ConvArgs& c2, int v, hipStream_t s)
 {
@@ -994,27 +1180,32 @@ hipError_t launch_conv_lp_dec0(int dtype, const ConvArgs& c1, const ConvArgs& c2
         c1.r_in != c2.r_in || c2.m_rows <= 0 || !c2.prob || !c2.head_w)
         return hipErrorInvalidValue;
     const int wm = kVariants[v].wm;
+    const bool dma = kVariants[v].pf == 5;
     const int bo = wm * 64 - 16;
     const unsigned m_tiles = (unsigned)((c2.m_rows + bo - 1) / bo);
     dim3 grid((m_tiles + kXcds - 1) / kXcds * kXcds);
-    if (dtype == PVF_BF16) {
-        if (wm == 4) hipLaunchKernelGGL((conv_mfma_lp_dec0<__bf16, 4>), grid, dim3(256), 0, s, c1, c2);
-        else hipLaunchKernelGGL((conv_mfma_lp_dec0<__bf16, 8>), grid, dim3(512), 0, s, c1, c2);
-    } else if (dtype == PVF_FP16) {
-        if (wm == 4) hipLaunchKernelGGL((conv_mfma_lp_dec0<_Float16, 4>), grid, dim3(256), 0, s, c1, c2);
-        else hipLaunchKernelGGL((conv_mfma_lp_dec0<_Float16, 8>), grid, dim3(512), 0, s, c1, c2);
-    } else {
-        return hipErrorInvalidValue;
-    }
+    auto go = [&](auto tag) {
+        using T = decltype(tag);
+        if (dma) {
+            if (wm == 4) hipLaunchKernelGGL((conv_mfma_lp_dec0d<T, 4>), grid, dim3(256), 0, s, c1, c2);
+            else hipLaunchKernelGGL((conv_mfma_lp_dec0d<T, 8>), grid, dim3(512), 0, s, c1, c2);
+        } else {
+            if (wm == 4) hipLaunchKernelGGL((conv_mfma_lp_dec0<T, 4>), grid, dim3(256), 0, s, c1, c2);
+            else hipLaunchKernelGGL((conv_mfma_lp_dec0<T, 8>), grid, dim3(512), 0, s, c1, c2);
+        }
+    };
+    if (dtype == PVF_BF16) go(__bf16{});
+    else if (dtype == PVF_FP16) go(_Float16{});
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
 std::string lp_kernel_name(int dtype, int v, int taps, Epi epi)
 {
     const Variant& x = kVariants[v];
-    if (x.pf == 3)
-        return std::string("conv_mfma_lp_dec0<") + (dtype == PVF_BF16 ? "__bf16" : "_Float16") + ", " +
-               std::to_string(x.wm) + ">";
+    if (x.pf == 3 || x.pf == 5)
+        return std::string(x.pf == 3 ? "conv_mfma_lp_dec0<" : "conv_mfma_lp_dec0d<") +
+               (dtype == PVF_BF16 ? "__bf16" : "_Float16") + ", " + std::to_string(x.wm) + ">";
     if (x.pf == 2 || x.pf == 4)
         return std::string("conv_mfma_lp_db<") + (dtype == PVF_BF16 ? "__bf16" : "_Float16") + ", " +
                std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " + std::to_string(x.tmw) + ", " +

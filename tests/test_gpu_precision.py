@@ -125,26 +125,27 @@ def test_fused_transposed_convs_identical(lp, batch16):
 
 
 def test_fused_level0_identical(lp, batch16):
-    """Head-launch variants 24 and 25 compute dec0.c1 in the same kernel, so
-    its 32-channel output stays in LDS and the dec0.c1 slot enqueues nothing:
-    every output equals the two-launch path bit for bit, and the debug view
-    refuses the unstored dec0.c1 while fused."""
+    """Head-launch variants 24, 25 (register-staged) and 31, 32 (stages
+    straight into LDS, dec0.c1's tile in the halo's place) compute dec0.c1 in
+    the same kernel, so its 32-channel output stays in LDS and the dec0.c1
+    slot enqueues nothing: every output equals the two-launch path bit for
+    bit, and the debug view refuses the unstored dec0.c1 while fused."""
     from paper_2602_19959_amd._binding import PvfError
     dt, eng, out = lp
     names = eng.launch_names()
     h = names.index("dec0.c2+head")
     base = eng.variants()
-    assert base[h] == 25, "the fused 8-wave head is the default"
+    assert base[h] == 32, "the fused 8-wave direct-to-LDS head is the default"
     try:
         assert eng.set_variant(h, 20)   # the two-launch path as the reference
         want = run(eng, batch16)
         assert eng.launch_kernels()[h - 1] != "conv (in dec0.c2+head)"
         for k in ("prob", "z", "integral", "n_vertices", "status", "bin"):
             assert np.array_equal(want[k], out[k]), k
-        for v in (24, 25):
+        for v in (24, 25, 31, 32):
             assert eng.set_variant(h, v)
             k = eng.launch_kernels()
-            assert k[h - 1] == "conv (in dec0.c2+head)" and k[h].startswith("conv_mfma_lp_dec0<"), k[h - 1:h + 1]
+            assert k[h - 1] == "conv (in dec0.c2+head)" and k[h].startswith("conv_mfma_lp_dec0"), k[h - 1:h + 1]
             got = run(eng, batch16)
             for key in ("prob", "z", "integral", "n_vertices", "status", "bin"):
                 assert np.array_equal(got[key], out[key]), (v, key)
