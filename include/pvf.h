@@ -255,12 +255,13 @@ pvf_status pvf_graph_launch(pvf_engine *eng);
  * enc0.c1 (the first convolution), enqueues nothing when enc0.c2's tile
  * variant computes the first convolution in its own staging (FP32, BF16 and
  * FP16 by default); its kernel name then reads "first_conv (in enc0.c2)" and
- * its profiled time is zero.  Likewise, in BF16 and FP16, the transposed-conv
- * slots up0 .. up(n_levels - 3) enqueue nothing when the decoder conv before
- * each (dec1.c2, dec2.c2, ...) has a tile variant holding all its output
- * channels (the default): that conv then runs the transposed conv in its
- * epilogue, and its kernel name reads "transposed conv (in dec1.c2)".  And
- * in BF16 and FP16 with 32 level-0 channels, the dec0.c1 slot enqueues
+ * its profiled time is zero.  Likewise, in BF16, FP16 and FP8, the
+ * transposed-conv slots up0 .. up(n_levels - 3) enqueue nothing when the
+ * decoder conv before each (dec1.c2, dec2.c2, ...) has a tile variant holding
+ * all its output channels (the default): that conv then runs the transposed
+ * conv in its epilogue, and its kernel name reads "transposed conv (in
+ * dec1.c2)".  And
+ * in BF16, FP16 and FP8 with 32 level-0 channels, the dec0.c1 slot enqueues
  * nothing when the head launch ("dec0.c2+head") takes a tile variant that
  * computes dec0.c1 in the same kernel (the default); its name then reads
  * "conv (in dec0.c2+head)". */

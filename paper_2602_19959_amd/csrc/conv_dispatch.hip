@@ -58,7 +58,21 @@ int conv_default_up_variant(int dtype, int n, int cin)
 
 int conv_default_dec0_variant(int dtype)
 {
-    return dtype == PVF_BF16 || dtype == PVF_FP16 ? 32 : -1;   // the autotuner's pick at 1000 events
+    if (dtype == PVF_BF16 || dtype == PVF_FP16) return 32;   // the autotuner's pick at 1000 events
+    return dtype == PVF_FP8_E4M3 ? 20 : -1;
+}
+
+bool conv_dec0_ok(int dtype, int variant)
+{
+    if (dtype == PVF_BF16 || dtype == PVF_FP16) return lp_dec0_ok(variant);
+    return dtype == PVF_FP8_E4M3 && fp8_dec0_ok(variant);
+}
+
+hipError_t launch_conv_dec0(int dtype, const ConvArgs& c1, const ConvArgs& c2, int variant, hipStream_t s)
+{
+    if (dtype == PVF_BF16 || dtype == PVF_FP16) return launch_conv_lp_dec0(dtype, c1, c2, variant, s);
+    if (dtype == PVF_FP8_E4M3) return launch_conv_fp8_dec0(c1, c2, variant, s);
+    return hipErrorInvalidValue;
 }
 
 std::string conv_kernel_name(int dtype, int variant, int cin, int taps, Epi epi)

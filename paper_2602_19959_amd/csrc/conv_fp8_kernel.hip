@@ -420,6 +420,189 @@ void conv_mfma_fp8x64(ConvArgs a)
     }
 }
 
+// dec0.c1 and dec0.c2 + head in one launch (32 level-0 channels): the
+// intermediate tensor stays in LDS as FP8.  A block of WM waves owns
+// BO = 64 WM - 16 output rows from m0:
+//   phase 1 runs dec0.c1 (64 input channels: one 64-channel stage) on the
+//     BA = 64 WM rows from m0 - 2, in its standalone launch's slice order,
+//     with its stored-output epilogue (folded scale and bias, LeakyReLU,
+//     saturation, e4m3); rows that are guard rows or outside the batch are
+//     zero, as in the stored tensor.  The codes go to LDS as a 32-channel
+//     tile (32-byte rows, the 32-channel stage's swizzle) in the halo tile's
+//     place;
+//   phase 2 runs dec0.c2 and the head on that tile as the standalone head
+//     launch runs them on its staged halo (32-channel stage: five slices, the
+//     last MFMA's second half zero; same head epilogue), so every bit of p is
+//     the same as from the two launches.
+// Both stages and both weight tiles go straight into LDS (global_load_lds).
+// c1: dec0.c1's arguments; c2: dec0.c2 + head's (in and ld_in unused).
+template <int WM>
+__global__ __launch_bounds__(WM * 64) __attribute__((amdgpu_waves_per_eu(4)))
+void conv_mfma_fp8x64_dec0(ConvArgs c1, ConvArgs c2)
+{
+    constexpr int NW = WM;
+    constexpr int BA = WM * 64;                   // phase-1 rows per block
+    constexpr int BO = BA - 16;                   // output rows per block
+    constexpr int K1 = 64, K2 = 32;               // row bytes of the two stages
+    constexpr int XRA = (BA + kTaps - 1 + 15) / 16 * 16;   // halo rows, whole 1 KB loads of 64-byte rows
+    constexpr int WR = kTaps * 32;                // weight rows (tap-major) of either conv
+    constexpr int HALO = XRA * K1;
+    __shared__ __attribute__((aligned(16))) uint8_t smem[HALO + WR * K1];
+    uint8_t* const xs = smem;                     // phase 1: halo; phase 2: dec0.c1's tile (32-byte rows)
+    uint8_t* const ws = smem + HALO;              // phase 1: dec0.c1's weights; phase 2: dec0.c2's
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int r32 = lane & 31;
+    const int h = lane >> 5;
+    const int m_tiles = (int)((c2.m_rows + BO - 1) / BO);
+    const int xcd = (int)(blockIdx.x % kXcds), slot = (int)(blockIdx.x / kXcds);
+    const int m_tile = slot * kXcds + xcd;
+    if (m_tile >= m_tiles) return;
+    const int64_t m0 = (int64_t)m_tile * BO;
+    const int64_t a0 = m0 - 2;                    // first phase-1 row
+
+    // phase-1 loads: wave-wide load j fills 16 rows of 64 bytes (halo rows,
+    // then the weight rows tap * 32 + column); lane L fills slot L % 4 of row
+    // L / 4 with the chunk the swizzle puts there
+    constexpr int NJ = XRA / 16 + WR / 16, JT = (NJ + NW - 1) / NW;
+    const uint8_t* xbase = static_cast<const uint8_t*>(c1.in) + (a0 - 2) * c1.ld_in;
+    const uint8_t* w1 = static_cast<const uint8_t*>(c1.w);
+    const uint8_t* w2 = static_cast<const uint8_t*>(c2.w);
+#pragma unroll
+    for (int t = 0; t < JT; ++t) {
+        const int j = wave + t * NW;
+        if (!((t + 1) * NW <= NJ || j < NJ)) continue;
+        const bool xj = j < XRA / 16;
+        const int row = 16 * (xj ? j : j - XRA / 16) + (lane >> 2);
+        const int c = (lane & 3) ^ swz<K1>(row);
+        unsigned off;
+        if (xj) {
+            int64_t g = a0 - 2 + row;
+            g = g < 0 ? 0 : (g >= c1.m_rows ? c1.m_rows - 1 : g);
+            off = (unsigned)((g - (a0 - 2)) * c1.ld_in + 16 * c);
+        } else {
+            const int tap = row / 32, n = row % 32;
+            off = (unsigned)(n * (kTaps * c1.cin) + tap * c1.cin + 16 * c);
+        }
+        __builtin_amdgcn_global_load_lds((const void*)((xj ? xbase : w1) + off),
+                                         (__attribute__((address_space(3))) void*)(smem + 1024 * j), 16, 0, 0);
+    }
+
+    f32x16 acc[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[i][v] = 0.f;
+
+    // ---- phase 1: ten (32-channel chunk, tap) slices, five MFMAs per block
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+        const int sidx = 2 * p + h, sub = sidx / kTaps, tap = sidx - sub * kTaps;
+        const int rw = tap * 32 + r32;
+        const i32x8 bv = join(*reinterpret_cast<const u32x4*>(ws + rw * K1 + 16 * ((2 * sub) ^ swz<K1>(rw))),
+                              *reinterpret_cast<const u32x4*>(ws + rw * K1 + 16 * ((2 * sub + 1) ^ swz<K1>(rw))));
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int r = wave * 64 + i * 32 + r32 + tap;
+            const i32x8 av = join(*reinterpret_cast<const u32x4*>(xs + r * K1 + 16 * ((2 * sub) ^ swz<K1>(r))),
+                                  *reinterpret_cast<const u32x4*>(xs + r * K1 + 16 * ((2 * sub + 1) ^ swz<K1>(r))));
+            acc[i] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(bv, av, acc[i], 0, 0, 0, 0, 0, 0);
+        }
+    }
+    __syncthreads();   // every wave is past its reads of the halo and of dec0.c1's weights
+    // dec0.c2's weights (32-byte rows: 32 per 1 KB load, 2 slots per row)
+#pragma unroll
+    for (int t = 0; t < (WR / 32 + NW - 1) / NW; ++t) {
+        const int j = wave + t * NW;
+        if (j >= WR / 32) continue;
+        const int row = 32 * j + (lane >> 1), tap = row / 32, n = row % 32;
+        const int c = (lane & 1) ^ swz<K2>(row);
+        __builtin_amdgcn_global_load_lds((const void*)(w2 + n * (kTaps * c2.cin) + tap * c2.cin + 16 * c),
+                                         (__attribute__((address_space(3))) void*)(ws + 1024 * j), 16, 0, 0);
+    }
+    // dec0.c1's stored-output epilogue into the tile: row r is row a0 + r
+    {
+        const RowMap rmap(a0 < 0 ? 0 : a0, c1.r_in);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int r = wave * 64 + i * 32 + r32;
+            const int64_t g = a0 + r;
+            bool keep = g >= 0 && g < c1.m_rows;
+            if (keep) {
+                int64_t e;
+                int loc;
+                rmap.at((int)(g - (a0 < 0 ? 0 : a0)), e, loc);
+                keep = loc >= kGuard && loc < c1.r_in - kGuard;
+            }
+#pragma unroll
+            for (int gq = 0; gq < 4; ++gq) {
+                const int col = 8 * gq + 4 * h;
+                const f32x4 fs = *reinterpret_cast<const f32x4*>(c1.fold_scale + col);
+                const f32x4 fb = *reinterpret_cast<const f32x4*>(c1.fold_bias + col);
+                float y[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    y[v] = fminf(fmaxf(lrelu(fmaf(acc[i][4 * gq + v], fs[v], fb[v]), c1.slope), -448.f), 448.f);
+                uint32_t w = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(y[0], y[1], 0, false);
+                w = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(y[2], y[3], (int)w, true);
+                *reinterpret_cast<uint32_t*>(xs + r * K2 + 16 * ((col / 16) ^ swz<K2>(r)) + col % 16) = keep ? w : 0u;
+            }
+        }
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    // ---- phase 2: dec0.c2 on the tile (five slices, three MFMAs; rows BA ..
+    // BA + 3 of the tile are stale and feed only outputs t >= BO)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[i][v] = 0.f;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const int s0 = 2 * p + h;
+        const bool pad = s0 >= kTaps;
+        const int tap = pad ? kTaps - 1 : s0;
+        const int rw = tap * 32 + r32;
+        const i32x8 bv = pad ? i32x8{0, 0, 0, 0, 0, 0, 0, 0}
+                             : join(*reinterpret_cast<const u32x4*>(ws + rw * K2 + 16 * (0 ^ swz<K2>(rw))),
+                                    *reinterpret_cast<const u32x4*>(ws + rw * K2 + 16 * (1 ^ swz<K2>(rw))));
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int r = wave * 64 + i * 32 + r32 + tap;
+            const i32x8 av = pad ? i32x8{0, 0, 0, 0, 0, 0, 0, 0}
+                                 : join(*reinterpret_cast<const u32x4*>(xs + r * K2 + 16 * (0 ^ swz<K2>(r))),
+                                        *reinterpret_cast<const u32x4*>(xs + r * K2 + 16 * (1 ^ swz<K2>(r))));
+            acc[i] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(bv, av, acc[i], 0, 0, 0, 0, 0, 0);
+        }
+    }
+    // head epilogue, as the standalone head launch's
+    const RowMap rows(m0, c2.r_in);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        float sum = 0.f;
+#pragma unroll
+        for (int gq = 0; gq < 4; ++gq)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = 8 * gq + 4 * h + v;
+                sum += lrelu(acc[i][4 * gq + v] * c2.col_scale[c] + c2.bias[c], c2.slope) * c2.head_w[c];
+            }
+        sum += __shfl_xor(sum, 32);
+        const int t = wave * 64 + i * 32 + r32;
+        if (h == 0 && t < BO && m0 + t < c2.m_rows) {
+            int64_t e;
+            int loc;
+            rows.at(t, e, loc);
+            if (loc >= kGuard && loc < c2.r_in - kGuard)
+                c2.prob[e * c2.l_out + (loc - kGuard)] = 1.f / (1.f + expf(-(sum + c2.head_b)));
+        }
+    }
+}
+
 template <int WM, int WN, int TMW, int TNW, int KB, int NB, int TAPS, int EPI>
 hipError_t run(const ConvArgs& a, hipStream_t s)
 {
@@ -457,6 +640,8 @@ constexpr Variant kVariants[] = {
     {4, 1, 2, 2, 32, 1},   // 17: 256 x 64, 32-channel stages, single-buffered
     {4, 1, 2, 1, 32, 1},   // 18: 256 x 32, 32-channel stages, single-buffered
     {2, 1, 2, 2, 64, 1},   // 19: 128 x 64, single-buffered (128 threads)
+    {4, 1, 2, 1, 32, 3},   // 20: head launch with dec0.c1 fused (conv_mfma_fp8x64_dec0, 4 waves, 240 rows)
+    {8, 1, 2, 1, 32, 3},   // 21: the same with 8 waves (496 rows)
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -553,6 +738,7 @@ bool fp8_variant_ok(int v, int n, int cin, int taps, Epi epi)
 {
     if (v < 0 || v >= kNumVariants) return false;
     const Variant& x = kVariants[v];
+    if (x.nb == 3) return epi == EPI_HEAD && n == 32 && cin == 32 && taps == kTaps;   // dec0 fused: 32-channel head
     const int bn = x.wn * x.tnw * 32;
     // the stage width follows the input channels: 64 when they allow it
     if (cin % 32 != 0 || (x.kb == 64) != (cin % 64 == 0)) return false;
@@ -591,9 +777,27 @@ std::string fp8_kernel_name(int v, int cin, int taps, Epi epi)
 {
     (void)cin;
     const Variant& x = kVariants[v];
+    if (x.nb == 3) return "conv_mfma_fp8x64_dec0<" + std::to_string(x.wm) + ">";
     return "conv_mfma_fp8x64<" + std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " + std::to_string(x.tmw) +
            ", " + std::to_string(x.tnw) + ", " + std::to_string(x.kb) + ", " + std::to_string(taps) + ", " +
            std::to_string((int)epi) + ", " + std::to_string(x.nb) + ">";
+}
+
+bool fp8_dec0_ok(int v) { return v >= 0 && v < kNumVariants && kVariants[v].nb == 3; }
+
+hipError_t launch_conv_fp8_dec0(const ConvArgs& c1, const ConvArgs& c2, int v, hipStream_t s)
+{
+    if (!fp8_dec0_ok(v) || c1.cin != 64 || c1.n != 32 || c2.cin != 32 || c2.n != 32 || c1.m_rows != c2.m_rows ||
+        c1.r_in != c2.r_in || c2.m_rows <= 0 || !c1.fold_scale || !c1.fold_bias || !c2.col_scale || !c2.prob ||
+        !c2.head_w)
+        return hipErrorInvalidValue;
+    const int wm = kVariants[v].wm;
+    const int bo = wm * 64 - 16;
+    const unsigned m_tiles = (unsigned)((c2.m_rows + bo - 1) / bo);
+    dim3 grid((m_tiles + kXcds - 1) / kXcds * kXcds);
+    if (wm == 4) hipLaunchKernelGGL(conv_mfma_fp8x64_dec0<4>, grid, dim3(256), 0, s, c1, c2);
+    else hipLaunchKernelGGL(conv_mfma_fp8x64_dec0<8>, grid, dim3(512), 0, s, c1, c2);
+    return hipGetLastError();
 }
 
 hipError_t launch_conv_fp8(const ConvArgs& a, int taps, Epi epi, int v, hipStream_t s)

@@ -960,6 +960,134 @@ void conv_mfma_lp_dec0d(ConvArgs c1, ConvArgs c2)
     }
 }
 
+// enc0.c2 (32 channels in and out) with the first convolution computed in
+// its staging, the weight tile loaded straight into LDS: no staging
+// registers, the first convolution's weights and biases in LDS (one copy per
+// block, read by every thread), and each thread computing one 8-channel chunk
+// of R consecutive halo rows from one window of R + 4 histogram values, all
+// loaded while the weight tile streams in.  The arithmetic per value is
+// first_conv_at and one rounding, as in the standalone kernel, and the
+// 32-channel stage, k order and max-pool epilogue are those of the
+// register-staged tile, so the bits are the same.
+template <class T, int WM, int TMW>
+__global__ __launch_bounds__(WM * 64) __attribute__((amdgpu_waves_per_eu(4)))
+void conv_mfma_lp_firstd(ConvArgs a)
+{
+    using V = typename Lp<T>::vec8;
+    constexpr int NW = WM, NT = NW * 64;
+    constexpr int BM = WM * TMW * 16;
+    constexpr int TNW = 2, BN = 32;              // all 32 output channels
+    constexpr int KC = 32, NCH = 4;              // the one 32-channel stage, 64-byte rows
+    constexpr int ROWB = KC * (int)sizeof(T);
+    constexpr int XROWS = BM + kTaps - 1;
+    constexpr int XR = (XROWS + 15) / 16 * 16;
+    constexpr int WRW = BN * kTaps;
+    constexpr int OP = BN + 8;
+    constexpr int SMEM = Max<(XR + WRW) * ROWB, BM * OP * (int)sizeof(T)>::v;
+    constexpr int GR = NT / NCH;                 // row groups (one per thread and chunk)
+    constexpr int R = (XROWS + GR - 1) / GR;     // consecutive halo rows per thread
+    __shared__ __attribute__((aligned(16))) char smem[SMEM];
+    __shared__ __attribute__((aligned(16))) float fp[KC * kTaps + KC];   // first conv: weights [c][5], biases [c]
+    T* const xs = reinterpret_cast<T*>(smem);
+    T* const ws = xs + XR * KC;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int li = lane & 15, lg = lane >> 4;
+    const int m_tiles = (int)((a.m_rows + BM - 1) / BM);
+    const int xcd = (int)(blockIdx.x % kXcds), slot = (int)(blockIdx.x / kXcds);
+    const int m_tile = slot * kXcds + xcd;
+    if (m_tile >= m_tiles) return;
+    const int64_t m0 = (int64_t)m_tile * BM;
+
+    // weight tile: wave-wide load j fills weight rows 16 j .. 16 j + 15
+    // (row = tap * 32 + column), lane L slot L % 4 of row L / 4
+    const T* wt = static_cast<const T*>(a.w);
+#pragma unroll
+    for (int t = 0; t < (WRW / 16 + NW - 1) / NW; ++t) {
+        const int j = wave + t * NW;
+        if (j >= WRW / 16) continue;
+        const int row = 16 * j + (lane >> 2), tap = row / BN, n = row % BN;
+        const int c = (lane & 3) ^ swz<NCH>(row);
+        __builtin_amdgcn_global_load_lds((const void*)(wt + (int64_t)n * (kTaps * a.cin) + tap * a.cin + 8 * c),
+                                         (__attribute__((address_space(3))) void*)(ws + 16 * j * KC), 16, 0, 0);
+    }
+    // the first convolution's 160 weights and 32 biases
+    if (wave == 0 && lane < KC * kTaps / 4)
+        __builtin_amdgcn_global_load_lds((const void*)(a.first_w + 4 * lane),
+                                         (__attribute__((address_space(3))) void*)fp, 16, 0, 0);
+    if (wave == NW - 1 && lane < KC / 4)
+        __builtin_amdgcn_global_load_lds((const void*)(a.first_b + 4 * lane),
+                                         (__attribute__((address_space(3))) void*)(fp + KC * kTaps), 16, 0, 0);
+    // this thread's rows r0 .. r0 + R - 1 (halo row r is row m0 - 2 + r) and
+    // their histogram window, clamped to the batch (clamped values only feed
+    // rows that are stored as zero)
+    const int q = tid % NCH, r0 = (tid / NCH) * R;
+    float xw[R + kTaps - 1];
+#pragma unroll
+    for (int k = 0; k < R + kTaps - 1; ++k) {
+        int64_t g = m0 - 2 + r0 + k - kGuard;
+        g = g < 0 ? 0 : (g >= a.m_rows ? a.m_rows - 1 : g);
+        xw[k] = a.first_x0[g];
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    {
+        const RowMap rmap(m0, a.r_in);
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int r = r0 + u;
+            if (r >= XROWS) break;
+            int64_t g = m0 - 2 + r;
+            g = g < 0 ? 0 : (g >= a.m_rows ? a.m_rows - 1 : g);
+            int64_t e;
+            int loc;
+            rmap.at((int)(g - m0), e, loc);
+            T y[8];
+            if (loc < kGuard || loc >= a.r_in - kGuard) {
+#pragma unroll
+                for (int v = 0; v < 8; ++v) y[v] = (T)0.f;
+            } else {
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    const int c = 8 * q + v;
+                    float w5[kTaps];
+#pragma unroll
+                    for (int k = 0; k < kTaps; ++k) w5[k] = fp[c * kTaps + k];
+                    y[v] = (T)first_conv_at(w5, fp[KC * kTaps + c], xw + u, a.slope);
+                }
+            }
+            u32x4 yv;
+            __builtin_memcpy(&yv, y, sizeof(y));
+            *reinterpret_cast<u32x4*>(xs + lds_at<NCH>(r, q)) = yv;
+        }
+    }
+    __syncthreads();
+
+    f32x4 acc[TMW][TNW];
+#pragma unroll
+    for (int i = 0; i < TMW; ++i)
+#pragma unroll
+        for (int j = 0; j < TNW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < kTaps; ++tap) {
+        V av[TMW], bv[TNW];
+#pragma unroll
+        for (int i = 0; i < TMW; ++i)
+            av[i] = *reinterpret_cast<const V*>(xs + lds_at<NCH>(wave * TMW * 16 + i * 16 + li + tap, lg));
+#pragma unroll
+        for (int j = 0; j < TNW; ++j)
+            bv[j] = *reinterpret_cast<const V*>(ws + lds_at<NCH>(tap * BN + j * 16 + li, lg));
+#pragma unroll
+        for (int i = 0; i < TMW; ++i)
+#pragma unroll
+            for (int j = 0; j < TNW; ++j) acc[i][j] = Lp<T>::mfma(bv[j], av[i], acc[i][j]);
+    }
+    __syncthreads();   // the epilogue reuses the stage buffer
+    lp_epilogue<T, NT, BM, BN, WM, TMW, TNW, EPI_POOL>(acc, a, smem, m0, 0, tid);
+}
+
 template <class T, int WM, int WN, int TMW, int TNW, int KC, int PF, int TAPS, int EPI>
 hipError_t run(const ConvArgs& a, hipStream_t s)
 {
@@ -1024,6 +1152,9 @@ constexpr Variant kVariants[] = {
     {2, 2, 4, 4, 32, 4},   // 30: 128 x 128, single-buffered direct-to-LDS
     {4, 1, 4, 2, 32, 5},   // 31: head launch with dec0.c1 fused, stages straight into LDS (4 waves, 240 rows)
     {8, 1, 4, 2, 32, 5},   // 32: the same with 8 waves (496 rows)
+    {2, 1, 4, 2, 32, 6},   // 33: enc0.c2 with the first conv, weight tile straight into LDS (128 x 32)
+    {4, 1, 4, 2, 32, 6},   // 34: the same, 256 x 32
+    {8, 1, 4, 2, 32, 6},   // 35: the same, 512 x 32
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -1104,6 +1235,11 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_LP_CASE(28)
             PVF_LP_CASE(29)
             PVF_LP_CASE(30)
+        // 33-35 run as the register-staged tile of the same shape when
+        // enc0.c2 does not compute the first convolution (calibration)
+        case 33: return run<T, 2, 1, 4, 2, 32, 0, TAPS, EPI>(a, s);
+        case 34: return run<T, 4, 1, 4, 2, 32, 0, TAPS, EPI>(a, s);
+        case 35: return run<T, 8, 1, 4, 2, 32, 0, TAPS, EPI>(a, s);
         default: return hipErrorInvalidValue;
         }
     }
@@ -1134,6 +1270,7 @@ bool lp_variant_ok(int v, int n, int cin, int taps, Epi epi)
     if (v < 0 || v >= kNumVariants) return false;
     const Variant& x = kVariants[v];
     if (x.pf == 3 || x.pf == 5) return epi == EPI_HEAD && n == 32 && cin == 32 && taps == kTaps;   // dec0 fused: 32-channel head
+    if (x.pf == 6) return epi == EPI_POOL && n == 32 && cin == 32 && taps == kTaps;   // enc0.c2 of 32 channels
     const int bn = x.wn * x.tnw * 16;
     if (cin % x.kc != 0) return false;
     if (epi == EPI_HEAD)
@@ -1146,7 +1283,9 @@ bool lp_variant_ok(int v, int n, int cin, int taps, Epi epi)
 }
 
 // Defaults from the autotuner's BF16 picks on MI355X at 1000 events.  The
-// small-channel layers take the 512-row, 128-row or 64-channel-stage tiles;
+// small-channel layers take the 512-row, 128-row or 64-channel-stage tiles
+// (the 32-channel enc0.c2: the 512-row tile that computes the first
+// convolution with its weight tile loaded straight into LDS);
 // from 64 output channels and 64 input channels on, the single-buffered
 // direct-to-LDS 256 x 64 tile (four blocks per CU; also the 64-channel head),
 // except the 128-channel layer over 64 input channels (256 x 128, single
@@ -1156,7 +1295,7 @@ int lp_default_variant(int n, int cin, int taps, Epi epi)
 {
     if (epi == EPI_HEAD) return n == 64 ? 28 : 20;
     if (epi == EPI_CONVT && taps == 1) return n >= 512 ? 17 : (n >= 128 ? 15 : (cin % 64 == 0 ? 8 : 4));
-    if (n <= 32) return epi == EPI_POOL ? 5 : (cin % 64 == 0 ? 8 : 14);
+    if (n <= 32) return epi == EPI_POOL ? (n == 32 && cin == 32 ? 35 : 5) : (cin % 64 == 0 ? 8 : 14);
     if (cin <= 32) return 22;
     if (n > 64 && cin < 128) return 3;
     return 28;
@@ -1203,6 +1342,10 @@ hipError_t launch_conv_lp_dec0(int dtype, const ConvArgs& c1, const ConvArgs& c2
 std::string lp_kernel_name(int dtype, int v, int taps, Epi epi)
 {
     const Variant& x = kVariants[v];
+    if (x.pf == 6)   // not fused: the register-staged tile of the same shape runs
+        return std::string("conv_mfma_lp<") + (dtype == PVF_BF16 ? "__bf16" : "_Float16") + ", " +
+               std::to_string(x.wm) + ", 1, " + std::to_string(x.tmw) + ", 2, 32, 0, " + std::to_string(taps) + ", " +
+               std::to_string((int)epi) + ">";
     if (x.pf == 3 || x.pf == 5)
         return std::string(x.pf == 3 ? "conv_mfma_lp_dec0<" : "conv_mfma_lp_dec0d<") +
                (dtype == PVF_BF16 ? "__bf16" : "_Float16") + ", " + std::to_string(x.wm) + ">";
@@ -1222,12 +1365,15 @@ std::string lp_kernel_name(int dtype, int v, int taps, Epi epi)
 // registers; the double-buffered ones load straight into LDS).
 bool lp_first_ok(int v)
 {
-    return v == 0 || v == 1 || v == 5 || v == 20 || v == 22;
+    return v == 0 || v == 1 || v == 5 || v == 20 || v == 22 || v == 33 || v == 34 || v == 35;
 }
 
 std::string lp_first_kernel_name(int dtype, int v)
 {
     const Variant& x = kVariants[v];
+    if (x.pf == 6)
+        return std::string("conv_mfma_lp_firstd<") + (dtype == PVF_BF16 ? "__bf16" : "_Float16") + ", " +
+               std::to_string(x.wm) + ", " + std::to_string(x.tmw) + ">";
     return std::string("conv_mfma_lp_first<") + (dtype == PVF_BF16 ? "__bf16" : "_Float16") + ", " +
            std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " + std::to_string(x.tmw) + ", " +
            std::to_string(x.tnw) + ">";
@@ -1238,6 +1384,21 @@ hipError_t launch_conv_lp_first(int dtype, const ConvArgs& a, int v, hipStream_t
     if (a.cin % 32 != 0 || a.m_rows <= 0 || !lp_first_ok(v) || !lp_variant_ok(v, a.n, a.cin, kTaps, EPI_POOL))
         return hipErrorInvalidValue;
     if (dtype != PVF_BF16 && dtype != PVF_FP16) return hipErrorInvalidValue;
+    if (kVariants[v].pf == 6) {
+        if (a.n != 32 || a.cin != 32) return hipErrorInvalidValue;
+        const int wm = kVariants[v].wm, bm = wm * 64;
+        const unsigned m_tiles = (unsigned)((a.m_rows + bm - 1) / bm);
+        dim3 grid((m_tiles + kXcds - 1) / kXcds * kXcds);
+        auto go = [&](auto tag) {
+            using T = decltype(tag);
+            if (wm == 2) hipLaunchKernelGGL((conv_mfma_lp_firstd<T, 2, 4>), grid, dim3(128), 0, s, a);
+            else if (wm == 4) hipLaunchKernelGGL((conv_mfma_lp_firstd<T, 4, 4>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((conv_mfma_lp_firstd<T, 8, 4>), grid, dim3(512), 0, s, a);
+        };
+        if (dtype == PVF_BF16) go(__bf16{});
+        else go(_Float16{});
+        return hipGetLastError();
+    }
 #define PVF_LP_FIRST(V, TYPE)                                                                                  \
     case V:                                                                                                \
         return run_first<TYPE, kVariants[V].wm, kVariants[V].wn, kVariants[V].tmw, kVariants[V].tnw>(a, s);

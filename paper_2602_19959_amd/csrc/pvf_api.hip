@@ -448,12 +448,11 @@ bool fuses_up(const pvf_engine* e, int i)
 }
 
 // Whether launch i (dec0.c2 + head) computes dec0.c1 in the same kernel:
-// 16-bit engines, a variant that does, and no calibration running (the
-// calibration reads dec0.c1's stored output).
+// 16-bit and FP8 engines, a variant that does, and no calibration running
+// (the calibration reads dec0.c1's stored output).
 bool fuses_dec0(const pvf_engine* e, int i)
 {
-    const int dt = e->spec.compute_dtype;
-    return e->conv[i].dec0 && !e->calib_table && (dt == PVF_BF16 || dt == PVF_FP16) && lp_dec0_ok(e->conv[i].variant);
+    return e->conv[i].dec0 && !e->calib_table && conv_dec0_ok(e->spec.compute_dtype, e->conv[i].variant);
 }
 
 // Kernel names of dec0.c1 and dec0.c2 + head for the head's current variant.
@@ -928,8 +927,15 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
             b.prob = prob;
             b.l_out = lv.L;
             if (dec0) {
-                check(launch_conv_lp_dec0(dt, c1, b, var(), s));
-            } else if (eng->conv[li].dec0 && lp_dec0_ok(var())) {
+                ConvArgs d1 = c1;
+                if (scales) {        // FP8: dec0.c1's (launch li - 1) stored-output factors, the head's column scales
+                    d1.col_scale = scales + eng->conv[li - 1].col;
+                    d1.fold_scale = scales + eng->conv[li - 1].fold;
+                    d1.fold_bias = scales + eng->conv[li - 1].fold + eng->conv[li - 1].n;
+                    b.col_scale = scales + eng->conv[li].col;
+                }
+                check(launch_conv_dec0(dt, d1, b, var(), s));
+            } else if (eng->conv[li].dec0 && conv_dec0_ok(dt, var())) {
                 // a fused variant while calibrating: dec0.c1 ran on its own,
                 // and the head takes the default tile
                 check(launch_conv(dt, b, kTaps, EPI_HEAD, conv_default_variant(dt, b.n, b.cin, kTaps, EPI_HEAD), s));

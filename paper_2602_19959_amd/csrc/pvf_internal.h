@@ -300,6 +300,11 @@ int lp_default_up_variant(int n, int cin);
 // arguments, c2: dec0.c2 + head's.
 bool lp_dec0_ok(int variant);
 hipError_t launch_conv_lp_dec0(int dtype, const ConvArgs& c1, const ConvArgs& c2, int variant, hipStream_t s);
+bool fp8_dec0_ok(int variant);
+hipError_t launch_conv_fp8_dec0(const ConvArgs& c1, const ConvArgs& c2, int variant, hipStream_t s);
+// dec0.c1 computed inside the head launch (16-bit and FP8 engines)
+bool conv_dec0_ok(int dtype, int variant);
+hipError_t launch_conv_dec0(int dtype, const ConvArgs& c1, const ConvArgs& c2, int variant, hipStream_t s);
 int fp8_default_up_variant(int n, int cin);
 std::string lp_first_kernel_name(int dtype, int variant);
 

@@ -171,6 +171,39 @@ def test_fused_transposed_convs_identical(fp8, batch16):
     assert eng.launch_kernels() == kernels
 
 
+def test_fused_level0_identical(fp8, batch16):
+    """Head-launch variants 20 and 21 compute dec0.c1 in the same kernel (its
+    FP8 codes stay in LDS) and the dec0.c1 slot enqueues nothing: every output
+    equals the two-launch path bit for bit, and the debug view refuses the
+    unstored dec0.c1 while fused."""
+    from paper_2602_19959_amd._binding import PvfError
+    eng, out = fp8
+    names = eng.launch_names()
+    h = names.index("dec0.c2+head")
+    base = eng.variants()
+    assert base[h] == 20, "the fused 4-wave head is the default"
+    try:
+        assert eng.set_variant(h, 13)   # the two-launch path as the reference
+        want = run(eng, batch16)
+        assert eng.launch_kernels()[h - 1] != "conv (in dec0.c2+head)"
+        for k in ("prob", "z", "integral", "n_vertices", "status", "bin"):
+            assert np.array_equal(want[k], out[k]), k
+        for v in (20, 21):
+            assert eng.set_variant(h, v)
+            k = eng.launch_kernels()
+            assert k[h - 1] == "conv (in dec0.c2+head)" and k[h].startswith("conv_mfma_fp8x64_dec0<"), k[h - 1:h + 1]
+            got = run(eng, batch16)
+            for key in ("prob", "z", "integral", "n_vertices", "status", "bin"):
+                assert np.array_equal(got[key], out[key]), (v, key)
+            with pytest.raises(PvfError):
+                eng.debug_tensor("dec0.c1", 1)
+            say("fused level 0, variant", v, "identical")
+    finally:
+        for i, v in enumerate(base):
+            if v >= 0:
+                eng.set_variant(i, v)
+
+
 def test_layer_taps_close_to_fp32(fp8, batch16):
     """Per-layer activations (dequantised with their channel scales) stay
     within FP8 rounding of the oracle's, normwise: 3 mantissa bits give a
@@ -179,13 +212,21 @@ def test_layer_taps_close_to_fp32(fp8, batch16):
     eng, out = fp8
     w = weights()
     taps = oracle.unet_taps(w.s_in * oracle.histogram(batch16.tracks_of(0), w)[0], w)
-    run(eng, batch16.subset([0]))
-    for name, bound in (("enc0.c2", 0.08), ("pool1", 0.1), ("enc3.c2", 0.2),
-                        ("up2", 0.2), ("dec1.c1", 0.2), ("dec0.c1", 0.25)):
-        got = eng.debug_tensor(name, 1).cpu().numpy().reshape(taps[name].shape)
-        err = parity.tap_err(got, taps[name])
-        say(name, "normwise %.3e (bound %.2f)" % (err, bound))
-        assert err <= bound, name
+    # event 0 alone, with the head on a tile that leaves dec0.c1 to its own
+    # launch (the fused head keeps dec0.c1 in LDS)
+    h = eng.launch_names().index("dec0.c2+head")
+    vh = eng.variants()[h]
+    assert eng.set_variant(h, 13)
+    try:
+        run(eng, batch16.subset([0]))
+        for name, bound in (("enc0.c2", 0.08), ("pool1", 0.1), ("enc3.c2", 0.2),
+                            ("up2", 0.2), ("dec1.c1", 0.2), ("dec0.c1", 0.25)):
+            got = eng.debug_tensor(name, 1).cpu().numpy().reshape(taps[name].shape)
+            err = parity.tap_err(got, taps[name])
+            say(name, "normwise %.3e (bound %.2f)" % (err, bound))
+            assert err <= bound, name
+    finally:
+        eng.set_variant(h, vh)
 
 
 def test_full_batch_sampled(amax):

@@ -124,6 +124,36 @@ def test_fused_transposed_convs_identical(lp, batch16):
     assert eng.launch_kernels() == kernels
 
 
+def test_first_conv_fused_and_standalone_agree(lp, batch16):
+    """By default enc0.c2 computes the first convolution in its staging
+    (weight tile straight into LDS); with a tile variant that cannot, the
+    standalone first-convolution kernel runs before it: every output is the
+    same bit for bit, and so with the register-staged fused tile."""
+    dt, eng, out = lp
+    names, kernels = eng.launch_names(), eng.launch_kernels()
+    i = names.index("enc0.c2")
+    assert names[i - 1] == "enc0.c1"
+    assert kernels[i].startswith("conv_mfma_lp_firstd<") and kernels[i - 1] == "first_conv (in enc0.c2)"
+    base = eng.variants()[i]
+    try:
+        for v in range(eng.variant_count(i)):
+            if eng.set_variant(i, v) and eng.launch_kernels()[i - 1] == "first_conv":
+                break
+        else:
+            pytest.fail("no variant of enc0.c2 without the fused first convolution")
+        say(dt, "enc0.c2 unfused:", eng.launch_kernels()[i])
+        got = run(eng, batch16)
+        for k in ("prob", "z", "integral", "n_vertices", "status", "bin"):
+            assert np.array_equal(got[k], out[k]), k
+        assert eng.set_variant(i, 5)
+        assert eng.launch_kernels()[i].startswith("conv_mfma_lp_first<")
+        got = run(eng, batch16)
+        assert np.array_equal(got["prob"], out["prob"])
+    finally:
+        eng.set_variant(i, base)
+    assert eng.launch_kernels() == kernels
+
+
 def test_fused_level0_identical(lp, batch16):
     """Head-launch variants 24, 25 (register-staged) and 31, 32 (stages
     straight into LDS, dec0.c1's tile in the halo's place) compute dec0.c1 in
