@@ -253,8 +253,8 @@ pvf_status pvf_graph_launch(pvf_engine *eng);
 
 /* Number of launch slots of one pvf_execute for this engine.  One slot,
  * enc0.c1 (the first convolution), enqueues nothing when enc0.c2's tile
- * variant computes the first convolution in its own staging (FP32, BF16 and
- * FP16 by default); its kernel name then reads "first_conv (in enc0.c2)" and
+ * variant computes the first convolution in its own staging (the default in
+ * every precision); its kernel name then reads "first_conv (in enc0.c2)" and
  * its profiled time is zero.  Likewise, in BF16, FP16 and FP8, the
  * transposed-conv slots up0 .. up(n_levels - 3) enqueue nothing when the
  * decoder conv before each (dec1.c2, dec2.c2, ...) has a tile variant holding

@@ -15,6 +15,7 @@ hipError_t launch_conv_first(int dtype, const ConvArgs& a, int variant, hipStrea
     if (!a.first_x0 || !a.first_w || !a.first_b) return hipErrorInvalidValue;
     if (dtype == PVF_FP32) return launch_conv_f32_first(a, variant, s);
     if (dtype == PVF_BF16 || dtype == PVF_FP16) return launch_conv_lp_first(dtype, a, variant, s);
+    if (dtype == PVF_FP8_E4M3) return launch_conv_fp8_first(a, variant, s);
     return hipErrorInvalidValue;
 }
 
@@ -22,12 +23,15 @@ bool conv_first_ok(int dtype, int variant)
 {
     if (dtype == PVF_FP32) return f32_first_ok(variant);
     if (dtype == PVF_BF16 || dtype == PVF_FP16) return lp_first_ok(variant);
+    if (dtype == PVF_FP8_E4M3) return fp8_first_ok(variant);
     return false;
 }
 
 std::string conv_first_kernel_name(int dtype, int variant)
 {
-    return dtype == PVF_FP32 ? f32_first_kernel_name(variant) : lp_first_kernel_name(dtype, variant);
+    if (dtype == PVF_FP32) return f32_first_kernel_name(variant);
+    if (dtype == PVF_FP8_E4M3) return fp8_first_kernel_name(variant);
+    return lp_first_kernel_name(dtype, variant);
 }
 
 int conv_variant_count(int dtype)

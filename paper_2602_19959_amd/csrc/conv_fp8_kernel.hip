@@ -98,11 +98,18 @@ struct F8Lds {
     static constexpr int v = Max<NB * STAGE, (EPI == EPI_HEAD ? 0 : BM * (BN + 16))>::v;
 };
 
-template <int WM, int WN, int TMW, int TNW, int KB, int TAPS, int EPI, int NB>
-__global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(occupancy_target(
-    F8Lds<WM * TMW * 32, WN * TNW * 32, KB, TAPS, EPI, NB>::v, WM * WN, TMW, TNW, NB))))
-void conv_mfma_fp8x64(ConvArgs a)
+// FC: enc0.c2 with the first convolution computed in its staging (one
+// 32-channel stage): the first convolution's weights, biases and output
+// scales go to LDS with the weight tile, each thread computes one 16-channel
+// chunk of R consecutive halo rows from one window of R + 4 histogram values
+// (loaded while the tiles stream in), with first_conv_at and the standalone
+// kernel's scaling and saturation, so the codes, and every bit after them,
+// are the same; guard rows and rows outside the batch are zero, as in the
+// stored tensor.
+template <int WM, int WN, int TMW, int TNW, int KB, int TAPS, int EPI, int NB, bool FC>
+__device__ __forceinline__ void fp8_tile(const ConvArgs& a)
 {
+    static_assert(!FC || (TAPS == kTaps && EPI == EPI_POOL && KB == 32), "the first convolution feeds enc0.c2");
     constexpr int NW = WM * WN;
     constexpr int NT = NW * 64;
     constexpr int BM = WM * TMW * 32;
@@ -121,6 +128,7 @@ void conv_mfma_fp8x64(ConvArgs a)
     constexpr int STAGE = L::STAGE;
     constexpr int OP = BN + 16;                  // epilogue tile pitch (bytes)
     __shared__ __attribute__((aligned(16))) uint8_t smem[L::v];
+    __shared__ __attribute__((aligned(16))) float fp[FC ? 7 * KB : 4];   // FC: weights [c][5], biases, 1 / output scales
 
     const uint8_t* in = static_cast<const uint8_t*>(a.in);
     const uint8_t* wt = static_cast<const uint8_t*>(a.w);
@@ -183,7 +191,7 @@ void conv_mfma_fp8x64(ConvArgs a)
 #pragma unroll
         for (int t = 0; t < JT; ++t) {
             const int j = wave + t * NW;
-            if ((t + 1) * NW <= NJ || j < NJ)
+            if (((t + 1) * NW <= NJ || j < NJ) && !(FC && j < XI))
                 __builtin_amdgcn_global_load_lds((const void*)((j < XI ? xbase : wbase) + (off[t] + (unsigned)c0)),
                                                  (__attribute__((address_space(3))) void*)(base + 1024 * j), 16, 0, 0);
         }
@@ -191,6 +199,54 @@ void conv_mfma_fp8x64(ConvArgs a)
 
     const int nk = a.cin / KB;
     issue(0, 0);
+    if constexpr (FC) {
+        constexpr int HR = BM + TAPS - 1;              // halo rows the MFMAs read
+        constexpr int GR = NT / CPR;                   // row groups: one per thread and 16-channel chunk
+        constexpr int R = (HR + GR - 1) / GR;          // consecutive rows per thread
+        if (wave == 0 && lane < KB * kTaps / 4)
+            __builtin_amdgcn_global_load_lds((const void*)(a.first_w + 4 * lane),
+                                             (__attribute__((address_space(3))) void*)fp, 16, 0, 0);
+        if (wave == NW - 1 && lane < KB / 4)
+            __builtin_amdgcn_global_load_lds((const void*)(a.first_b + 4 * lane),
+                                             (__attribute__((address_space(3))) void*)(fp + 5 * KB), 16, 0, 0);
+        if (wave == NW - 1 && lane < KB / 4)
+            __builtin_amdgcn_global_load_lds((const void*)(a.first_inv_scale + 4 * lane),
+                                             (__attribute__((address_space(3))) void*)(fp + 6 * KB), 16, 0, 0);
+        const int q = tid % CPR, r0 = (tid / CPR) * R;
+        float xw[R + kTaps - 1];
+#pragma unroll
+        for (int k = 0; k < R + kTaps - 1; ++k) {
+            int64_t g = m0 - RAD + r0 + k - kGuard;
+            g = g < 0 ? 0 : (g >= a.m_rows ? a.m_rows - 1 : g);
+            xw[k] = a.first_x0[g];
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        const RowMap rmap(m0, a.r_in);
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int r = r0 + u;
+            if (r >= HR) break;
+            int64_t g = m0 - RAD + r;
+            g = g < 0 ? 0 : (g >= a.m_rows ? a.m_rows - 1 : g);
+            int64_t e;
+            int loc;
+            rmap.at((int)(g - m0), e, loc);
+            uint32_t w4[4] = {0u, 0u, 0u, 0u};
+            if (loc >= kGuard && loc < a.r_in - kGuard) {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int c = 16 * q + v;
+                    float w5[kTaps];
+#pragma unroll
+                    for (int k = 0; k < kTaps; ++k) w5[k] = fp[c * kTaps + k];
+                    const float act = first_conv_at(w5, fp[5 * KB + c], xw + u, a.slope);
+                    w4[v / 4] |= (uint32_t)e4m3_sat(act * fp[6 * KB + c]) << (8 * (v % 4));
+                }
+            }
+            *reinterpret_cast<u32x4*>(smem + r * KB + 16 * (q ^ swz<KB>(r))) = u32x4{w4[0], w4[1], w4[2], w4[3]};
+        }
+    }
     for (int k = 0; k < nk; ++k) {
         // this wave's loads of stage k have landed; the barrier makes every
         // wave's visible and (NB = 2) frees the other buffer (last read in
@@ -603,6 +659,22 @@ void conv_mfma_fp8x64_dec0(ConvArgs c1, ConvArgs c2)
     }
 }
 
+template <int WM, int WN, int TMW, int TNW, int KB, int TAPS, int EPI, int NB>
+__global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(occupancy_target(
+    F8Lds<WM * TMW * 32, WN * TNW * 32, KB, TAPS, EPI, NB>::v, WM * WN, TMW, TNW, NB))))
+void conv_mfma_fp8x64(ConvArgs a)
+{
+    fp8_tile<WM, WN, TMW, TNW, KB, TAPS, EPI, NB, false>(a);
+}
+
+template <int WM, int WN, int TMW, int TNW, int NB>
+__global__ __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(occupancy_target(
+    F8Lds<WM * TMW * 32, WN * TNW * 32, 32, kTaps, EPI_POOL, NB>::v, WM * WN, TMW, TNW, NB))))
+void conv_mfma_fp8x64_first(ConvArgs a)
+{
+    fp8_tile<WM, WN, TMW, TNW, 32, kTaps, EPI_POOL, NB, true>(a);
+}
+
 template <int WM, int WN, int TMW, int TNW, int KB, int NB, int TAPS, int EPI>
 hipError_t run(const ConvArgs& a, hipStream_t s)
 {
@@ -642,6 +714,7 @@ constexpr Variant kVariants[] = {
     {2, 1, 2, 2, 64, 1},   // 19: 128 x 64, single-buffered (128 threads)
     {4, 1, 2, 1, 32, 3},   // 20: head launch with dec0.c1 fused (conv_mfma_fp8x64_dec0, 4 waves, 240 rows)
     {8, 1, 2, 1, 32, 3},   // 21: the same with 8 waves (496 rows)
+    {8, 1, 2, 1, 32, 1},   // 22: 512 x 32, 32-channel stages, single-buffered
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -684,6 +757,7 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_FP8_CASE(17)
             PVF_FP8_CASE(18)
             PVF_FP8_CASE(19)
+            PVF_FP8_CASE(22)
         default: return hipErrorInvalidValue;
         }
     } else if constexpr (TAPS == 1) {
@@ -725,6 +799,7 @@ hipError_t dispatch(int v, const ConvArgs& a, hipStream_t s)
             PVF_FP8_CASE(17)
             PVF_FP8_CASE(18)
             PVF_FP8_CASE(19)
+            PVF_FP8_CASE(22)
         default: return hipErrorInvalidValue;
         }
     }
@@ -753,7 +828,8 @@ bool fp8_variant_ok(int v, int n, int cin, int taps, Epi epi)
 }
 
 // Picks of the autotuner over 1000 events: the single-buffered tiles (more
-// blocks per CU) on the 5-tap layers but the 32-channel head, 256 x 64 (64 x 64 per wave) where the
+// blocks per CU) on the 5-tap layers but the 32-channel head (enc0.c2: the
+// single-buffered 256 x 32 tile that computes the first convolution), 256 x 64 (64 x 64 per wave) where the
 // layer has 64 or more output channels, 256 x 32 or 128 x 32 where it has 32,
 // 128 x 128 and 256 x 128 on the wide transposed convolutions; a decoder conv
 // that runs the following transposed conv in its epilogue needs a tile of all
@@ -763,7 +839,7 @@ int fp8_default_variant(int n, int cin, int taps, Epi epi)
     const bool k64 = cin % 64 == 0;
     if (epi == EPI_HEAD) return n == 64 ? (k64 ? 14 : 10) : (k64 ? 0 : 13);
     if (taps == 1) return n >= 256 ? 2 : (n >= 128 ? 3 : 0);
-    if (n <= 32) return k64 ? 15 : 9;
+    if (n <= 32) return k64 ? 15 : (epi == EPI_POOL ? 18 : 9);
     return k64 ? 14 : 17;
 }
 
@@ -784,6 +860,33 @@ std::string fp8_kernel_name(int v, int cin, int taps, Epi epi)
 }
 
 bool fp8_dec0_ok(int v) { return v >= 0 && v < kNumVariants && kVariants[v].nb == 3; }
+
+// enc0.c2 tiles that compute the first convolution in their staging: 32
+// output columns and one 32-channel stage (the 32-channel network's level
+// 0); the double-buffered 128- and 512-row tiles keep the standalone first
+// convolution, so level 0 has a variant of each kind.
+bool fp8_first_ok(int v) { return v == 9 || v == 18 || v == 22; }
+
+std::string fp8_first_kernel_name(int v)
+{
+    const Variant& x = kVariants[v];
+    return "conv_mfma_fp8x64_first<" + std::to_string(x.wm) + ", " + std::to_string(x.wn) + ", " +
+           std::to_string(x.tmw) + ", " + std::to_string(x.tnw) + ", " + std::to_string(x.nb) + ">";
+}
+
+hipError_t launch_conv_fp8_first(const ConvArgs& a, int v, hipStream_t s)
+{
+    if (!fp8_first_ok(v) || a.m_rows <= 0 || a.cin != 32 || a.n != 32 || !a.first_x0 || !a.first_w || !a.first_b ||
+        !a.first_inv_scale || !a.col_scale || !a.fold_scale || !a.fold_bias)
+        return hipErrorInvalidValue;
+    const int bm = kVariants[v].wm * 64;
+    const unsigned m_tiles = (unsigned)((a.m_rows + bm - 1) / bm);
+    dim3 grid((m_tiles + kXcds - 1) / kXcds * kXcds);
+    if (v == 9) hipLaunchKernelGGL((conv_mfma_fp8x64_first<4, 1, 2, 1, 2>), grid, dim3(256), 0, s, a);
+    else if (v == 18) hipLaunchKernelGGL((conv_mfma_fp8x64_first<4, 1, 2, 1, 1>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((conv_mfma_fp8x64_first<8, 1, 2, 1, 1>), grid, dim3(512), 0, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_conv_fp8_dec0(const ConvArgs& c1, const ConvArgs& c2, int v, hipStream_t s)
 {

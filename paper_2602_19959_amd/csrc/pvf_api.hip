@@ -870,6 +870,7 @@ pvf_status enqueue(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertices* ou
                 a.first_x0 = reinterpret_cast<float*>(wk(P.x0));
                 a.first_w = wbase + W.first_w;
                 a.first_b = wbase + W.first_b;
+                a.first_inv_scale = scales ? scales + eng->outinv_off[first_li] : nullptr;
             }
             conv(a, kTaps, EPI_POOL, l, 2 * lv.C, 0);
         } else {

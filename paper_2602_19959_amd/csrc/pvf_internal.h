@@ -152,6 +152,7 @@ struct ConvArgs {
     const float* first_x0;      // [m_rows] histogram rows, the input level's row layout
     const float* first_w;       // [cin][taps]
     const float* first_b;       // [cin]
+    const float* first_inv_scale;   // FP8: [cin], 1 / scale of the first convolution's stored output
     // EPI_UP: the transposed conv applied to this launch's output tile
     const void* up_w;           // packed [2 up_cout][n] (compute dtype), as a transposed-conv launch reads it
     const float* up_b;          // [up_cout] (16-bit engines; FP8 folds it into up_fold_bias)
@@ -301,6 +302,10 @@ int lp_default_up_variant(int n, int cin);
 bool lp_dec0_ok(int variant);
 hipError_t launch_conv_lp_dec0(int dtype, const ConvArgs& c1, const ConvArgs& c2, int variant, hipStream_t s);
 bool fp8_dec0_ok(int variant);
+// enc0.c2 with the first convolution fused into its staging (FP8)
+hipError_t launch_conv_fp8_first(const ConvArgs& a, int variant, hipStream_t s);
+bool fp8_first_ok(int variant);
+std::string fp8_first_kernel_name(int variant);
 hipError_t launch_conv_fp8_dec0(const ConvArgs& c1, const ConvArgs& c2, int variant, hipStream_t s);
 // dec0.c1 computed inside the head launch (16-bit and FP8 engines)
 bool conv_dec0_ok(int dtype, int variant);

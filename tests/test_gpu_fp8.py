@@ -171,6 +171,32 @@ def test_fused_transposed_convs_identical(fp8, batch16):
     assert eng.launch_kernels() == kernels
 
 
+def test_first_conv_fused_and_standalone_agree(fp8, batch16):
+    """By default enc0.c2 computes the first convolution in its staging (the
+    standalone kernel's arithmetic and output scale); with a tile variant that
+    cannot, the standalone first-convolution kernel runs before it, and every
+    output is the same bit for bit."""
+    eng, out = fp8
+    names, kernels = eng.launch_names(), eng.launch_kernels()
+    i = names.index("enc0.c2")
+    assert names[i - 1] == "enc0.c1"
+    assert kernels[i].startswith("conv_mfma_fp8x64_first<") and kernels[i - 1] == "first_conv (in enc0.c2)"
+    base = eng.variants()[i]
+    try:
+        for v in range(eng.variant_count(i)):
+            if eng.set_variant(i, v) and eng.launch_kernels()[i - 1] == "first_conv":
+                break
+        else:
+            pytest.fail("no variant of enc0.c2 without the fused first convolution")
+        say("enc0.c2 unfused:", eng.launch_kernels()[i])
+        got = run(eng, batch16)
+        for k in ("prob", "z", "integral", "n_vertices", "status", "bin"):
+            assert np.array_equal(got[k], out[k]), k
+    finally:
+        eng.set_variant(i, base)
+    assert eng.launch_kernels() == kernels
+
+
 def test_fused_level0_identical(fp8, batch16):
     """Head-launch variants 20 and 21 compute dec0.c1 in the same kernel (its
     FP8 codes stay in LDS) and the dec0.c1 slot enqueues nothing: every output
