@@ -22,15 +22,9 @@
 //     accumulators and writes the FP32 probability; a decoder conv whose
 //     output only feeds the next transposed conv runs that transposed conv on
 //     its tile in the epilogue (EPI_UP) and stores only the upsampled rows;
-//   * stages reach LDS through registers (conv_mfma_lp), or straight from
-//     global memory (global_load_lds_dwordx4: conv_mfma_lp_db), double- or
-//     single-buffered; the single-buffered tiles take half the LDS, so more
-//     blocks share a CU and cover each other's load latency;
-//   * conv_mfma_lp_first / conv_mfma_lp_firstd run enc0.c2 with the first
-//     convolution (one input channel, five taps) computed in its halo
-//     staging from the histogram rows, and conv_mfma_lp_dec0 /
-//     conv_mfma_lp_dec0d run dec0.c1 inside the head launch, so neither
-//     32-channel tensor goes through HBM.
+//   * conv_mfma_lp_first runs enc0.c2 with the first convolution (one input
+//     channel, five taps) computed in its halo staging from the histogram
+//     rows, so that 32-channel tensor never goes through HBM.
 #include "pvf_internal.h"
 
 namespace pvf {
