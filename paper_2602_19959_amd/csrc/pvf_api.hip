@@ -422,12 +422,6 @@ namespace {
 template <class T>
 T* at(pvf_engine* e, size_t off) { return reinterpret_cast<T*>(e->arena + off); }
 
-std::string track_kernel_name(bool persistent, int dtype)
-{
-    static const char* const kType[] = {"float", "__bf16", "_Float16", "unsigned char"};
-    return std::string(persistent ? "track_stage_queue<" : "track_stage<") + kType[dtype] + ">";
-}
-
 // Whether launch i (enc0.c2) computes the first convolution in its staging:
 // its tile variant can, and no calibration is running (the calibration reads
 // the first convolution's stored output).
@@ -533,7 +527,8 @@ void build_names(pvf_engine* e)
         e->conv.push_back(c);
         e->out_channels.push_back(epi == EPI_HEAD ? 0 : cout);
     };
-    plain("track", track_kernel_name(e->track_blocks > 0, e->spec.compute_dtype), 0);
+    plain("track", track_kernel_name(e->spec.compute_dtype, e->track_blocks > 0,
+                                    e->spec.n_bins / e->spec.bins_per_interval), 0);
     for (int l = 0; l < n; ++l) {
         const std::string L = std::to_string(l);
         const int C = c0 << l;
@@ -1037,7 +1032,8 @@ static pvf_status init_impl(const pvf_spec* spec, const void* blob, size_t blob_
         delete e;
         return PVF_ERR_DEVICE;
     }
-    e->track_blocks = 2 * e->cu_count;   // two 64 KB-LDS blocks per CU
+    e->track_blocks = track_queue_blocks(e->spec.compute_dtype, e->spec.n_bins / e->spec.bins_per_interval,
+                                         e->cu_count);
     e->scratch = scratch_base(dev);      // set-up of pvf_execute_scratch, once per device
     build_names(e);
 
@@ -1286,8 +1282,9 @@ pvf_status pvf_autotune(pvf_engine* eng, const pvf_tracks* tr, const pvf_vertice
 pvf_status pvf_set_track_schedule(pvf_engine* eng, int persistent)
 {
     if (!eng || (persistent != 0 && persistent != 1)) return PVF_ERR_INVALID_ARGUMENT;
-    eng->track_blocks = persistent ? 2 * eng->cu_count : 0;
-    eng->kernels[0] = track_kernel_name(persistent, eng->spec.compute_dtype);
+    const int n_intervals = eng->spec.n_bins / eng->spec.bins_per_interval;
+    eng->track_blocks = persistent ? track_queue_blocks(eng->spec.compute_dtype, n_intervals, eng->cu_count) : 0;
+    eng->kernels[0] = track_kernel_name(eng->spec.compute_dtype, persistent, n_intervals);
     return PVF_OK;
 }
 

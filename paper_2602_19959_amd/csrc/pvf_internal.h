@@ -256,6 +256,11 @@ hipError_t launch_amax(const AmaxArgs& a, hipStream_t s);
 // persistent_blocks > 0: the work-queue form (order kernel + persistent
 // blocks, a.order and a.queue_counter set).  Otherwise one block per event.
 hipError_t launch_track(const TrackArgs& a, int n_events, int persistent_blocks, hipStream_t s);
+// Blocks of the track stage's work-queue form for this engine: as many as fit
+// on the device at once.
+int track_queue_blocks(int dtype, int n_intervals, int cu_count);
+// Name of the track-stage kernel an engine launches.
+std::string track_kernel_name(int dtype, bool persistent, int n_intervals);
 hipError_t launch_first_conv(const FirstConvArgs& a, int dtype, hipStream_t s);
 // Conv launches run one of several tile-shape variants of the kernel for
 // the compute dtype; all variants of a dtype give identical bits.

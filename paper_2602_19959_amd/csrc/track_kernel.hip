@@ -68,6 +68,25 @@ __device__ __forceinline__ float softplus(float x)
     return fmaxf(x, 0.f) + 2.f * s * p;
 }
 
+// Softplus of the matrix-core engines, whose outputs come from a network
+// with 16-bit or 8-bit inputs: the same method with the exponent argument
+// rounded once (relative error of t below 6e-6 for |x| < 88; t flushes to
+// zero where the hardware exp2 does, near x = -87) and the atanh series to
+// s^11 / 11 (truncation below 2e-7 relative), about half the instructions.
+__device__ __forceinline__ float softplus_lp(float x)
+{
+    const float t = __builtin_amdgcn_exp2f(-fabsf(x) * 1.44269504f);
+    const float s = t * __builtin_amdgcn_rcpf(2.f + t);
+    const float z = s * s;
+    float p = 1.f / 11.f;
+    p = fmaf(p, z, 1.f / 9.f);
+    p = fmaf(p, z, 1.f / 7.f);
+    p = fmaf(p, z, 1.f / 5.f);
+    p = fmaf(p, z, 1.f / 3.f);
+    p = fmaf(p, z, 1.f);
+    return fmaxf(x, 0.f) + 2.f * s * p;
+}
+
 // Exact (uncontracted) lower edge of interval i, as the binning takes it.
 __device__ __forceinline__ double edge(const TrackArgs& a, int i)
 {
@@ -81,6 +100,42 @@ __device__ __forceinline__ void features(const TrackArgs& a, const float* f, dou
     g[0] = (float)((zd - edge(a, itv)) / (a.interval_mm * 0.5) - 1.0);
 #pragma unroll
     for (int k = 1; k < kFeat; ++k) g[k] = (f[k] - a.shift[k]) * a.scale[k];
+}
+
+// Item t of an event (t < end): its interval (-1 when it is dropped: outside
+// the window or not finite), its network inputs g in that interval's frame,
+// and the neighbouring interval it also feeds (-1 if none); the binning
+// compares with the exact interval edges in double.  A dropped item sets
+// *dropped (a benign race: every writer stores 1).
+__device__ __forceinline__ void bin_track(const TrackArgs& a, int64_t t, double z_max, bool two, int& itv, int& nb,
+                                          float* g, int* dropped)
+{
+    float f[kFeat];
+    bool finite = true;
+#pragma unroll
+    for (int k = 0; k < kFeat; ++k) {
+        f[k] = a.feat[k][t];
+        finite = finite && isfinite(f[k]);
+    }
+    const double zd = (double)f[0];
+    if (finite && zd >= a.z_min && zd < z_max) {
+        int i = (int)floor((zd - a.z_min) / a.interval_mm);
+        i = i < 0 ? 0 : (i >= a.n_intervals ? a.n_intervals - 1 : i);
+        if (zd < edge(a, i)) --i;
+        else if (zd >= edge(a, i + 1)) ++i;
+        if (i >= 0 && i < a.n_intervals) itv = i;
+    }
+    if (itv < 0) {
+        *dropped = 1;
+    } else {
+        features(a, f, zd, itv, g);
+        // boundary item: closer than boundary_mm to an edge shared with
+        // another interval (distances in double, exact edges)
+        if (two) {
+            if (zd - edge(a, itv) < a.boundary_mm && itv > 0) nb = itv - 1;
+            else if (edge(a, itv + 1) - zd < a.boundary_mm && itv < a.n_intervals - 1) nb = itv + 1;
+        }
+    }
 }
 
 // Calibration: the largest |v| over the wave, per channel, merged into the
@@ -433,38 +488,10 @@ __device__ void track_event(const TrackArgs& a, int e, float* smem)
             // ---- A: bin, features, hidden layers (own interval)
             const int64_t t = base + tid;
             int itv = -1, nb = -1;
-            float f[kFeat];
             float g[kFeat];
-            double zd = 0.0;
 #pragma unroll
             for (int k = 0; k < kFeat; ++k) g[k] = 0.f;
-            if (t < end) {
-                bool finite = true;
-#pragma unroll
-                for (int k = 0; k < kFeat; ++k) {
-                    f[k] = a.feat[k][t];
-                    finite = finite && isfinite(f[k]);
-                }
-                zd = (double)f[0];
-                if (finite && zd >= a.z_min && zd < z_max) {
-                    int i = (int)floor((zd - a.z_min) / a.interval_mm);
-                    i = i < 0 ? 0 : (i >= a.n_intervals ? a.n_intervals - 1 : i);
-                    if (zd < edge(a, i)) --i;
-                    else if (zd >= edge(a, i + 1)) ++i;
-                    if (i >= 0 && i < a.n_intervals) itv = i;
-                }
-                if (itv < 0) {
-                    dropped_any = 1;   // benign race: every writer stores 1
-                } else {
-                    features(a, f, zd, itv, g);
-                    // boundary track: closer than boundary_mm to an edge shared
-                    // with another interval (distances in double, exact edges)
-                    if (two) {
-                        if (zd - edge(a, itv) < a.boundary_mm && itv > 0) nb = itv - 1;
-                        else if (edge(a, itv + 1) - zd < a.boundary_mm && itv < a.n_intervals - 1) nb = itv + 1;
-                    }
-                }
-            }
+            if (t < end) bin_track(a, t, z_max, two, itv, nb, g, &dropped_any);
             network_hidden(g, itv >= 0);
             iv[tid] = itv;
             nbv[tid] = nb;
@@ -550,6 +577,279 @@ __global__ __launch_bounds__(NT) void track_stage_queue(TrackArgs a, int n_event
     }
 }
 
+// ---------------------------------------------------------------- histogram on the matrix cores
+//
+// The matrix-core engines keep an event's histogram in registers when it has
+// at most kRegIntervals intervals, and accumulate it on the matrix cores: per
+// sub-chunk of 64 items, H[i][j] += sum_t S[i][t] Y[t][j], with S the one-hot
+// item-to-interval matrix (a dropped item has a zero column) and Y the items'
+// softplus outputs.  Each wave owns two of the seven output column tiles (16
+// columns each) over every interval tile, and computes those outputs for all
+// of the chunk's sub-chunks itself; the output layer's MFMA fragment already
+// is the B operand of the accumulation: in K step s, element u of lane group
+// lg is item 16 (2 s + u / 4) + 4 lg + u % 4, the row that lane holds.  Y
+// enters as two BF16 terms, y = t0 + t1 + r with t0 = bf16(y) and
+// t1 = bf16(y - t0), so |r| <= 2^-16 |y| (below the 16-bit network's own
+// rounding), the products with the one-hot operand are exact, and the sums
+// are FP32 in the matrix core's fixed order: deterministic, no atomics,
+// depending only on the event's own items.  Outputs are capped below the
+// BF16 maximum, so a non-finite output cannot reach other intervals through
+// 0 x inf.  The event's histogram leaves the registers once, scaled, into the
+// UNet's input rows.
+constexpr int kRegMT = 3;                   // interval tiles of 16
+constexpr int kRegIntervals = 16 * kRegMT;
+constexpr float kBf16Max = 0x1.fcp127f;     // largest finite BF16
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// One-hot A operand of interval m for K step s: element u is 1 when the
+// lane's item (2 s + u / 4, u % 4) lies in interval m.
+__device__ __forceinline__ bf16x8 onehot(const int (&itv)[4][4], int s, int m)
+{
+    u32x4 r;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int u0 = 2 * p, u1 = 2 * p + 1;
+        const bool e0 = itv[2 * s + u0 / 4][u0 % 4] == m;
+        const bool e1 = itv[2 * s + u1 / 4][u1 % 4] == m;
+        r[p] = (e0 ? 0x3F80u : 0u) | (e1 ? 0x3F800000u : 0u);
+    }
+    return __builtin_bit_cast(bf16x8, r);
+}
+
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x8 x, bf16x8 w, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, w, c, 0, 0, 0);
+}
+
+// Column tiles of wave `wave` in block `blk`: q and q + 4, q = (wave + blk) % 4
+// (the tile count is odd, so the rotation spreads the lighter wave over the
+// SIMDs of a CU).
+__device__ __forceinline__ int hist_tile(int wave, int blk, int jl) { return ((wave + blk) & 3) + 4 * jl; }
+
+// Outputs of items [0, n) of the chunk for the wave's column tiles, added to
+// the wave's histogram tiles h[column tile][interval tile].
+template <class E>
+__device__ void outputs_to_hist(const TrackArgs& a, const E* xa, const int* iv, int n, int wave, int lane,
+                                f32x4 (&h)[2][kRegMT])
+{
+    using V = typename Net<E>::V;
+    constexpr int KP = Net<E>::KP;
+    const int li = lane & 15, lg = lane >> 4;
+    const E* W = static_cast<const E*>(a.mlp_lp) + (size_t)a.n_hidden * kMlpHiddenN * kMlpK;
+    const float* b = layer_bias(a, a.n_hidden);
+    bool on[2];
+    V w[2];
+    float cs[2], bn[2];
+#pragma unroll
+    for (int jl = 0; jl < 2; ++jl) {
+        const int jt = hist_tile(wave, blockIdx.x, jl);
+        on[jl] = jt < kMlpOutN / 16 && 16 * jt < a.n_out;
+        const int c = on[jl] ? 16 * jt + li : li;
+        w[jl] = *reinterpret_cast<const V*>(W + (size_t)c * kMlpK + 8 * lg);
+        const bool used = on[jl] && c < a.n_out;
+        cs[jl] = (sizeof(E) == 1 && used) ? a.mlp_col[a.n_hidden * kMlpHiddenN + c] : 1.f;
+        bn[jl] = used ? b[c] : 0.f;
+    }
+#pragma unroll 1
+    for (int sub = 0; sub < n; sub += SUB) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            // the lane's items 16 i + 4 lg + v, i = 2 s, 2 s + 1: intervals,
+            // layer inputs, and the one-hot operand of each interval tile
+            int itv[4][4];
+            V x[2];
+#pragma unroll
+            for (int ii = 0; ii < 2; ++ii) {
+                const int i = 2 * s + ii;
+                x[ii] = *reinterpret_cast<const V*>(xa + (size_t)(sub + 16 * i + li) * KP + 8 * lg);
+                const int4 q = *reinterpret_cast<const int4*>(iv + sub + 16 * i + 4 * lg);
+                itv[i][0] = q.x;
+                itv[i][1] = q.y;
+                itv[i][2] = q.z;
+                itv[i][3] = q.w;
+            }
+            bf16x8 oh[kRegMT];
+#pragma unroll
+            for (int mt = 0; mt < kRegMT; ++mt) oh[mt] = onehot(itv, s, 16 * mt + li);
+#pragma unroll
+            for (int jl = 0; jl < 2; ++jl) {
+                if (!on[jl]) continue;
+                // y = t0 + t1 + r with t0 = bf16(y), t1 = bf16(y - t0), |r| <= 2^-16 |y|
+                bf16x8 t0, t1;
+#pragma unroll
+                for (int ii = 0; ii < 2; ++ii) {
+                    const f32x4 acc = Net<E>::mfma(x[ii], w[jl], f32x4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const float y = fminf(softplus_lp(acc[v] * cs[jl] + bn[jl]), kBf16Max);
+                        const __bf16 y0 = (__bf16)y;
+                        t0[4 * ii + v] = y0;
+                        t1[4 * ii + v] = (__bf16)(y - (float)y0);
+                    }
+                }
+#pragma unroll
+                for (int mt = 0; mt < kRegMT; ++mt) {
+                    if (16 * mt >= a.n_intervals) break;
+                    h[jl][mt] = mfma_bf16(oh[mt], t0, h[jl][mt]);
+                    h[jl][mt] = mfma_bf16(oh[mt], t1, h[jl][mt]);
+                }
+            }
+        }
+    }
+}
+
+template <class E>
+__device__ void track_event_mma(const TrackArgs& a, int e, char* smem)
+{
+    constexpr int KP = Net<E>::KP;
+    E* xa = reinterpret_cast<E*>(smem);                               // [NT][KP] layer inputs
+    int* iv = reinterpret_cast<int*>(smem + NT * KP * sizeof(E));   // [NT] interval of each item
+    int* nbv = iv + NT;                                               // [NT] neighbour interval, or -1
+    int* st = nbv + NT;                                               // [NT] staged boundary items
+    __shared__ int dropped_any;
+    __shared__ int wave_count[NT / 64];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    f32x4 h[2][kRegMT];
+#pragma unroll
+    for (int jl = 0; jl < 2; ++jl)
+#pragma unroll
+        for (int mt = 0; mt < kRegMT; ++mt) h[jl][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    if (tid == 0) dropped_any = 0;
+    const int64_t beg = a.offsets[e];
+    const int64_t end = a.offsets[e + 1];
+    int status = 0;
+    if (beg < 0 || end < beg || end > a.n_tracks_total) status = PVF_EV_BAD_INPUT;
+    else if (end - beg > a.max_tracks) status = PVF_EV_TOO_MANY_TRACKS;
+    __syncthreads();
+
+    const double z_max = edge(a, a.n_intervals);
+    const bool two = a.boundary_mm > 0.0;
+
+    // hidden layers of one item per thread, into xa
+    auto network_hidden = [&](const float* g, bool valid) {
+        const bool any = __ballot(valid) != 0;
+        float z[kFeat];
+#pragma unroll
+        for (int k = 0; k < kFeat; ++k) z[k] = valid ? g[k] : 0.f;
+        if (a.mlp_calib)
+#pragma unroll
+            for (int k = 0; k < kFeat; ++k) wave_amax(a.mlp_calib + calib_off(0) + k, z[k]);
+        store_inputs<E>(a, xa, tid, z);
+        __builtin_amdgcn_wave_barrier();
+        if (any) hidden_layers_mma<E>(a, xa, wave, lane);
+    };
+
+    if (status == 0) {
+        for (int64_t base = beg; base < end; base += NT) {
+            const int64_t t = base + tid;
+            int itv = -1, nb = -1;
+            float g[kFeat];
+#pragma unroll
+            for (int k = 0; k < kFeat; ++k) g[k] = 0.f;
+            if (t < end) bin_track(a, t, z_max, two, itv, nb, g, &dropped_any);
+            network_hidden(g, itv >= 0);
+            iv[tid] = itv;
+            nbv[tid] = nb;
+            __syncthreads();
+            const int n_chunk = (int)((end - base) < NT ? (end - base) : NT);
+            outputs_to_hist<E>(a, xa, iv, n_chunk, wave, lane, h);
+            if (two) {
+                // the chunk's boundary items, in item order, once more in the
+                // neighbour's frame (the barrier below also ends every wave's
+                // reads of xa and iv above)
+                const bool is_b = nbv[tid] >= 0;
+                const uint64_t m = __ballot(is_b);
+                if (lane == 0) wave_count[wave] = __popcll(m);
+                __syncthreads();
+                int off = 0, n_st = 0;
+#pragma unroll
+                for (int w = 0; w < NT / 64; ++w) {
+                    off += w < wave ? wave_count[w] : 0;
+                    n_st += wave_count[w];
+                }
+                if (is_b) st[off + __popcll(m & ((1ull << lane) - 1ull))] = tid;
+                __syncthreads();
+                if (n_st > 0) {
+                    int inb = -1;
+                    float gs[kFeat];
+#pragma unroll
+                    for (int k = 0; k < kFeat; ++k) gs[k] = 0.f;
+                    if (tid < n_st) {
+                        const int src = st[tid];
+                        inb = nbv[src];
+                        float fs[kFeat];
+#pragma unroll
+                        for (int k = 0; k < kFeat; ++k) fs[k] = a.feat[k][base + src];
+                        features(a, fs, (double)fs[0], inb, gs);
+                    }
+                    __syncthreads();    // every read of nbv / st above is done
+                    network_hidden(gs, tid < n_st);
+                    iv[tid] = inb;
+                    __syncthreads();
+                    outputs_to_hist<E>(a, xa, iv, n_st, wave, lane, h);
+                }
+            }
+            __syncthreads();   // xa and iv are rewritten by the next chunk
+        }
+    }
+    // scaled histogram into the UNet's input rows (one sequence per event, or
+    // one per interval of unit_bins bins, two guard rows on each side); the
+    // lane holds intervals 16 mt + 4 lg + v of column 16 jt + li
+    const int n_bins = a.n_out * a.n_intervals;
+    const int U = n_bins / a.unit_bins;
+    float* x0 = a.x0 + (int64_t)e * U * a.r0 + kGuard;
+    // the store addresses are formed here, not held in registers (or spilled)
+    // through the event
+    int lo = lane;
+    asm volatile("" : "+v"(lo));
+    const int li = lo & 15, lg = lo >> 4;
+#pragma unroll
+    for (int jl = 0; jl < 2; ++jl) {
+        const int jt = hist_tile(wave, blockIdx.x, jl);
+        const int c = 16 * jt + li;
+        if (jt >= kMlpOutN / 16 || c >= a.n_out) continue;
+#pragma unroll
+        for (int mt = 0; mt < kRegMT; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int iw = 16 * mt + 4 * lg + v;
+                if (iw >= a.n_intervals) continue;
+                const int bb = iw * a.n_out + c;
+                const int u = bb / a.unit_bins;
+                x0[(int64_t)u * a.r0 + (bb - u * a.unit_bins)] = a.s_in * h[jl][mt][v];
+            }
+    }
+    if (tid == 0) a.flags[e] = status | (dropped_any ? PVF_EV_TRACKS_DROPPED : 0);
+    __syncthreads();   // the block's LDS is reused by its next event
+}
+
+// One block per event (queued == 0, grid = events), or the work-queue form
+// of track_stage_queue (queued == 1) when the events outnumber the blocks
+// that fit on the device at once.
+template <class E>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void track_stage_mma(TrackArgs a, int n_events,
+                                                                                         int queued)
+{
+    extern __shared__ __attribute__((aligned(16))) char smem_mma[];
+    __shared__ int ticket;
+    // one call site of the event body, for both forms
+    for (int k = blockIdx.x;;) {
+        if (queued) {
+            if (threadIdx.x == 0) ticket = atomicAdd(a.queue_counter, 1);
+            __syncthreads();
+            k = ticket;
+            __syncthreads();
+        }
+        if (k >= n_events) break;
+        track_event_mma<E>(a, queued ? a.order[k] : k, smem_mma);
+        if (!queued) break;
+    }
+}
+
 // Queue order: a counting sort of the events by descending track count
 // (counts clamped to [0, min(max_tracks, kOrderBuckets - 2) + 1]; malformed
 // offsets count 0), in one block, with the count histogram and the scatter
@@ -611,10 +911,34 @@ static size_t track_stage_lds_bytes(int n_out, int n_intervals)
            sizeof(int) * (2 * NT + 3 * SUB + 1);
 }
 
+// Whether the matrix-core engine's histogram fits the registers.
+static bool track_mma_ok(int dtype, int n_intervals) { return dtype != PVF_FP32 && n_intervals <= kRegIntervals; }
+
+template <class E>
+static size_t track_mma_lds_bytes()
+{
+    return (size_t)NT * Net<E>::KP * sizeof(E) + 3 * NT * sizeof(int);
+}
+
 template <class E>
 hipError_t launch_track_typed(const TrackArgs& a, int n_events, int persistent_blocks, hipStream_t s)
 {
     if (a.n_out < 1 || a.n_out > NT) return hipErrorInvalidValue;   // one thread per output column
+    if constexpr (sizeof(E) != 4) {
+        if (track_mma_ok(a.mlp_dtype, a.n_intervals)) {
+            // the queue (and its ordering pass) only when the events do not all
+            // fit on the device at once
+            const int queued = persistent_blocks > 0 && n_events > persistent_blocks && a.order && a.queue_counter;
+            if (queued) {
+                hipLaunchKernelGGL(track_order, dim3(1), dim3(kOrderThreads), 0, s, a, n_events);
+                const hipError_t err = hipGetLastError();
+                if (err != hipSuccess) return err;
+            }
+            hipLaunchKernelGGL(track_stage_mma<E>, dim3(queued ? persistent_blocks : n_events), dim3(NT),
+                               track_mma_lds_bytes<E>(), s, a, n_events, queued);
+            return hipGetLastError();
+        }
+    }
     const size_t lds = track_stage_lds_bytes(a.n_out, a.n_intervals);
     if (lds > 64 * 1024) {
         hipError_t err = hipFuncSetAttribute((const void*)track_stage<E>,
@@ -648,6 +972,36 @@ hipError_t launch_track(const TrackArgs& a, int n_events, int persistent_blocks,
     case PVF_FP8_E4M3: return launch_track_typed<uint8_t>(a, n_events, persistent_blocks, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+int track_queue_blocks(int dtype, int n_intervals, int cu_count)
+{
+    if (!track_mma_ok(dtype, n_intervals)) return 2 * cu_count;   // two 64 KB-LDS blocks per CU
+    int per_cu = 0;
+    hipError_t err = hipErrorInvalidValue;
+    switch (dtype) {
+    case PVF_BF16:
+        err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, track_stage_mma<__bf16>, NT,
+                                                           track_mma_lds_bytes<__bf16>());
+        break;
+    case PVF_FP16:
+        err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, track_stage_mma<_Float16>, NT,
+                                                           track_mma_lds_bytes<_Float16>());
+        break;
+    case PVF_FP8_E4M3:
+        err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, track_stage_mma<uint8_t>, NT,
+                                                           track_mma_lds_bytes<uint8_t>());
+        break;
+    default: break;
+    }
+    return (err == hipSuccess && per_cu > 0 ? per_cu : 1) * cu_count;
+}
+
+std::string track_kernel_name(int dtype, bool persistent, int n_intervals)
+{
+    static const char* const kType[] = {"float", "__bf16", "_Float16", "unsigned char"};
+    if (track_mma_ok(dtype, n_intervals)) return std::string("track_stage_mma<") + kType[dtype] + ">";
+    return std::string(persistent ? "track_stage_queue<" : "track_stage<") + kType[dtype] + ">";
 }
 
 }  // namespace pvf

@@ -20,9 +20,11 @@ def say(*a):
 
 @pytest.mark.parametrize("dtype", ["fp32", "bf16", "fp8_e4m3"])
 def test_track_schedules_identical(dtype):
+    """One block per event against the work queue; 2500 events outnumber the
+    blocks that fit on the device at once, so the queue form really runs."""
     torch_cuda()
-    batch = make_events(300, seed=4, mix="lognormal")
-    eng = engine_for(300, dtype, max_tracks_per_event=1000)
+    batch = make_events(2500, seed=4, mix="lognormal")
+    eng = engine_for(2500, dtype, max_tracks_per_event=1000)
     eng.set_track_schedule(True)
     q = run(eng, batch)
     eng.set_track_schedule(False)
