@@ -112,6 +112,33 @@ def test_boundary_tracks_fp32(b):
     eng.close()
 
 
+def test_boundary_tracks_bf16():
+    """Boundary tracks through the matrix-core network and the register
+    histogram: the BF16 histogram within BF16 rounding of the oracle's
+    (normwise), the neighbour terms present, p within the BF16 bound, and the
+    result deterministic and batch-invariant with the staging pass."""
+    torch_cuda()
+    b = 5.0
+    batch = make_events(8, seed=2)
+    say(f"boundary {b} mm, BF16, 8 events")
+    eng = make_engine(8, boundary_mm=b, compute_dtype="bf16")
+    assert eng.launch_kernels()[0].startswith("track_stage_mma<")
+    out = run(eng, batch)
+    w = weights()
+    refs = oracle.run_batch(batch, w, geometry(eng))
+    hist = eng.debug_tensor("hist", 8).cpu().numpy().reshape(8, -1)
+    for e in range(8):
+        err = parity.tap_err(hist[e], w.s_in * refs[e]["H"])
+        assert err <= 3e-2, (e, err)
+        assert float(np.max(np.abs(out["prob"][e] - refs[e]["p"]))) <= parity.P_ABS["bf16"], e
+    plain = oracle.histogram(batch.tracks_of(0), w)[0] * w.s_in
+    assert np.max(np.abs(hist[0] - plain)) > 1e-2 * np.max(np.abs(plain))
+    assert np.array_equal(run(eng, batch)["prob"], out["prob"])
+    alone = run(eng, batch.subset([3]))
+    assert np.array_equal(alone["prob"][0], out["prob"][3])
+    eng.close()
+
+
 def test_boundary_decisions_at_the_edges():
     """Tracks placed at, just inside and just outside the boundary distance of
     shared and outer edges: the intervals each event touches (non-zero bins)
