@@ -528,7 +528,7 @@ void build_names(pvf_engine* e)
         e->out_channels.push_back(epi == EPI_HEAD ? 0 : cout);
     };
     plain("track", track_kernel_name(e->spec.compute_dtype, e->track_blocks > 0,
-                                    e->spec.n_bins / e->spec.bins_per_interval), 0);
+                                    e->spec.n_bins / e->spec.bins_per_interval, e->spec.bins_per_interval), 0);
     for (int l = 0; l < n; ++l) {
         const std::string L = std::to_string(l);
         const int C = c0 << l;
@@ -1033,7 +1033,7 @@ static pvf_status init_impl(const pvf_spec* spec, const void* blob, size_t blob_
         return PVF_ERR_DEVICE;
     }
     e->track_blocks = track_queue_blocks(e->spec.compute_dtype, e->spec.n_bins / e->spec.bins_per_interval,
-                                         e->cu_count);
+                                         e->spec.bins_per_interval, e->cu_count);
     e->scratch = scratch_base(dev);      // set-up of pvf_execute_scratch, once per device
     build_names(e);
 
@@ -1283,8 +1283,10 @@ pvf_status pvf_set_track_schedule(pvf_engine* eng, int persistent)
 {
     if (!eng || (persistent != 0 && persistent != 1)) return PVF_ERR_INVALID_ARGUMENT;
     const int n_intervals = eng->spec.n_bins / eng->spec.bins_per_interval;
-    eng->track_blocks = persistent ? track_queue_blocks(eng->spec.compute_dtype, n_intervals, eng->cu_count) : 0;
-    eng->kernels[0] = track_kernel_name(eng->spec.compute_dtype, persistent, n_intervals);
+    const int n_out = eng->spec.bins_per_interval;
+    eng->track_blocks =
+        persistent ? track_queue_blocks(eng->spec.compute_dtype, n_intervals, n_out, eng->cu_count) : 0;
+    eng->kernels[0] = track_kernel_name(eng->spec.compute_dtype, persistent, n_intervals, n_out);
     return PVF_OK;
 }
 

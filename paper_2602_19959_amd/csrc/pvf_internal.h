@@ -258,9 +258,9 @@ hipError_t launch_amax(const AmaxArgs& a, hipStream_t s);
 hipError_t launch_track(const TrackArgs& a, int n_events, int persistent_blocks, hipStream_t s);
 // Blocks of the track stage's work-queue form for this engine: as many as fit
 // on the device at once.
-int track_queue_blocks(int dtype, int n_intervals, int cu_count);
+int track_queue_blocks(int dtype, int n_intervals, int n_out, int cu_count);
 // Name of the track-stage kernel an engine launches.
-std::string track_kernel_name(int dtype, bool persistent, int n_intervals);
+std::string track_kernel_name(int dtype, bool persistent, int n_intervals, int n_out);
 hipError_t launch_first_conv(const FirstConvArgs& a, int dtype, hipStream_t s);
 // Conv launches run one of several tile-shape variants of the kernel for
 // the compute dtype; all variants of a dtype give identical bits.

@@ -24,6 +24,7 @@
 // (sub-chunk by sub-chunk): the histogram is deterministic, with no atomics,
 // and depends only on the event's own tracks.  The block then writes the
 // scaled histogram, once, straight into the UNet's input rows.
+#include <cfloat>
 #include <cmath>
 
 #include "pvf_internal.h"
@@ -253,13 +254,14 @@ __device__ __forceinline__ void store_inputs(const TrackArgs& a, E* xa, int row,
 
 // Hidden layers of the wave's 64 rows, in place in xa.
 template <class E>
-__device__ void hidden_layers_mma(const TrackArgs& a, E* xa, int wave, int lane)
+__device__ void hidden_layers_mma(const TrackArgs& a, E* xa, const int* iv, int wave, int lane)
 {
     using V = typename Net<E>::V;
     constexpr int KP = Net<E>::KP;
     const int li = lane & 15, lg = lane >> 4;
     const E* wp = static_cast<const E*>(a.mlp_lp);
     E* rows = xa + (size_t)wave * 64 * KP;
+    const int* kept = iv + wave * 64 + 4 * lg;   // kept[16 i + v] >= 0: row 16 i + 4 lg + v is a kept item
     for (int l = 0; l < a.n_hidden; ++l) {
         const E* W = wp + (size_t)l * kMlpHiddenN * kMlpK;
         const float* b = layer_bias(a, l);
@@ -281,16 +283,21 @@ __device__ void hidden_layers_mma(const TrackArgs& a, E* xa, int wave, int lane)
             const float cs = (sizeof(E) == 1 && used) ? a.mlp_col[l * kMlpHiddenN + n] : 1.f;
             const float bn = used ? b[n] : 0.f;
             const float inv = (sizeof(E) == 1 && used) ? a.mlp_in_inv[(l + 1) * kMlpK + n] : 1.f;
-            float m = 0.f;
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const float y = used ? lrelu(acc[i][j][v] * cs + bn, a.slope) : 0.f;
-                    m = fmaxf(m, fabsf(y));
                     rows[(16 * i + 4 * lg + v) * KP + n] = Net<E>::cvt(y, inv);
                 }
             if (a.mlp_calib) {
+                // the largest |output| over the wave's kept items
+                float m = 0.f;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (kept[16 * i + v] >= 0) m = fmaxf(m, fabsf(used ? lrelu(acc[i][j][v] * cs + bn, a.slope) : 0.f));
                 m = fmaxf(m, __shfl_xor(m, 16));
                 m = fmaxf(m, __shfl_xor(m, 32));
                 if (lg == 0 && used)
@@ -400,7 +407,7 @@ __device__ void track_event(const TrackArgs& a, int e, float* smem)
                 for (int k = 0; k < kFeat; ++k) wave_amax(a.mlp_calib + calib_off(0) + k, z[k]);
             store_inputs<E>(a, xa, tid, z);
             __builtin_amdgcn_wave_barrier();
-            if (any) hidden_layers_mma<E>(a, xa, wave, lane);
+            if (any) hidden_layers_mma<E>(a, xa, iv, wave, lane);
         }
     };
 
@@ -492,8 +499,8 @@ __device__ void track_event(const TrackArgs& a, int e, float* smem)
 #pragma unroll
             for (int k = 0; k < kFeat; ++k) g[k] = 0.f;
             if (t < end) bin_track(a, t, z_max, two, itv, nb, g, &dropped_any);
+            iv[tid] = itv;   // read by the hidden layers' calibration
             network_hidden(g, itv >= 0);
-            iv[tid] = itv;
             nbv[tid] = nb;
             __syncthreads();
 
@@ -529,8 +536,8 @@ __device__ void track_event(const TrackArgs& a, int e, float* smem)
                         features(a, fs, (double)fs[0], inb, gs);
                     }
                     __syncthreads();    // every read of nbv / st above is done
-                    network_hidden(gs, tid < n_st);
                     iv[tid] = inb;
+                    network_hidden(gs, tid < n_st);
                     __syncthreads();
                     outputs_and_accumulate(n_st);
                 }
@@ -699,12 +706,147 @@ __device__ void outputs_to_hist(const TrackArgs& a, const E* xa, const int* iv, 
     }
 }
 
+// FP32 hidden layers on the matrix cores (v_mfma_f32_16x16x4_f32) for the
+// wave's 64 rows of hb, in place: K step s of row tile i gives lane (lg, li)
+// element k = 4 s + lg of row 16 i + li (zero past the layer's inputs) and
+// of channel 16 j + li's weights; bias and LeakyReLU in FP32 on the way back.
+// Calibration: each layer's per-channel output maximum over the wave's kept
+// rows (iv >= 0), the quantity the vector-ALU form measures.
+__device__ void hidden_layers_f32_mma(const TrackArgs& a, float* hb, const int* iv, int wave, int lane)
+{
+    const int li = lane & 15, lg = lane >> 4;
+    float* rows = hb + (size_t)wave * 64 * HP;
+    const float* Wh = a.mlp + kHidden * kFeat + kHidden;   // hidden layers 2.. : [W 20x20, b 20]
+    constexpr int KS = kHidden / 4;
+    const int* kept = iv + wave * 64 + 4 * lg;   // kept[16 i + v] >= 0: row 16 i + 4 lg + v is a kept item
+    for (int l = 0; l < a.n_hidden; ++l) {
+        const int K = l == 0 ? kFeat : kHidden;
+        const float* W = l == 0 ? a.mlp : Wh + (size_t)(l - 1) * (kHidden * kHidden + kHidden);   // [20][K]
+        const float* b = W + kHidden * K;
+        float w[2][KS];
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int c = 16 * j + li, k = 4 * ks + lg;
+                w[j][ks] = (c < kHidden && k < K) ? W[c * K + k] : 0.f;
+            }
+        f32x4 acc[4][2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            if (4 * ks >= K) break;
+            const int k = 4 * ks + lg;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float x = k < K ? rows[(16 * i + li) * HP + k] : 0.f;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, w[j][ks], acc[i][j], 0, 0, 0);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int c = 16 * j + li;
+            const bool used = c < kHidden;
+            const float bn = used ? b[c] : 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (used) rows[(16 * i + 4 * lg + v) * HP + c] = lrelu(acc[i][j][v] + bn, a.slope);
+            if (a.mlp_calib) {
+                // the largest |output| over the wave's kept items
+                float m = 0.f;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (kept[16 * i + v] >= 0) m = fmaxf(m, fabsf(lrelu(acc[i][j][v] + bn, a.slope)));
+                m = fmaxf(m, __shfl_xor(m, 16));
+                m = fmaxf(m, __shfl_xor(m, 32));
+                if (lg == 0 && used)
+                    atomicMax(reinterpret_cast<unsigned int*>(a.mlp_calib + calib_off(l + 1) + c), __float_as_uint(m));
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// FP32 engines: the output layer and the histogram on the matrix cores in
+// FP32 (v_mfma_f32_16x16x4_f32), from the last hidden activations in hb.  Output layer: K step s of
+// row tile i gives lane (lg, li) element k = 4 s + lg of item 16 i + li and
+// of column li's weights (K = 20, five steps).  Histogram: K step (i, v)
+// gives item 16 i + 4 lg + v, whose output the lane holds in acc[v] (the B
+// operand as it stands) and whose one-hot entry for interval 16 mt + li is
+// the A operand; every product is exact and the sums are FP32.
+__device__ void outputs_to_hist_f32(const TrackArgs& a, const float* hb, const int* iv, int n, int wave, int lane,
+                                    f32x4 (&h)[2][kRegMT])
+{
+    const int li = lane & 15, lg = lane >> 4;
+    const float* Wo = a.mlp + kHidden * kFeat + kHidden +
+                      (size_t)(a.n_hidden - 1) * (kHidden * kHidden + kHidden);   // [n_out][kHidden]
+    const float* bo = Wo + (size_t)a.n_out * kHidden;
+    constexpr int KS = kHidden / 4;
+    bool on[2];
+    float w[2][KS], bn[2];
+#pragma unroll
+    for (int jl = 0; jl < 2; ++jl) {
+        const int jt = hist_tile(wave, blockIdx.x, jl);
+        on[jl] = jt < kMlpOutN / 16 && 16 * jt < a.n_out;
+        const int c = 16 * jt + li;
+        const bool used = on[jl] && c < a.n_out;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) w[jl][ks] = used ? Wo[(size_t)c * kHidden + 4 * ks + lg] : 0.f;
+        bn[jl] = used ? bo[c] : 0.f;
+    }
+#pragma unroll
+    for (int jl = 0; jl < 2; ++jl) {
+        if (!on[jl]) continue;
+#pragma unroll 1
+        for (int sub = 0; sub < n; sub += SUB) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int4 q = *reinterpret_cast<const int4*>(iv + sub + 16 * i + 4 * lg);
+                const int itv[4] = {q.x, q.y, q.z, q.w};
+                const float* x = hb + (size_t)(sub + 16 * i + li) * HP + lg;
+                f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x[4 * ks], w[jl][ks], acc, 0, 0, 0);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float y = fminf(softplus(acc[v] + bn[jl]), FLT_MAX);
+#pragma unroll
+                    for (int mt = 0; mt < kRegMT; ++mt) {
+                        if (16 * mt >= a.n_intervals) break;
+                        const float oh = itv[v] == 16 * mt + li ? 1.f : 0.f;
+                        h[jl][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(oh, y, h[jl][mt], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Bytes of the layer-input rows: FP32 hidden activations [NT][HP], or the
+// matrix-core network's inputs [NT][KP] in E.
+template <class E>
+constexpr size_t row_tile_bytes()
+{
+    if constexpr (sizeof(E) == 4) return (size_t)NT * HP * sizeof(float);
+    else return (size_t)NT * Net<E>::KP * sizeof(E);
+}
+
 template <class E>
 __device__ void track_event_mma(const TrackArgs& a, int e, char* smem)
 {
-    constexpr int KP = Net<E>::KP;
-    E* xa = reinterpret_cast<E*>(smem);                               // [NT][KP] layer inputs
-    int* iv = reinterpret_cast<int*>(smem + NT * KP * sizeof(E));   // [NT] interval of each item
+    constexpr bool kF32 = sizeof(E) == 4;
+    E* xa = reinterpret_cast<E*>(smem);            // [NT][KP] layer inputs (matrix-core network)
+    float* hb = reinterpret_cast<float*>(smem);    // [NT][HP] hidden activations (FP32 network)
+    int* iv = reinterpret_cast<int*>(smem + row_tile_bytes<E>());    // [NT] interval of each item
     int* nbv = iv + NT;                                               // [NT] neighbour interval, or -1
     int* st = nbv + NT;                                               // [NT] staged boundary items
     __shared__ int dropped_any;
@@ -729,18 +871,34 @@ __device__ void track_event_mma(const TrackArgs& a, int e, char* smem)
     const double z_max = edge(a, a.n_intervals);
     const bool two = a.boundary_mm > 0.0;
 
-    // hidden layers of one item per thread, into xa
+    // hidden layers of one item per thread, into hb (FP32) or xa; a wave
+    // without a single kept item skips the network (its rows are never
+    // accumulated, and it adds nothing to a calibration maximum)
     auto network_hidden = [&](const float* g, bool valid) {
         const bool any = __ballot(valid) != 0;
-        float z[kFeat];
+        if constexpr (kF32) {
 #pragma unroll
-        for (int k = 0; k < kFeat; ++k) z[k] = valid ? g[k] : 0.f;
-        if (a.mlp_calib)
+            for (int k = 0; k < kFeat; ++k) hb[tid * HP + k] = valid ? g[k] : 0.f;
+            if (a.mlp_calib)
 #pragma unroll
-            for (int k = 0; k < kFeat; ++k) wave_amax(a.mlp_calib + calib_off(0) + k, z[k]);
-        store_inputs<E>(a, xa, tid, z);
-        __builtin_amdgcn_wave_barrier();
-        if (any) hidden_layers_mma<E>(a, xa, wave, lane);
+                for (int k = 0; k < kFeat; ++k) wave_amax(a.mlp_calib + calib_off(0) + k, valid ? g[k] : 0.f);
+            __builtin_amdgcn_wave_barrier();
+            if (any) hidden_layers_f32_mma(a, hb, iv, wave, lane);
+        } else {
+            float z[kFeat];
+#pragma unroll
+            for (int k = 0; k < kFeat; ++k) z[k] = valid ? g[k] : 0.f;
+            if (a.mlp_calib)
+#pragma unroll
+                for (int k = 0; k < kFeat; ++k) wave_amax(a.mlp_calib + calib_off(0) + k, z[k]);
+            store_inputs<E>(a, xa, tid, z);
+            __builtin_amdgcn_wave_barrier();
+            if (any) hidden_layers_mma<E>(a, xa, iv, wave, lane);
+        }
+    };
+    auto outputs = [&](int n) {
+        if constexpr (kF32) outputs_to_hist_f32(a, hb, iv, n, wave, lane, h);
+        else outputs_to_hist<E>(a, xa, iv, n, wave, lane, h);
     };
 
     if (status == 0) {
@@ -751,12 +909,12 @@ __device__ void track_event_mma(const TrackArgs& a, int e, char* smem)
 #pragma unroll
             for (int k = 0; k < kFeat; ++k) g[k] = 0.f;
             if (t < end) bin_track(a, t, z_max, two, itv, nb, g, &dropped_any);
+            iv[tid] = itv;   // read by the hidden layers' calibration
             network_hidden(g, itv >= 0);
-            iv[tid] = itv;
             nbv[tid] = nb;
             __syncthreads();
             const int n_chunk = (int)((end - base) < NT ? (end - base) : NT);
-            outputs_to_hist<E>(a, xa, iv, n_chunk, wave, lane, h);
+            outputs(n_chunk);
             if (two) {
                 // the chunk's boundary items, in item order, once more in the
                 // neighbour's frame (the barrier below also ends every wave's
@@ -787,10 +945,10 @@ __device__ void track_event_mma(const TrackArgs& a, int e, char* smem)
                         features(a, fs, (double)fs[0], inb, gs);
                     }
                     __syncthreads();    // every read of nbv / st above is done
-                    network_hidden(gs, tid < n_st);
                     iv[tid] = inb;
+                    network_hidden(gs, tid < n_st);
                     __syncthreads();
-                    outputs_to_hist<E>(a, xa, iv, n_st, wave, lane, h);
+                    outputs(n_st);
                 }
             }
             __syncthreads();   // xa and iv are rewritten by the next chunk
@@ -911,21 +1069,21 @@ static size_t track_stage_lds_bytes(int n_out, int n_intervals)
            sizeof(int) * (2 * NT + 3 * SUB + 1);
 }
 
-// Whether the matrix-core engine's histogram fits the registers.
-static bool track_mma_ok(int dtype, int n_intervals) { return dtype != PVF_FP32 && n_intervals <= kRegIntervals; }
+// Whether the event's histogram fits the registers of the matrix-core form.
+static bool track_mma_ok(int n_intervals, int n_out) { return n_intervals <= kRegIntervals && n_out <= kMlpOutN; }
 
 template <class E>
 static size_t track_mma_lds_bytes()
 {
-    return (size_t)NT * Net<E>::KP * sizeof(E) + 3 * NT * sizeof(int);
+    return row_tile_bytes<E>() + 3 * NT * sizeof(int);
 }
 
 template <class E>
 hipError_t launch_track_typed(const TrackArgs& a, int n_events, int persistent_blocks, hipStream_t s)
 {
     if (a.n_out < 1 || a.n_out > NT) return hipErrorInvalidValue;   // one thread per output column
-    if constexpr (sizeof(E) != 4) {
-        if (track_mma_ok(a.mlp_dtype, a.n_intervals)) {
+    {
+        if (track_mma_ok(a.n_intervals, a.n_out)) {
             // the queue (and its ordering pass) only when the events do not all
             // fit on the device at once
             const int queued = persistent_blocks > 0 && n_events > persistent_blocks && a.order && a.queue_counter;
@@ -974,12 +1132,16 @@ hipError_t launch_track(const TrackArgs& a, int n_events, int persistent_blocks,
     }
 }
 
-int track_queue_blocks(int dtype, int n_intervals, int cu_count)
+int track_queue_blocks(int dtype, int n_intervals, int n_out, int cu_count)
 {
-    if (!track_mma_ok(dtype, n_intervals)) return 2 * cu_count;   // two 64 KB-LDS blocks per CU
+    if (!track_mma_ok(n_intervals, n_out)) return 2 * cu_count;   // two 64 KB-LDS blocks per CU
     int per_cu = 0;
     hipError_t err = hipErrorInvalidValue;
     switch (dtype) {
+    case PVF_FP32:
+        err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, track_stage_mma<float>, NT,
+                                                           track_mma_lds_bytes<float>());
+        break;
     case PVF_BF16:
         err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, track_stage_mma<__bf16>, NT,
                                                            track_mma_lds_bytes<__bf16>());
@@ -997,10 +1159,10 @@ int track_queue_blocks(int dtype, int n_intervals, int cu_count)
     return (err == hipSuccess && per_cu > 0 ? per_cu : 1) * cu_count;
 }
 
-std::string track_kernel_name(int dtype, bool persistent, int n_intervals)
+std::string track_kernel_name(int dtype, bool persistent, int n_intervals, int n_out)
 {
     static const char* const kType[] = {"float", "__bf16", "_Float16", "unsigned char"};
-    if (track_mma_ok(dtype, n_intervals)) return std::string("track_stage_mma<") + kType[dtype] + ">";
+    if (track_mma_ok(n_intervals, n_out)) return std::string("track_stage_mma<") + kType[dtype] + ">";
     return std::string(persistent ? "track_stage_queue<" : "track_stage<") + kType[dtype] + ">";
 }
 
