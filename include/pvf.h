@@ -233,11 +233,11 @@ const char *pvf_status_string(pvf_status s);
 
 /* Track-stage schedule.  persistent = 1 (default): a counting-sort kernel
  * orders the batch's events by descending track count and a fixed grid of
- * blocks (as many as fit on the device at once: two per compute unit for the
- * FP32 network, four for the BF16, FP16 and FP8 networks) takes them from a
+ * blocks (as many as fit on the device at once: four per compute unit for
+ * histograms of up to 48 intervals, two for longer ones) takes them from a
  * device work queue, so heavy-tailed batches do not end on their largest
- * events; the BF16, FP16 and FP8 networks skip the queue and run one block
- * per event when the batch fits on the device at once.  persistent = 0: one
+ * events; with up to 48 intervals the queue is skipped, and one block runs
+ * per event, when the batch fits on the device at once.  persistent = 0: one
  * block per event.  Results are identical either way. */
 pvf_status pvf_set_track_schedule(pvf_engine *eng, int persistent);
 

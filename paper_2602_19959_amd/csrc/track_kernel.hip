@@ -11,19 +11,27 @@
 // accumulated, its boundary tracks are compacted into a staging list (track
 // order) and go through the network and the accumulation once more.
 //
-// Per chunk of 256 tracks (one per thread, coalesced SoA loads):
-//   A  bin the track (exact comparison with the interval edges in double),
-//      build its features and run the hidden layers in registers; the
-//      weights are wave-uniform, so they come through the scalar cache;
-//   B  per sub-chunk of 64 tracks, wave q computes outputs j = q, q+4, ...
-//      of all 64 tracks (softplus, positive), into LDS;
-//   C  the sub-chunk's tracks are grouped by interval (wave ballots, track
-//      order kept inside a group); each (group, output column) pair is summed
-//      in track order in a register by one thread and added to its LDS bin.
-// Every bin is therefore a fixed sequence of sums in ascending track order
-// (sub-chunk by sub-chunk): the histogram is deterministic, with no atomics,
-// and depends only on the event's own tracks.  The block then writes the
-// scaled histogram, once, straight into the UNet's input rows.
+// Two forms, both deterministic, atomic-free and dependent only on the
+// event's own tracks; the block writes the scaled histogram once, straight
+// into the UNet's input rows.
+//
+// track_stage_mma (every engine, histograms of at most 48 intervals and 112
+// bins per interval): per chunk of 256 tracks (one per thread, coalesced SoA
+// loads) each thread bins its track (exact comparison with the interval
+// edges in double) and builds its features; each wave runs its 64 tracks
+// through the hidden layers on the matrix cores (FP32, or BF16/FP16/FP8 with
+// FP32 accumulation); each wave then computes two of the seven 16-column
+// tiles of the output layer for every track of the chunk and adds them to
+// the histogram, which it holds in registers, as a one-hot GEMM on the
+// matrix cores (the output fragment is the GEMM's B operand as it stands).
+//
+// track_stage / track_stage_queue (longer histograms): the hidden layers in
+// registers (FP32 on the vector ALUs, weights through the scalar cache), or
+// on the matrix cores; per sub-chunk of 64 tracks the outputs go to LDS, the
+// sub-chunk's tracks are grouped by interval (wave ballots, track order kept
+// inside a group), and each (group, output column) pair is summed in track
+// order in a register by one thread and added to its LDS bin, so every bin
+// is a fixed sequence of sums in ascending track order.
 #include <cfloat>
 #include <cmath>
 
@@ -586,8 +594,8 @@ __global__ __launch_bounds__(NT) void track_stage_queue(TrackArgs a, int n_event
 
 // ---------------------------------------------------------------- histogram on the matrix cores
 //
-// The matrix-core engines keep an event's histogram in registers when it has
-// at most kRegIntervals intervals, and accumulate it on the matrix cores: per
+// Every engine keeps an event's histogram in registers when it has at most
+// kRegIntervals intervals, and accumulates it on the matrix cores: per
 // sub-chunk of 64 items, H[i][j] += sum_t S[i][t] Y[t][j], with S the one-hot
 // item-to-interval matrix (a dropped item has a zero column) and Y the items'
 // softplus outputs.  Each wave owns two of the seven output column tiles (16
@@ -595,14 +603,15 @@ __global__ __launch_bounds__(NT) void track_stage_queue(TrackArgs a, int n_event
 // of the chunk's sub-chunks itself; the output layer's MFMA fragment already
 // is the B operand of the accumulation: in K step s, element u of lane group
 // lg is item 16 (2 s + u / 4) + 4 lg + u % 4, the row that lane holds.  Y
-// enters as two BF16 terms, y = t0 + t1 + r with t0 = bf16(y) and
-// t1 = bf16(y - t0), so |r| <= 2^-16 |y| (below the 16-bit network's own
-// rounding), the products with the one-hot operand are exact, and the sums
-// are FP32 in the matrix core's fixed order: deterministic, no atomics,
-// depending only on the event's own items.  Outputs are capped below the
-// BF16 maximum, so a non-finite output cannot reach other intervals through
-// 0 x inf.  The event's histogram leaves the registers once, scaled, into the
-// UNet's input rows.
+// enters as two BF16 terms in the 16-bit and 8-bit engines, y = t0 + t1 + r
+// with t0 = bf16(y) and t1 = bf16(y - t0), so |r| <= 2^-16 |y| (below the
+// network's own rounding), and as itself in the FP32 engine (FP32 MFMA); the
+// products with the one-hot operand are exact, and the sums are FP32 in the
+// matrix core's fixed order: deterministic, no atomics, depending only on
+// the event's own items.  Outputs are capped at the largest finite value of
+// the operand type, so a non-finite output cannot reach other intervals
+// through 0 x inf.  The event's histogram leaves the registers once, scaled,
+// into the UNet's input rows.
 constexpr int kRegMT = 3;                   // interval tiles of 16
 constexpr int kRegIntervals = 16 * kRegMT;
 constexpr float kBf16Max = 0x1.fcp127f;     // largest finite BF16
