@@ -93,6 +93,78 @@ def test_calibration_table_matches_oracle_taps():
         assert err <= 1e-4, n
 
 
+@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+def test_calibration_network_layers_count_kept_tracks(dtype):
+    """The track network's entries of the calibration table: per layer input
+    and channel, the largest |value| over the kept tracks only.  Two events
+    of one kept track (and one out of the window) leave 255 padding rows in
+    their 256-track chunk; with every network bias at +1 the padding rows'
+    bias-only activations exceed the kept track's in several channels, and
+    they must not count.  FP32 against an FP64 evaluation of the layers at
+    1e-5 per channel; the BF16 network (16-bit layer inputs, six layers deep)
+    within 3e-2 of each layer's largest entry, and below 1.5 times the kept
+    maximum wherever the padding rows' value is over twice it."""
+    import dataclasses
+    import paper_2602_19959_amd as pv
+    from synth import weights_to_blob
+    from synth.events import pack_events
+    torch_cuda()
+    w0 = weights()
+    t = dict(w0.tensors)
+    for l in range(w0.shape.n_hidden):
+        t[f"mlp{l}.b"] = np.full_like(t[f"mlp{l}.b"], 1.0)
+    w = dataclasses.replace(w0, tensors=t)
+    src = make_events(2, seed=11)
+    lists = []
+    for e in range(2):
+        tr = src.tracks_of(e)[:, :2].copy()
+        tr[0, 1] = 400.0                      # outside the histogram window: dropped
+        lists.append(tr)
+    batch = pack_events(lists)
+    spec = pv.default_spec(max_events=2, max_tracks_total=16, compute_dtype=dtype)
+    eng = pv.Engine(weights_to_blob(w), spec)
+    feat, off = pv.upload_events(batch)
+    amax = eng.calibrate(feat, off)
+    eng.close()
+    s = w.shape
+    n_mlp = s.n_feat + s.n_hidden * s.hidden
+    got = amax[len(amax) - n_mlp:]
+    g = []
+    for tr in lists:
+        for k in range(tr.shape[1]):
+            i = oracle.bin_index(tr[0, k])
+            if i >= 0:
+                g.append(np.asarray(oracle.features(tr[:, k], i, w), np.float64))
+    h = np.stack(g)
+    assert len(h) == 2
+    z = np.zeros((1, s.n_feat))                # a padding row: zero inputs
+    kept, pad = [np.abs(h).max(axis=0)], [np.zeros(s.n_feat)]
+    for l in range(s.n_hidden):
+        W = np.asarray(w[f"mlp{l}.w"], np.float64)
+        b = np.asarray(w[f"mlp{l}.b"], np.float64)
+        y, yz = h @ W.T + b, z @ W.T + b
+        h, z = np.where(y >= 0, y, w.leaky * y), np.where(yz >= 0, yz, w.leaky * yz)
+        kept.append(np.abs(h).max(axis=0))
+        pad.append(np.abs(z[0]))
+    n_above = sum(int(np.sum(p > 2 * k)) for k, p in zip(kept, pad))
+    assert n_above >= 3                        # the check below has channels to bite on
+    if dtype == "fp32":
+        want = np.concatenate(kept)
+        err = float(np.max(np.abs(got - want) / np.maximum(want, 1e-30)))
+        say(dtype, "network calibration max rel err %.2e" % err)
+        assert err <= 1e-5
+        return
+    o = 0
+    for l, (k, p) in enumerate(zip(kept, pad)):
+        gl = got[o:o + len(k)]
+        o += len(k)
+        err = float(np.max(np.abs(gl - k)) / np.max(k))
+        say(dtype, "layer input", l, "normwise err %.2e" % err)
+        assert err <= 3e-2, l
+        above = p > 2 * k
+        assert np.all(gl[above] < 1.5 * k[above]), l
+
+
 def test_probability_within_stated_bound(fp8, ref16):
     eng, out = fp8
     dp = max(float(np.max(np.abs(out["prob"][e] - ref16[e]["p"]))) for e in range(16))
