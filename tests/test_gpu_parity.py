@@ -310,6 +310,39 @@ def test_ragged_shapes(dtype):
     eng.close()
 
 
+@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+@pytest.mark.parametrize("n_bins,bpi", [(800, 100), (400, 10)])
+def test_short_histograms(dtype, n_bins, bpi):
+    """Histograms inside one interval tile of the register histogram: 8
+    intervals of 100 bins, and 40 intervals of 10 bins (one partly used
+    column tile: three of the four waves hold no output columns), windows
+    centred on the vertices.  p and peaks of four events against the oracle
+    (FP32 at the FP32 bar, BF16 within its stated bound)."""
+    from synth import NetShape
+    torch_cuda()
+    shape = NetShape(n_out=bpi)
+    z_min = -0.05 * n_bins
+    eng = make_engine(4, shape=shape, n_bins=n_bins, bins_per_interval=bpi, z_min_mm=z_min,
+                      compute_dtype=dtype, max_peaks_per_event=n_bins // 2)
+    assert eng.launch_kernels()[0].startswith("track_stage_mma<")
+    batch = make_events(4, seed=9)
+    say("short histogram", n_bins, bpi, dtype)
+    out = run(eng, batch)
+    geo = geometry(eng)
+    assert geo.n_bins == n_bins and geo.bins_per_interval == bpi and geo.z_min == z_min
+    refs = oracle.run_batch(batch, weights(0, shape), geo)
+    for e in range(4):
+        if dtype == "fp32":
+            assert parity.max_rel(out["prob"][e], refs[e]["p"]) <= parity.P_REL, e
+            bins, z, h, S = event_vertices(out, e)
+            parity.compare_peaks(bins, z, h, S, refs[e], geo)
+        else:
+            assert float(np.max(np.abs(out["prob"][e] - refs[e]["p"]))) <= parity.P_ABS[dtype], e
+        assert (out["status"][e] & ~pv_dropped()) == 0
+    parity.exact_peaks_all(out, geo)
+    eng.close()
+
+
 def pv_dropped():
     import paper_2602_19959_amd as pv
     return pv.EV_TRACKS_DROPPED
