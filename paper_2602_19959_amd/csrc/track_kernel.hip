@@ -732,53 +732,51 @@ __device__ void hidden_layers_f32_mma(const TrackArgs& a, float* hb, const int* 
         const int K = l == 0 ? kFeat : kHidden;
         const float* W = l == 0 ? a.mlp : Wh + (size_t)(l - 1) * (kHidden * kHidden + kHidden);   // [20][K]
         const float* b = W + kHidden * K;
-        float w[2][KS];
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                const int c = 16 * j + li, k = 4 * ks + lg;
-                w[j][ks] = (c < kHidden && k < K) ? W[c * K + k] : 0.f;
-            }
-        f32x4 acc[4][2];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            if (4 * ks >= K) break;
-            const int k = 4 * ks + lg;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float x = k < K ? rows[(16 * i + li) * HP + k] : 0.f;
-#pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, w[j][ks], acc[i][j], 0, 0, 0);
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
+        float w[2][KS], bn[2], m[2] = {0.f, 0.f};
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int c = 16 * j + li;
-            const bool used = c < kHidden;
-            const float bn = used ? b[c] : 0.f;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int ks = 0; ks < KS; ++ks) {
+                const int k = 4 * ks + lg;
+                w[j][ks] = (c < kHidden && k < K) ? W[c * K + k] : 0.f;
+            }
+            bn[j] = c < kHidden ? b[c] : 0.f;
+        }
+        // one row tile at a time: its outputs replace its inputs (the tile's
+        // reads come first in the wave's program order), so only that tile's
+        // accumulators are live
+#pragma unroll 1
+        for (int i = 0; i < 4; ++i) {
+            f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    if (used) rows[(16 * i + 4 * lg + v) * HP + c] = lrelu(acc[i][j][v] + bn, a.slope);
-            if (a.mlp_calib) {
-                // the largest |output| over the wave's kept items
-                float m = 0.f;
+            for (int ks = 0; ks < KS; ++ks) {
+                if (4 * ks >= K) break;
+                const int k = 4 * ks + lg;
+                const float x = k < K ? rows[(16 * i + li) * HP + k] : 0.f;
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 2; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, w[j][ks], acc[j], 0, 0, 0);
+            }
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        if (kept[16 * i + v] >= 0) m = fmaxf(m, fabsf(lrelu(acc[i][j][v] + bn, a.slope)));
-                m = fmaxf(m, __shfl_xor(m, 16));
-                m = fmaxf(m, __shfl_xor(m, 32));
-                if (lg == 0 && used)
-                    atomicMax(reinterpret_cast<unsigned int*>(a.mlp_calib + calib_off(l + 1) + c), __float_as_uint(m));
+            for (int j = 0; j < 2; ++j) {
+                const int c = 16 * j + li;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float y = lrelu(acc[j][v] + bn[j], a.slope);
+                    if (c < kHidden) rows[(16 * i + 4 * lg + v) * HP + c] = y;
+                    if (a.mlp_calib && kept[16 * i + v] >= 0) m[j] = fmaxf(m[j], fabsf(y));
+                }
+            }
+        }
+        if (a.mlp_calib) {
+            // the largest |output| over the wave's kept items
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                float mm = fmaxf(m[j], __shfl_xor(m[j], 16));
+                mm = fmaxf(mm, __shfl_xor(mm, 32));
+                const int c = 16 * j + li;
+                if (lg == 0 && c < kHidden)
+                    atomicMax(reinterpret_cast<unsigned int*>(a.mlp_calib + calib_off(l + 1) + c), __float_as_uint(mm));
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -800,21 +798,16 @@ __device__ void outputs_to_hist_f32(const TrackArgs& a, const float* hb, const i
                       (size_t)(a.n_hidden - 1) * (kHidden * kHidden + kHidden);   // [n_out][kHidden]
     const float* bo = Wo + (size_t)a.n_out * kHidden;
     constexpr int KS = kHidden / 4;
-    bool on[2];
-    float w[2][KS], bn[2];
 #pragma unroll
     for (int jl = 0; jl < 2; ++jl) {
         const int jt = hist_tile(wave, blockIdx.x, jl);
-        on[jl] = jt < kMlpOutN / 16 && 16 * jt < a.n_out;
+        if (jt >= kMlpOutN / 16 || 16 * jt >= a.n_out) continue;
         const int c = 16 * jt + li;
-        const bool used = on[jl] && c < a.n_out;
+        const bool used = c < a.n_out;
+        float w[KS];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) w[jl][ks] = used ? Wo[(size_t)c * kHidden + 4 * ks + lg] : 0.f;
-        bn[jl] = used ? bo[c] : 0.f;
-    }
-#pragma unroll
-    for (int jl = 0; jl < 2; ++jl) {
-        if (!on[jl]) continue;
+        for (int ks = 0; ks < KS; ++ks) w[ks] = used ? Wo[(size_t)c * kHidden + 4 * ks + lg] : 0.f;
+        const float bn = used ? bo[c] : 0.f;
 #pragma unroll 1
         for (int sub = 0; sub < n; sub += SUB) {
 #pragma unroll
@@ -824,10 +817,10 @@ __device__ void outputs_to_hist_f32(const TrackArgs& a, const float* hb, const i
                 const float* x = hb + (size_t)(sub + 16 * i + li) * HP + lg;
                 f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x[4 * ks], w[jl][ks], acc, 0, 0, 0);
+                for (int ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x[4 * ks], w[ks], acc, 0, 0, 0);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const float y = fminf(softplus(acc[v] + bn[jl]), FLT_MAX);
+                    const float y = fminf(softplus(acc[v] + bn), FLT_MAX);
 #pragma unroll
                     for (int mt = 0; mt < kRegMT; ++mt) {
                         if (16 * mt >= a.n_intervals) break;
