@@ -42,7 +42,11 @@ namespace {
 
 constexpr int NT = 256;   // tracks per chunk, one per thread
 constexpr int SUB = 64;   // tracks per output/scatter sub-chunk (one per lane)
-constexpr int HP = kHidden + 1;   // LDS pitch of the hidden activations
+constexpr int HP = kHidden + 1;   // LDS pitch of the hidden activations (one row per thread)
+// LDS pitch of the FP32 layer rows of the matrix-core form: with 64 banks,
+// 20 makes both of its access patterns conflict-free (fragment reads: 16
+// rows x 4 consecutive k; writes: 4 row groups x 16 consecutive channels)
+constexpr int HPM = kHidden;
 
 __device__ __forceinline__ float lrelu(float x, float s) { return x >= 0.f ? x : s * x; }
 
@@ -724,7 +728,7 @@ __device__ void outputs_to_hist(const TrackArgs& a, const E* xa, const int* iv, 
 __device__ void hidden_layers_f32_mma(const TrackArgs& a, float* hb, const int* iv, int wave, int lane)
 {
     const int li = lane & 15, lg = lane >> 4;
-    float* rows = hb + (size_t)wave * 64 * HP;
+    float* rows = hb + (size_t)wave * 64 * HPM;
     const float* Wh = a.mlp + kHidden * kFeat + kHidden;   // hidden layers 2.. : [W 20x20, b 20]
     constexpr int KS = kHidden / 4;
     const int* kept = iv + wave * 64 + 4 * lg;   // kept[16 i + v] >= 0: row 16 i + 4 lg + v is a kept item
@@ -753,7 +757,7 @@ __device__ void hidden_layers_f32_mma(const TrackArgs& a, float* hb, const int* 
             for (int ks = 0; ks < KS; ++ks) {
                 if (4 * ks >= K) break;
                 const int k = 4 * ks + lg;
-                const float x = k < K ? rows[(16 * i + li) * HP + k] : 0.f;
+                const float x = k < K ? rows[(16 * i + li) * HPM + k] : 0.f;
 #pragma unroll
                 for (int j = 0; j < 2; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, w[j][ks], acc[j], 0, 0, 0);
             }
@@ -763,7 +767,7 @@ __device__ void hidden_layers_f32_mma(const TrackArgs& a, float* hb, const int* 
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const float y = lrelu(acc[j][v] + bn[j], a.slope);
-                    if (c < kHidden) rows[(16 * i + 4 * lg + v) * HP + c] = y;
+                    if (c < kHidden) rows[(16 * i + 4 * lg + v) * HPM + c] = y;
                     if (a.mlp_calib && kept[16 * i + v] >= 0) m[j] = fmaxf(m[j], fabsf(y));
                 }
             }
@@ -814,7 +818,7 @@ __device__ void outputs_to_hist_f32(const TrackArgs& a, const float* hb, const i
             for (int i = 0; i < 4; ++i) {
                 const int4 q = *reinterpret_cast<const int4*>(iv + sub + 16 * i + 4 * lg);
                 const int itv[4] = {q.x, q.y, q.z, q.w};
-                const float* x = hb + (size_t)(sub + 16 * i + li) * HP + lg;
+                const float* x = hb + (size_t)(sub + 16 * i + li) * HPM + lg;
                 f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x[4 * ks], w[ks], acc, 0, 0, 0);
@@ -833,12 +837,12 @@ __device__ void outputs_to_hist_f32(const TrackArgs& a, const float* hb, const i
     }
 }
 
-// Bytes of the layer-input rows: FP32 hidden activations [NT][HP], or the
+// Bytes of the layer-input rows: FP32 hidden activations [NT][HPM], or the
 // matrix-core network's inputs [NT][KP] in E.
 template <class E>
 constexpr size_t row_tile_bytes()
 {
-    if constexpr (sizeof(E) == 4) return (size_t)NT * HP * sizeof(float);
+    if constexpr (sizeof(E) == 4) return (size_t)NT * HPM * sizeof(float);
     else return (size_t)NT * Net<E>::KP * sizeof(E);
 }
 
@@ -847,7 +851,7 @@ __device__ void track_event_mma(const TrackArgs& a, int e, char* smem)
 {
     constexpr bool kF32 = sizeof(E) == 4;
     E* xa = reinterpret_cast<E*>(smem);            // [NT][KP] layer inputs (matrix-core network)
-    float* hb = reinterpret_cast<float*>(smem);    // [NT][HP] hidden activations (FP32 network)
+    float* hb = reinterpret_cast<float*>(smem);    // [NT][HPM] layer rows (FP32 network)
     int* iv = reinterpret_cast<int*>(smem + row_tile_bytes<E>());    // [NT] interval of each item
     int* nbv = iv + NT;                                               // [NT] neighbour interval, or -1
     int* st = nbv + NT;                                               // [NT] staged boundary items
@@ -880,7 +884,7 @@ __device__ void track_event_mma(const TrackArgs& a, int e, char* smem)
         const bool any = __ballot(valid) != 0;
         if constexpr (kF32) {
 #pragma unroll
-            for (int k = 0; k < kFeat; ++k) hb[tid * HP + k] = valid ? g[k] : 0.f;
+            for (int k = 0; k < kFeat; ++k) hb[tid * HPM + k] = valid ? g[k] : 0.f;
             if (a.mlp_calib)
 #pragma unroll
                 for (int k = 0; k < kFeat; ++k) wave_amax(a.mlp_calib + calib_off(0) + k, valid ? g[k] : 0.f);
