@@ -234,14 +234,22 @@ __device__ __forceinline__ void fp8_tile(const ConvArgs& a)
             rmap.at((int)(g - m0), e, loc);
             uint32_t w4[4] = {0u, 0u, 0u, 0u};
             if (loc >= kGuard && loc < a.r_in - kGuard) {
+                // four codes per register, two per conversion (each code as
+                // e4m3_sat gives it in the standalone kernel)
 #pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    const int c = 16 * q + v;
-                    float w5[kTaps];
+                for (int p = 0; p < 4; ++p) {
+                    float y[4];
 #pragma unroll
-                    for (int k = 0; k < kTaps; ++k) w5[k] = fp[c * kTaps + k];
-                    const float act = first_conv_at(w5, fp[5 * KB + c], xw + u, a.slope);
-                    w4[v / 4] |= (uint32_t)e4m3_sat(act * fp[6 * KB + c]) << (8 * (v % 4));
+                    for (int k4 = 0; k4 < 4; ++k4) {
+                        const int c = 16 * q + 4 * p + k4;
+                        float w5[kTaps];
+#pragma unroll
+                        for (int k = 0; k < kTaps; ++k) w5[k] = fp[c * kTaps + k];
+                        const float act = first_conv_at(w5, fp[5 * KB + c], xw + u, a.slope);
+                        y[k4] = fminf(fmaxf(act * fp[6 * KB + c], -448.f), 448.f);
+                    }
+                    uint32_t w = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(y[0], y[1], 0, false);
+                    w4[p] = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(y[2], y[3], (int)w, true);
                 }
             }
             *reinterpret_cast<u32x4*>(smem + r * KB + 16 * (q ^ swz<KB>(r))) = u32x4{w4[0], w4[1], w4[2], w4[3]};
